@@ -1,0 +1,145 @@
+/*
+ * mochy.h - C ABI of the MI355X hypergraph-motif counter.
+ *
+ * Method: MoCHy (Lee, Yoon, Ko, Kim, Shin, "Hypergraph motifs and their
+ * extensions beyond binary", arXiv 2310.15668).  A hypergraph goes in; counts
+ * of the 26 h-motifs (section 2.2) and 431 3h-motifs (section 5.1, theta = 1),
+ * unbiased sampled estimates (MoCHy-A+, Algorithm 5), significance (Eq. 1)
+ * and the characteristic profile (Eq. 2) come out.
+ *
+ * Conventions for every call:
+ *  - Return value is a mochy_status; outputs are written only on MOCHY_OK.
+ *  - Array arguments marked "host" are ordinary host memory owned by the
+ *    caller and never retained past the call.
+ *  - All device work is enqueued on the context's HIP stream; every call is
+ *    synchronous on return (results are on the host, device work finished).
+ *  - A context is not thread-safe: one host thread at a time per context.
+ *  - Motif ids: h-motifs 1..26, 3h-motifs 1..431; count arrays are indexed
+ *    id-1.  mochy_motif_pattern() gives the region pattern behind every id.
+ *    Ids 17..22 are the open h-motifs, the others closed.
+ *  - Hyperedge ids are positions in the input CSR.
+ */
+#ifndef MOCHY_H
+#define MOCHY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MOCHY_OK = 0,
+  MOCHY_EINVAL = -1,      /* malformed input: a node list not strictly ascending,
+                             a node id outside [0, num_nodes), an empty hyperedge,
+                             decreasing edge_ptr, or a bad argument */
+  MOCHY_EDUP = -2,        /* two hyperedges hold the same node set (hyperedges form a
+                             set, section 2.1); pass MOCHY_DEDUP to drop repeats */
+  MOCHY_ERANGE = -3,      /* a hyperedge holds more than MOCHY_MAX_EDGE nodes, or a
+                             size exceeds what the library can address */
+  MOCHY_ENOMEM = -4,      /* device or host allocation failed */
+  MOCHY_EDEVICE = -5,     /* a HIP runtime call failed */
+  MOCHY_EUNSUPPORTED = -6 /* valid request this build does not handle (message says why) */
+} mochy_status;
+
+#define MOCHY_MAX_EDGE 32   /* nodes per hyperedge: the per-centre region masks are 32-bit */
+#define MOCHY_NUM_H 26
+#define MOCHY_NUM_3H 431
+
+typedef struct mochy_ctx mochy_ctx;      /* device, stream, pattern tables, error text */
+typedef struct mochy_graph mochy_graph;  /* device-resident incidence, its transpose and
+                                            the line graph; owned by the library */
+
+/* CSR incidence of a hypergraph: hyperedge e holds the node ids
+ * edge_nodes[edge_ptr[e] .. edge_ptr[e+1]-1], strictly ascending.
+ * edge_ptr has num_edges+1 int64 entries starting at 0.
+ * on_device = 0: host pointers; 1: device pointers (memory already in HBM of
+ * the context's device; read during mochy_project only, never retained). */
+typedef struct {
+  int64_t num_nodes;
+  int64_t num_edges;
+  const int64_t* edge_ptr;
+  const int32_t* edge_nodes;
+  int32_t on_device;
+} mochy_csr;
+
+/* mochy_project flags */
+#define MOCHY_DEDUP 1u  /* host input only: drop repeated hyperedges, keeping the first;
+                           later ids shift down */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to use,
+ * or NULL to create a private one (default priority).  Builds the pattern
+ * tables on the device. */
+mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx** out);
+void mochy_ctx_destroy(mochy_ctx* ctx);
+/* Text of the last error on this context ("" if none); owned by the context. */
+const char* mochy_last_error(const mochy_ctx* ctx);
+
+/* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
+ * builds on the device the transposed incidence E_v (node -> hyperedges),
+ * the full line graph rows N_{e_i} (ascending hyperedge ids) with
+ * omega(e_i, e_j) = |e_i ∩ e_j| folded into per-neighbour region masks, and
+ * returns it.  *num_hyperwedges = |wedges| = number of adjacent unordered
+ * pairs.  Errors: MOCHY_EINVAL, MOCHY_EDUP, MOCHY_ERANGE, MOCHY_ENOMEM,
+ * MOCHY_EDEVICE.  Free the result with mochy_graph_free. */
+mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* g, uint32_t flags,
+                           mochy_graph** out, int64_t* num_hyperwedges);
+void mochy_graph_free(mochy_graph* g);
+
+/* Exact counts (MoCHy-E, Algorithm 2): every connected triple of distinct
+ * hyperedges counted once in its h-motif and its 3h-motif.  counts26 (host,
+ * 26 int64) and counts431 (host, 431 int64) may each be NULL if not wanted. */
+mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g,
+                               int64_t* counts26, int64_t* counts431);
+
+/* The same, restricted to the instances Algorithm 2 attributes to centres
+ * e_i with center_begin <= i < center_end (an open instance belongs to its
+ * middle hyperedge, a closed one to its smallest index).  Summing disjoint
+ * ranges that cover [0, num_edges) gives mochy_count_exact. */
+mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_graph* g,
+                                     int64_t center_begin, int64_t center_end,
+                                     int64_t* counts26, int64_t* counts431);
+
+/* MoCHy-A+ (Algorithm 5): samples n = sample_begin .. sample_begin+r-1 each
+ * draw one hyperwedge uniformly with replacement, using Philox4x32-10 with
+ * counter (lo32 n, hi32 n, 0, 0), key (lo32 seed, hi32 seed),
+ * u = (x1 << 32) | x0 and hyperwedge index floor(u * |wedges| / 2^64) in the
+ * order of (i, j), i < j, lexicographic.  For the sampled {e_i, e_j}, each
+ * e_k in N_i ∪ N_j minus {e_i, e_j} adds one hit to its motif.  raw26/raw431
+ * (host int64) receive the hits; est26/est431 (host double) the unbiased
+ * estimates raw * |wedges| / (w * r), w = 2 for open and 3 for closed motifs
+ * (w of a 3h-motif is its h-motif's).  Any output pointer may be NULL.
+ * r must be > 0; a graph with no hyperwedge gives zeros. */
+mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r,
+                                 uint64_t seed, int64_t sample_begin,
+                                 int64_t* raw26, double* est26,
+                                 int64_t* raw431, double* est431);
+
+/* Significance and characteristic profile against randomized copies
+ * (section 3.1).  graphs[0] is the hypergraph, graphs[1..num_graphs-1] its
+ * randomized copies (host or device CSRs; the caller draws them).  All graphs
+ * are projected and counted exactly on the device.  Outputs (host): counts
+ * (num_graphs x 457 int64: per graph 26 h-motif then 431 3h-motif counts),
+ * sig26/cp26 (26 doubles) and sig431/cp431 (431 doubles), each may be NULL.
+ *   Delta_t = (M[t] - Mr[t]) / (M[t] + Mr[t] + eps),  Mr = mean over copies;
+ *   CP_t    = Delta_t / sqrt(sum_t Delta_t^2)    (0 for all t if every Delta is 0).
+ * num_graphs >= 2. */
+mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,
+                           double eps, int64_t* counts,
+                           double* sig26, double* cp26, double* sig431, double* cp431);
+
+/* Region pattern of a motif id: states[r] for regions R1..R7 of section 2.2
+ * (R1 = e_i - e_j - e_k, ..., R4 = e_i ∩ e_j - e_k, ..., R7 = all three), in
+ * the canonical labelling.  kind = 2: h-motif (0 empty / 1 non-empty);
+ * kind = 3: 3h-motif (0 empty, 1 one node, 2 more).  MOCHY_EINVAL for an id
+ * out of range.  Host only, needs no context. */
+mochy_status mochy_motif_pattern(int32_t id, uint32_t kind, uint8_t states[7]);
+
+/* Parent h-motif id of a 3h-motif id (1..431), or 0 if out of range. */
+int32_t mochy_parent_motif(int32_t id3);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOCHY_H */

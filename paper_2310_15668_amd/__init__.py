@@ -1,0 +1,11 @@
+"""MI355X-native hypergraph-motif counter (MoCHy, arXiv 2310.15668).
+
+The computation lives in ``libmochy.so`` (hand-written HIP for gfx950) behind
+the C ABI of ``include/mochy.h``; ``paper_2310_15668_amd._lib`` is its ctypes
+binding with the same names.  Importing this package loads nothing; the
+library is loaded on first use and raises if it has not been built.
+"""
+from ._lib import (  # noqa: F401
+    Context, Graph, MochyError, mochy_project, mochy_count_exact, mochy_count_exact_range,
+    mochy_count_sampled, mochy_profile, motif_pattern, parent_motif, NUM_H, NUM_3H, MOCHY_DEDUP,
+)

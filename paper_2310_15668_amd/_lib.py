@@ -1,0 +1,221 @@
+"""ctypes binding of libmochy.so: the C ABI of include/mochy.h, same names.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+library; if the library is not built this module raises, it never falls
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmochy.so")
+
+MOCHY_OK = 0
+STATUS = {0: "MOCHY_OK", -1: "MOCHY_EINVAL", -2: "MOCHY_EDUP", -3: "MOCHY_ERANGE",
+          -4: "MOCHY_ENOMEM", -5: "MOCHY_EDEVICE", -6: "MOCHY_EUNSUPPORTED"}
+MOCHY_DEDUP = 1
+NUM_H, NUM_3H = 26, 431
+MAX_EDGE = 32
+
+# every symbol include/mochy.h declares
+EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_project",
+            "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
+            "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif")
+
+
+class MochyError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_int64), ("num_edges", ctypes.c_int64),
+                ("edge_ptr", ctypes.c_void_p), ("edge_nodes", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmochy.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2310_15668_amd.build")
+    # One HIP runtime per process: torch ships its own libamdhip64 (soname
+    # libamdhip64.so.7) and asks for it by an unversioned name, so if it is
+    # loaded after us a second runtime comes up and cannot open the device.
+    # Loading torch first makes our libamdhip64.so.7 dependency resolve to the
+    # runtime torch already loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64
+    L.mochy_ctx_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.mochy_ctx_create.restype = ctypes.c_int
+    L.mochy_ctx_destroy.argtypes = [vp]
+    L.mochy_ctx_destroy.restype = None
+    L.mochy_last_error.argtypes = [vp]
+    L.mochy_last_error.restype = ctypes.c_char_p
+    L.mochy_project.argtypes = [vp, ctypes.POINTER(CSR), u32, ctypes.POINTER(vp), ctypes.POINTER(i64)]
+    L.mochy_project.restype = ctypes.c_int
+    L.mochy_graph_free.argtypes = [vp]
+    L.mochy_graph_free.restype = None
+    L.mochy_count_exact.argtypes = [vp, vp, vp, vp]
+    L.mochy_count_exact.restype = ctypes.c_int
+    L.mochy_count_exact_range.argtypes = [vp, vp, i64, i64, vp, vp]
+    L.mochy_count_exact_range.restype = ctypes.c_int
+    L.mochy_count_sampled.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
+    L.mochy_count_sampled.restype = ctypes.c_int
+    L.mochy_profile.argtypes = [vp, i32, ctypes.POINTER(CSR), ctypes.c_double, vp, vp, vp, vp, vp]
+    L.mochy_profile.restype = ctypes.c_int
+    L.mochy_motif_pattern.argtypes = [i32, u32, ctypes.POINTER(ctypes.c_uint8)]
+    L.mochy_motif_pattern.restype = ctypes.c_int
+    L.mochy_parent_motif.argtypes = [i32]
+    L.mochy_parent_motif.restype = i32
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def motif_pattern(motif_id: int, kind: int):
+    out = (ctypes.c_uint8 * 7)()
+    st = lib().mochy_motif_pattern(int(motif_id), int(kind), out)
+    if st != MOCHY_OK:
+        raise MochyError(st, f"motif id {motif_id} kind {kind}")
+    return tuple(out)
+
+
+def parent_motif(id3: int) -> int:
+    return int(lib().mochy_parent_motif(int(id3)))
+
+
+class Context:
+    """mochy_ctx on one device; ``stream`` is a hipStream_t handle (int) or None."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        st = lib().mochy_ctx_create(int(device), ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != MOCHY_OK:
+            raise MochyError(st, "mochy_ctx_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().mochy_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def check(self, st, what):
+        if st != MOCHY_OK:
+            msg = lib().mochy_last_error(self.handle)
+            raise MochyError(st, f"{what}: {msg.decode() if msg else ''}")
+
+
+def make_csr(edge_ptr, edge_nodes, num_nodes, keep):
+    """A CSR struct from numpy arrays (host) or torch tensors (device)."""
+    if hasattr(edge_ptr, "data_ptr"):  # torch tensor
+        if str(edge_ptr.dtype) != "torch.int64" or str(edge_nodes.dtype) != "torch.int32":
+            raise TypeError("edge_ptr must be int64 and edge_nodes int32")
+        if not (edge_ptr.is_contiguous() and edge_nodes.is_contiguous()):
+            raise ValueError("CSR tensors must be contiguous")
+        on_dev = 1 if edge_ptr.is_cuda else 0
+        if on_dev != (1 if edge_nodes.is_cuda else 0):
+            raise ValueError("edge_ptr and edge_nodes must live on the same side")
+        keep.extend([edge_ptr, edge_nodes])
+        return CSR(int(num_nodes), int(edge_ptr.numel() - 1), edge_ptr.data_ptr(),
+                   edge_nodes.data_ptr() if edge_nodes.numel() else None, on_dev)
+    p = np.ascontiguousarray(edge_ptr, dtype=np.int64)
+    n = np.ascontiguousarray(edge_nodes, dtype=np.int32)
+    keep.extend([p, n])
+    return CSR(int(num_nodes), int(p.size - 1), p.ctypes.data, n.ctypes.data if n.size else None, 0)
+
+
+class Graph:
+    """mochy_graph: the device-resident projection of one hypergraph."""
+
+    def __init__(self, ctx: Context, edge_ptr, edge_nodes, num_nodes, flags: int = 0):
+        keep = []
+        c = make_csr(edge_ptr, edge_nodes, num_nodes, keep)
+        h = ctypes.c_void_p()
+        w = ctypes.c_int64()
+        ctx.check(lib().mochy_project(ctx.handle, ctypes.byref(c), int(flags), ctypes.byref(h), ctypes.byref(w)),
+                  "mochy_project")
+        self.ctx, self.handle, self.num_hyperwedges = ctx, h, int(w.value)
+        self.num_edges = int(c.num_edges)
+
+    def close(self):
+        if self.handle:
+            lib().mochy_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mochy_project(ctx, edge_ptr, edge_nodes, num_nodes, flags=0) -> Graph:
+    return Graph(ctx, edge_ptr, edge_nodes, num_nodes, flags)
+
+
+def mochy_count_exact(ctx: Context, g: Graph):
+    c26 = np.zeros(NUM_H, dtype=np.int64)
+    c431 = np.zeros(NUM_3H, dtype=np.int64)
+    ctx.check(lib().mochy_count_exact(ctx.handle, g.handle, _ptr(c26), _ptr(c431)), "mochy_count_exact")
+    return c26, c431
+
+
+def mochy_count_exact_range(ctx: Context, g: Graph, c0: int, c1: int):
+    c26 = np.zeros(NUM_H, dtype=np.int64)
+    c431 = np.zeros(NUM_3H, dtype=np.int64)
+    ctx.check(lib().mochy_count_exact_range(ctx.handle, g.handle, int(c0), int(c1), _ptr(c26), _ptr(c431)),
+              "mochy_count_exact_range")
+    return c26, c431
+
+
+def mochy_count_sampled(ctx: Context, g: Graph, r: int, seed: int, sample_begin: int = 0):
+    raw26 = np.zeros(NUM_H, dtype=np.int64)
+    est26 = np.zeros(NUM_H, dtype=np.float64)
+    raw431 = np.zeros(NUM_3H, dtype=np.int64)
+    est431 = np.zeros(NUM_3H, dtype=np.float64)
+    ctx.check(lib().mochy_count_sampled(ctx.handle, g.handle, int(r), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                        int(sample_begin), _ptr(raw26), _ptr(est26), _ptr(raw431),
+                                        _ptr(est431)), "mochy_count_sampled")
+    return raw26, est26, raw431, est431
+
+
+def mochy_profile(ctx: Context, graphs, eps: float = 1.0):
+    """graphs: list of (edge_ptr, edge_nodes, num_nodes); graphs[0] is the hypergraph."""
+    keep = []
+    arr = (CSR * len(graphs))(*[make_csr(p, n, v, keep) for (p, n, v) in graphs])
+    counts = np.zeros((len(graphs), NUM_H + NUM_3H), dtype=np.int64)
+    sig26, cp26 = np.zeros(NUM_H), np.zeros(NUM_H)
+    sig431, cp431 = np.zeros(NUM_3H), np.zeros(NUM_3H)
+    ctx.check(lib().mochy_profile(ctx.handle, len(graphs), arr, float(eps), _ptr(counts), _ptr(sig26),
+                                  _ptr(cp26), _ptr(sig431), _ptr(cp431)), "mochy_profile")
+    return counts, sig26, cp26, sig431, cp431

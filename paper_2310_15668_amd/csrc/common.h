@@ -1,0 +1,94 @@
+// Internal declarations of the MI355X MoCHy library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mochy.h"
+
+// Ternary region code used on the device: code = sum_r state(R_r) * 3^r with
+// R1 in the least significant digit, state(c) = min(c, 2) (theta = 1).
+constexpr int kNumCodes = 2187;
+constexpr int kHistSlots = 432;       // slot 0 = invalid pattern, 1..431 = 3h ids
+constexpr int kHeavyBits = 64;        // nodes with an exact outside-overlap bit
+constexpr int kWave = 64;
+
+// Host-side pattern tables (patterns.cpp).
+struct PatternTables {
+  uint16_t code_to_id3[kNumCodes];    // any ternary code -> 3h id (0 if invalid)
+  int16_t id3_to_id26[kHistSlots];    // 3h id -> h id (slot 0 -> 0)
+  uint8_t id26_state[27][7];          // canonical binary tuple of each h id
+  uint8_t id3_state[kHistSlots][7];   // canonical ternary tuple of each 3h id
+  uint8_t id26_open[27];
+};
+const PatternTables& pattern_tables();
+
+struct mochy_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cus = 0;
+  std::string err;
+  uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
+  int32_t* d_id3_to_id26 = nullptr;   // [kHistSlots]
+  int32_t* d_flags = nullptr;         // device error flags (bit set by validation kernels)
+  int64_t* d_small = nullptr;         // small pinned-size scratch for readbacks
+  int64_t* h_small = nullptr;         // pinned host mirror
+};
+
+struct mochy_graph {
+  mochy_ctx* ctx = nullptr;
+  int64_t E = 0, V = 0, nnz = 0, W = 0;  // hyperedges, nodes, incidences, hyperwedges
+  int32_t max_deg = 0;                   // max line-graph degree
+  int64_t* edge_ptr = nullptr;           // [E+1]
+  int32_t* edge_nodes = nullptr;         // [nnz]
+  int64_t* node_ptr = nullptr;           // [V+1]
+  int32_t* node_edges = nullptr;         // [nnz]
+  int8_t* heavy_bit = nullptr;           // [V]: bit index for the 64 highest-degree nodes, -1 otherwise
+  int64_t* lg_ptr = nullptr;             // [E+1] full line-graph rows
+  int32_t* lg_col = nullptr;             // [2W] ascending neighbour ids
+  int32_t* up_first = nullptr;           // [E]: position in row i of the first neighbour > i
+  int64_t* up_ptr = nullptr;             // [E+1]: prefix sums of upper-row lengths (wedge order)
+  uint4* rec = nullptr;                  // [2W]: per (centre, neighbour) region record
+  size_t bytes = 0;                      // device bytes held
+};
+
+// Per (centre i, neighbour x) record, 16 bytes:
+//   x: bit p set iff the p-th node of e_i (ascending) is in e_x
+//   y: bits 0..7  = |e_x \ e_i|;  bit 8 = e_x \ e_i holds a node without a heavy bit
+//   z,w: 64-bit mask of heavy nodes in e_x \ e_i
+constexpr uint32_t kRecLight = 1u << 8;
+
+// Error flag bits (d_flags[0]).
+constexpr int kFlagInval = 1, kFlagRange = 2, kFlagDup = 4;
+
+#define MOCHY_HIP(call)                                                        \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return MOCHY_EDEVICE;                                                    \
+    }                                                                          \
+  } while (0)
+
+// scan.hip
+void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp,
+                               hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+
+// project.hip
+mochy_status project_device(mochy_ctx* ctx, mochy_graph* g);
+
+// exact.hip
+mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                          int64_t* d_hist /* kHistSlots, zeroed inside */);
+
+// sampled.hip
+mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
+                            int64_t n0, int64_t* d_hist);
+
+// api.hip helpers
+mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);

@@ -1,0 +1,295 @@
+// Line-graph construction on the device (Algorithm 1, section 4.1).
+//
+// Steps, all on the context stream:
+//   1. validate the CSR (sorted, in range, non-empty, size <= MOCHY_MAX_EDGE);
+//   2. transpose it into E_v (node -> hyperedges): count, scan, scatter;
+//   3. pick the 64 highest-degree nodes ("heavy"; ties to the smaller id);
+//   4. line-graph degree of every hyperedge: the row of e_i is the union of
+//      E_v over v in e_i minus e_i itself, formed as a bitmap over hyperedge
+//      ids in LDS (so the row comes out sorted and de-duplicated);
+//   5. scan the degrees into row pointers; |wedges| = sum / 2;
+//   6. fill the rows (ascending neighbour ids) from the same bitmap;
+//   7. one 16-byte record per (centre, neighbour): which nodes of e_i the
+//      neighbour holds (a 32-bit mask; omega = its popcount), how many of its
+//      nodes lie outside e_i, which heavy nodes lie outside e_i, and whether a
+//      non-heavy node does.  Identical hyperedges show up here (no outside
+//      node, every node of e_i) and are reported.
+#include "common.h"
+
+namespace {
+
+__global__ void k_validate(int64_t E, int64_t V, int64_t nnz, const int64_t* __restrict__ ptr,
+                           const int32_t* __restrict__ nodes, int32_t* flags) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int64_t s = ptr[e], t = ptr[e + 1];
+  if (s < 0 || t > nnz || t <= s) { atomicOr(flags, kFlagInval); return; }
+  if (t - s > MOCHY_MAX_EDGE) { atomicOr(flags, kFlagRange); return; }
+  int32_t prev = -1;
+  for (int64_t q = s; q < t; ++q) {
+    const int32_t v = nodes[q];
+    if (v < 0 || int64_t(v) >= V || v <= prev) { atomicOr(flags, kFlagInval); return; }
+    prev = v;
+  }
+}
+
+__global__ void k_node_count(int64_t nnz, const int32_t* __restrict__ nodes,
+                             unsigned long long* cnt) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < nnz) atomicAdd(&cnt[nodes[q]], 1ull);
+}
+
+__global__ void k_node_fill(int64_t E, const int64_t* __restrict__ ptr,
+                            const int32_t* __restrict__ nodes, const int64_t* __restrict__ node_ptr,
+                            unsigned int* fill, int32_t* node_edges) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  for (int64_t q = ptr[e]; q < ptr[e + 1]; ++q) {
+    const int32_t v = nodes[q];
+    const unsigned slot = atomicAdd(&fill[v], 1u);
+    node_edges[node_ptr[v] + slot] = int32_t(e);
+  }
+}
+
+// One block of 1024 threads: 64 rounds of "largest degree not yet taken".
+__global__ __launch_bounds__(1024) void k_heavy(int64_t V, const int64_t* __restrict__ node_ptr,
+                                                int8_t* heavy_bit) {
+  __shared__ unsigned long long best[1024];
+  for (int64_t v = threadIdx.x; v < V; v += 1024) heavy_bit[v] = -1;
+  __syncthreads();
+  for (int round = 0; round < kHeavyBits; ++round) {
+    unsigned long long mine = 0;
+    for (int64_t v = threadIdx.x; v < V; v += 1024) {
+      if (heavy_bit[v] >= 0) continue;
+      const unsigned long long deg = (unsigned long long)(node_ptr[v + 1] - node_ptr[v]);
+      const unsigned long long key = (deg << 32) | (0xffffffffull - (unsigned long long)v);
+      mine = key > mine ? key : mine;
+    }
+    best[threadIdx.x] = mine;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+      if (threadIdx.x < unsigned(off) && best[threadIdx.x + off] > best[threadIdx.x])
+        best[threadIdx.x] = best[threadIdx.x + off];
+      __syncthreads();
+    }
+    const unsigned long long top = best[0];
+    __syncthreads();
+    if ((top >> 32) < 2) break;  // a node in fewer than two hyperedges is never shared
+    if (threadIdx.x == 0) heavy_bit[0xffffffffull - (top & 0xffffffffull)] = int8_t(round);
+    __syncthreads();
+  }
+}
+
+// Builds the neighbour bitmap of row i in LDS (nwords 32-bit words).
+__device__ void build_row_bitmap(int64_t i, const int64_t* __restrict__ ptr,
+                                 const int32_t* __restrict__ nodes,
+                                 const int64_t* __restrict__ node_ptr,
+                                 const int32_t* __restrict__ node_edges, uint32_t* bm, int nwords) {
+  for (int w = threadIdx.x; w < nwords; w += blockDim.x) bm[w] = 0;
+  __syncthreads();
+  for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) {
+    const int32_t v = nodes[q];
+    const int64_t lo = node_ptr[v], hi = node_ptr[v + 1];
+    for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+      const int32_t x = node_edges[r];
+      if (x != i) atomicOr(&bm[x >> 5], 1u << (x & 31));
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_proj_degree(int64_t E, const int64_t* __restrict__ ptr,
+                                                     const int32_t* __restrict__ nodes,
+                                                     const int64_t* __restrict__ node_ptr,
+                                                     const int32_t* __restrict__ node_edges,
+                                                     int nwords, int64_t* deg, int32_t* max_deg) {
+  extern __shared__ uint32_t bm[];
+  __shared__ int32_t red[256];
+  const int64_t i = blockIdx.x;
+  build_row_bitmap(i, ptr, nodes, node_ptr, node_edges, bm, nwords);
+  int32_t c = 0;
+  for (int w = threadIdx.x; w < nwords; w += blockDim.x) c += __popc(bm[w]);
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < unsigned(off)) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    deg[i] = red[0];
+    atomicMax(max_deg, red[0]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_proj_fill(int64_t E, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ nodes,
+                                                   const int64_t* __restrict__ node_ptr,
+                                                   const int32_t* __restrict__ node_edges,
+                                                   int nwords, const int64_t* __restrict__ lg_ptr,
+                                                   int32_t* lg_col, int32_t* up_first) {
+  extern __shared__ uint32_t bm[];
+  __shared__ int32_t part[256];
+  const int64_t i = blockIdx.x;
+  build_row_bitmap(i, ptr, nodes, node_ptr, node_edges, bm, nwords);
+  // each thread owns a contiguous chunk of words
+  const int chunk = (nwords + 255) / 256;
+  const int w0 = min(nwords, int(threadIdx.x) * chunk), w1 = min(nwords, w0 + chunk);
+  int32_t c = 0;
+  for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t pos = part[threadIdx.x] - c;  // exclusive
+  int32_t* out = lg_col + lg_ptr[i];
+  const int wi = int(i >> 5);
+  for (int w = w0; w < w1; ++w) {
+    uint32_t bits = bm[w];
+    if (w == wi) up_first[i] = pos + __popc(bits & ((1u << (i & 31)) - 1u));
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      bits &= bits - 1;
+      out[pos++] = (w << 5) | b;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ nodes,
+                                                 const int8_t* __restrict__ heavy_bit,
+                                                 const int64_t* __restrict__ lg_ptr,
+                                                 const int32_t* __restrict__ lg_col, uint4* rec,
+                                                 int32_t* flags) {
+  __shared__ int32_t ei[MOCHY_MAX_EDGE];
+  const int64_t i = blockIdx.x;
+  const int64_t s = ptr[i];
+  const int a = int(ptr[i + 1] - s);
+  if (threadIdx.x < unsigned(a)) ei[threadIdx.x] = nodes[s + threadIdx.x];
+  __syncthreads();
+  const int64_t base = lg_ptr[i];
+  const int64_t d = lg_ptr[i + 1] - base;
+  for (int64_t p = threadIdx.x; p < d; p += blockDim.x) {
+    const int32_t x = lg_col[base + p];
+    uint32_t m = 0, o = 0, light = 0;
+    unsigned long long hv = 0;
+    for (int64_t q = ptr[x]; q < ptr[x + 1]; ++q) {
+      const int32_t v = nodes[q];
+      int lo = 0, hi = a;  // binary search of v in e_i
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ei[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      if (lo < a && ei[lo] == v) {
+        m |= 1u << lo;
+      } else {
+        ++o;
+        const int hb = heavy_bit[v];
+        if (hb >= 0) hv |= 1ull << hb; else light = 1;
+      }
+    }
+    if (o == 0 && __popc(m) == a) atomicOr(flags, kFlagDup);
+    rec[base + p] = make_uint4(m, o | (light ? kRecLight : 0u), uint32_t(hv), uint32_t(hv >> 32));
+  }
+}
+
+__global__ void k_upper_len(int64_t E, const int64_t* __restrict__ lg_ptr,
+                            const int32_t* __restrict__ up_first, int64_t* up_len) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < E) up_len[i] = (lg_ptr[i + 1] - lg_ptr[i]) - up_first[i];
+  if (i == E) up_len[E] = 0;
+}
+
+inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+}  // namespace
+
+// Largest hyperedge count whose row bitmap (and rank table) fits in LDS.
+constexpr int64_t kMaxEdgesBitmap = 400000;
+
+mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
+  hipStream_t st = ctx->stream;
+  const int64_t E = g->E, V = g->V, nnz = g->nnz;
+  if (E > kMaxEdgesBitmap) {
+    ctx->err = "hypergraphs above 400000 hyperedges need the line-graph-free mode, not in this build";
+    return MOCHY_EUNSUPPORTED;
+  }
+  MOCHY_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int32_t), st));
+  if (E > 0)
+    k_validate<<<blocks(E, 256), 256, 0, st>>>(E, V, nnz, g->edge_ptr, g->edge_nodes, ctx->d_flags);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int32_t f0 = *reinterpret_cast<int32_t*>(ctx->h_small);
+  if (f0 & kFlagInval) { ctx->err = "malformed CSR (unsorted, out-of-range or empty hyperedge)"; return MOCHY_EINVAL; }
+  if (f0 & kFlagRange) { ctx->err = "a hyperedge exceeds MOCHY_MAX_EDGE nodes"; return MOCHY_ERANGE; }
+
+  // 2. transpose
+  const size_t tmpn = scan_tmp_elems(std::max<int64_t>(V, E) + 1);
+  int64_t* tmp = nullptr;
+  int64_t* cnt = nullptr;
+  unsigned int* fill = nullptr;
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK) return rc;
+  if ((rc = device_alloc(ctx, (void**)&cnt, size_t(std::max(V, E) + 1) * 8)) != MOCHY_OK) return rc;
+  if ((rc = device_alloc(ctx, (void**)&fill, size_t(V + 1) * 4)) != MOCHY_OK) return rc;
+  auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(cnt); (void)hipFree(fill); };
+  if ((rc = device_alloc(ctx, (void**)&g->node_ptr, size_t(V + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->node_edges, size_t(std::max<int64_t>(nnz, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->heavy_bit, size_t(std::max<int64_t>(V, 1)))) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->lg_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->up_first, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->up_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  g->bytes += size_t(V + 1) * 8 + size_t(nnz) * 4 + size_t(V) + size_t(E + 1) * 16 + size_t(E) * 4;
+
+  MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(V + 1) * 8, st));
+  MOCHY_HIP(hipMemsetAsync(fill, 0, size_t(V + 1) * 4, st));
+  if (nnz > 0)
+    k_node_count<<<blocks(nnz, 256), 256, 0, st>>>(nnz, g->edge_nodes, (unsigned long long*)cnt);
+  launch_exclusive_scan_i64(cnt, g->node_ptr, V + 1, tmp, st);
+  if (E > 0)
+    k_node_fill<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr, fill,
+                                                g->node_edges);
+  // 3. heavy nodes
+  if (V > 0) k_heavy<<<1, 1024, 0, st>>>(V, g->node_ptr, g->heavy_bit);
+
+  // 4-5. degrees and row pointers
+  const int nwords = int((E + 31) / 32);
+  const size_t bm_bytes = size_t(std::max(nwords, 1)) * 4;
+  MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(E + 1) * 8, st));
+  MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 1, 0, sizeof(int32_t), st));
+  if (E > 0)
+    k_proj_degree<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
+                                                      g->node_edges, nwords, cnt, ctx->d_flags + 1);
+  launch_exclusive_scan_i64(cnt, g->lg_ptr, E + 1, tmp, st);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + E, 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 1, 4, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int64_t twoW = ctx->h_small[0];
+  g->W = twoW / 2;
+  g->max_deg = *reinterpret_cast<int32_t*>(ctx->h_small + 1);
+
+  // 6. rows
+  if ((rc = device_alloc(ctx, (void**)&g->lg_col, size_t(std::max<int64_t>(twoW, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->rec, size_t(std::max<int64_t>(twoW, 1)) * 16)) != MOCHY_OK) { cleanup(); return rc; }
+  g->bytes += size_t(twoW) * 20;
+  if (E > 0)
+    k_proj_fill<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
+                                                    g->node_edges, nwords, g->lg_ptr, g->lg_col,
+                                                    g->up_first);
+  // 7. records
+  if (E > 0)
+    k_records<<<unsigned(E), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
+                                           g->lg_col, g->rec, ctx->d_flags);
+  // upper-row prefix (hyperwedge order for sampling)
+  k_upper_len<<<blocks(E + 1, 256), 256, 0, st>>>(E, g->lg_ptr, g->up_first, cnt);
+  launch_exclusive_scan_i64(cnt, g->up_ptr, E + 1, tmp, st);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  cleanup();
+  const int32_t f1 = *reinterpret_cast<int32_t*>(ctx->h_small);
+  if (f1 & kFlagDup) { ctx->err = "duplicate hyperedges (pass MOCHY_DEDUP for host input)"; return MOCHY_EDUP; }
+  return MOCHY_OK;
+}
