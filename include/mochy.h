@@ -138,6 +138,24 @@ mochy_status mochy_motif_pattern(int32_t id, uint32_t kind, uint8_t states[7]);
 /* Parent h-motif id of a 3h-motif id (1..431), or 0 if out of range. */
 int32_t mochy_parent_motif(int32_t id3);
 
+/* Workload statistics of a projected graph, computed on the device:
+ * out[0] |E|, out[1] |V|, out[2] sum |e|, out[3] |wedges|, out[4] max
+ * line-graph degree, out[5] MoCHy-E candidates sum_i C(d_i, 2) (pairs
+ * Algorithm 2 considers), out[6] sum over those candidates of
+ * min(|e_i|, |e_j|, |e_k|) (the size factor of Lemma 2's triple
+ * intersection), out[7] sum_i d_i^2.  out: host, 8 int64. */
+mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* out);
+
+/* Milliseconds spent in each device phase by the most recent call on this
+ * context, from HIP events recorded on the context stream (0 for phases the
+ * call did not run).  Phases: 0 upload+validate, 1 transpose + heavy-node
+ * pick, 2 line-graph degrees, 3 line-graph rows, 4 region records,
+ * 5 exact scheduling, 6 exact pair kernel, 7 exact light-node correction,
+ * 8 sampling draws, 9 sampled enumeration, 10 profile significance + CP.
+ * ms: host, MOCHY_NUM_PHASES doubles. */
+#define MOCHY_NUM_PHASES 11
+mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,11 @@ MAX_EDGE = 32
 # every symbol include/mochy.h declares
 EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_project",
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
-            "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif")
+            "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
+            "mochy_graph_stats", "mochy_phase_ms")
+NUM_PHASES = 11
+PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
+          "exact_correct", "sample_draw", "sample_enum", "profile_cp")
 
 
 class MochyError(RuntimeError):
@@ -82,6 +86,10 @@ def lib():
     L.mochy_motif_pattern.restype = ctypes.c_int
     L.mochy_parent_motif.argtypes = [i32]
     L.mochy_parent_motif.restype = i32
+    L.mochy_graph_stats.argtypes = [vp, vp, vp]
+    L.mochy_graph_stats.restype = ctypes.c_int
+    L.mochy_phase_ms.argtypes = [vp, vp]
+    L.mochy_phase_ms.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -219,3 +227,17 @@ def mochy_profile(ctx: Context, graphs, eps: float = 1.0):
     ctx.check(lib().mochy_profile(ctx.handle, len(graphs), arr, float(eps), _ptr(counts), _ptr(sig26),
                                   _ptr(cp26), _ptr(sig431), _ptr(cp431)), "mochy_profile")
     return counts, sig26, cp26, sig431, cp431
+
+
+def mochy_graph_stats(ctx: Context, g: Graph) -> dict:
+    out = np.zeros(8, dtype=np.int64)
+    ctx.check(lib().mochy_graph_stats(ctx.handle, g.handle, _ptr(out)), "mochy_graph_stats")
+    keys = ("num_edges", "num_nodes", "nnz", "hyperwedges", "max_line_degree", "candidates",
+            "candidate_min_size_sum", "sum_deg_sq")
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def mochy_phase_ms(ctx: Context) -> dict:
+    out = np.zeros(NUM_PHASES, dtype=np.float64)
+    ctx.check(lib().mochy_phase_ms(ctx.handle, _ptr(out)), "mochy_phase_ms")
+    return {k: float(v) for k, v in zip(PHASES, out)}

@@ -60,7 +60,59 @@ mochy_status check_host_csr(mochy_ctx* ctx, const mochy_csr* c) {
   return MOCHY_OK;
 }
 
+// Per-row workload statistics from the region records: candidates C(d,2),
+// the sum over candidate pairs of min(|e_i|, |e_j|, |e_k|), and d^2.
+__global__ __launch_bounds__(256) void k_stats(const int64_t* __restrict__ edge_ptr,
+                                               const int64_t* __restrict__ lg_ptr,
+                                               const uint4* __restrict__ rec,
+                                               unsigned long long* out) {
+  __shared__ unsigned int cnt[MOCHY_MAX_EDGE + 2];
+  const int64_t i = blockIdx.x;
+  if (threadIdx.x < MOCHY_MAX_EDGE + 2) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = lg_ptr[i], d = lg_ptr[i + 1] - base;
+  for (int64_t p = threadIdx.x; p < d; p += blockDim.x) {
+    const uint4 r = rec[base + p];
+    atomicAdd(&cnt[__popc(r.x) + (r.y & 0xffu)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long a = (unsigned long long)(edge_ptr[i + 1] - edge_ptr[i]);
+    unsigned long long ge = 0, sum = 0;  // ge = neighbours of size >= s
+    for (int s = MOCHY_MAX_EDGE; s >= 1; --s) {
+      const unsigned long long gt = ge;
+      ge += cnt[s];
+      const unsigned long long pairs_min_s = ge * (ge - (ge ? 1 : 0)) / 2 - gt * (gt - (gt ? 1 : 0)) / 2;
+      sum += pairs_min_s * (a < (unsigned long long)s ? a : (unsigned long long)s);
+    }
+    const unsigned long long dd = (unsigned long long)d;
+    atomicAdd(&out[0], dd * (dd - (dd ? 1 : 0)) / 2);
+    atomicAdd(&out[1], sum);
+    atomicAdd(&out[2], dd * dd);
+  }
+}
+
 }  // namespace
+
+void phases_collect(mochy_ctx* c) {
+  for (int p = 0; p < MOCHY_NUM_PHASES; ++p) {
+    if (!(c->phases_run & (1u << p))) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]) == hipSuccess) c->phase_ms[p] += ms;
+  }
+  c->phases_run = 0;
+}
+
+static void phases_reset(mochy_ctx* c) {
+  c->phases_run = 0;
+  for (double& m : c->phase_ms) m = 0.0;
+}
+
+extern "C" mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return MOCHY_EINVAL;
+  std::memcpy(ms, ctx->phase_ms, sizeof(ctx->phase_ms));
+  return MOCHY_OK;
+}
 
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
@@ -104,6 +156,8 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
     return fail(MOCHY_ENOMEM);
   if (hipHostMalloc((void**)&ctx->h_small, 512 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
+  for (auto& e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(MOCHY_EDEVICE);
   if (hipMemcpy(ctx->d_code_to_id3, pt.code_to_id3, sizeof(pt.code_to_id3), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(ctx->d_id3_to_id26, parent, sizeof(parent), hipMemcpyHostToDevice) != hipSuccess)
     return fail(MOCHY_EDEVICE);
@@ -120,6 +174,8 @@ extern "C" void mochy_ctx_destroy(mochy_ctx* ctx) {
   (void)hipFree(ctx->d_flags);
   (void)hipFree(ctx->d_small);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -144,6 +200,7 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
   if (!c || !out) { ctx->err = "null argument"; return MOCHY_EINVAL; }
   *out = nullptr;
   ctx->err.clear();
+  phases_reset(ctx);
   if (c->num_edges < 0 || c->num_nodes < 0 || c->num_nodes > INT32_MAX || c->num_edges > INT32_MAX - 1) {
     ctx->err = "num_nodes / num_edges out of range";
     return MOCHY_EINVAL;
@@ -157,6 +214,7 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
   g->V = c->num_nodes;
   auto fail = [&](mochy_status s) { mochy_graph_free(g); return s; };
   mochy_status rc;
+  phase_begin(ctx, kPhUpload);
   if (!c->on_device) {
     if ((rc = check_host_csr(ctx, c)) != MOCHY_OK) return fail(rc);
     const int64_t* ptr = c->edge_ptr;
@@ -239,6 +297,7 @@ extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_grap
                                                 int64_t* counts431) {
   if (!ctx) return MOCHY_EINVAL;
   ctx->err.clear();
+  phases_reset(ctx);
   if (!g || g->ctx != ctx || c0 < 0 || c1 < c0 || c1 > g->E) {
     ctx->err = "bad graph or centre range";
     return MOCHY_EINVAL;
@@ -261,6 +320,21 @@ extern "C" mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g, 
     return MOCHY_EINVAL;
   }
   return mochy_count_exact_range(ctx, g, 0, g->E, counts26, counts431);
+}
+
+extern "C" mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* out) {
+  if (!ctx) return MOCHY_EINVAL;
+  if (!g || g->ctx != ctx || !out) { ctx->err = "bad argument"; return MOCHY_EINVAL; }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  unsigned long long* d = (unsigned long long*)(ctx->d_small + 500);
+  MOCHY_HIP(hipMemsetAsync(d, 0, 3 * 8, st));
+  if (g->E > 0) k_stats<<<unsigned(g->E), 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->rec, d);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 500, d, 3 * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  out[0] = g->E; out[1] = g->V; out[2] = g->nnz; out[3] = g->W; out[4] = g->max_deg;
+  out[5] = ctx->h_small[500]; out[6] = ctx->h_small[501]; out[7] = ctx->h_small[502];
+  return MOCHY_OK;
 }
 
 extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r,

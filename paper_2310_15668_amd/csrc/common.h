@@ -37,7 +37,23 @@ struct mochy_ctx {
   int32_t* d_flags = nullptr;         // device error flags (bit set by validation kernels)
   int64_t* d_small = nullptr;         // small pinned-size scratch for readbacks
   int64_t* h_small = nullptr;         // pinned host mirror
+  hipEvent_t ev[2 * MOCHY_NUM_PHASES] = {};
+  uint32_t phases_run = 0;            // phases recorded since the last reset
+  double phase_ms[MOCHY_NUM_PHASES] = {};
 };
+
+// Phase timing: bracket device work on the context stream.
+enum Phase { kPhUpload = 0, kPhTranspose, kPhDegree, kPhRows, kPhRecords, kPhSched, kPhPairs,
+             kPhCorrect, kPhDraw, kPhSample, kPhProfile };
+inline void phase_begin(mochy_ctx* c, int p) {
+  (void)hipEventRecord(c->ev[2 * p], c->stream);
+}
+inline void phase_end(mochy_ctx* c, int p) {
+  (void)hipEventRecord(c->ev[2 * p + 1], c->stream);
+  c->phases_run |= 1u << p;
+}
+// after the stream is synchronized: fold recorded phases into phase_ms
+void phases_collect(mochy_ctx* c);
 
 struct mochy_graph {
   mochy_ctx* ctx = nullptr;
@@ -85,6 +101,10 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g);
 // exact.hip
 mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                           int64_t* d_hist /* kHistSlots, zeroed inside */);
+
+// correct.hip: exact fix-up of pairs that share a light node outside the centre
+mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                            int64_t* d_hist);
 
 // sampled.hip
 mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,

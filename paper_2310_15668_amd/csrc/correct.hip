@@ -1,0 +1,261 @@
+// Exact fix-up of the pairs the pair kernel classified with an incomplete R5.
+//
+// The pair kernel takes R5 = |e_j ∩ e_k - e_i| from exact bits for the 64
+// highest-degree ("heavy") nodes only.  It is exact for every pair of
+// neighbours of e_i unless e_j and e_k also share a lower-degree ("light")
+// node outside e_i.  Whether two hyperedges share a light node does not
+// depend on the centre, and few pairs do (sum over light nodes w of
+// C(|E_w|, 2)), so the fix-up works pair by pair:
+//
+//  1. light pairs: for every light node w, every pair {e_j, e_k} of E_w whose
+//     smallest shared light node is w (each pair once).  The pair is owned by
+//     the endpoint with the longer line-graph row.
+//  2. for every light pair, the centres are N_j ∩ N_k: one workgroup per
+//     owner j holds row j as an LDS bitmap (with per-word ranks, so a hit gives
+//     the position of e_i in row j) and scans the partner's row.  For a
+//     centre e_i, with masks over the nodes of e_j taken from the records of
+//     row j (m_ji: e_j ∩ e_i, m_jk: e_j ∩ e_k) and the heavy-node mask H_j of
+//     e_j:
+//        t   = popcount(m_ji & m_jk)                 = |e_i ∩ e_j ∩ e_k|
+//        r5h = popcount(m_jk & H_j & ~m_ji)            heavy part of R5
+//        ls  = popcount(m_jk & ~H_j & ~m_ji)           light part of R5
+//     and omega(e_i, e_k) from the record of row k at the scanned position.
+//     If ls = 0 the pair kernel was exact at this centre.  Otherwise the pair
+//     kernel recorded the class with R5 = r5h, counted iff both neighbours
+//     are above e_i or the two looked disjoint; the exact class has
+//     R5 = r5h + ls and, since e_j and e_k meet, is counted iff both are
+//     above e_i (Algorithm 2's condition).  The first is removed, the second
+//     added.
+#include "classify.h"
+#include "common.h"
+
+namespace {
+
+// Is w the smallest light node shared by e_x and e_y?  (Both contain w.)
+__device__ __forceinline__ bool smallest_shared_light(int32_t x, int32_t y, int32_t w,
+                                                      const int64_t* __restrict__ edge_ptr,
+                                                      const int32_t* __restrict__ edge_nodes,
+                                                      const int8_t* __restrict__ heavy_bit) {
+  int64_t p = edge_ptr[x], q = edge_ptr[y];
+  const int64_t pe = edge_ptr[x + 1], qe = edge_ptr[y + 1];
+  while (p < pe && q < qe) {
+    const int32_t u = edge_nodes[p], v = edge_nodes[q];
+    if (u >= w || v >= w) {
+      if (u < v) ++p;
+      else if (u > v) ++q;
+      else return true;  // reached w (u == v >= w means u == w: first shared light is w)
+      continue;
+    }
+    if (u < v) ++p;
+    else if (u > v) ++q;
+    else {
+      if (heavy_bit[u] < 0) return false;
+      ++p; ++q;
+    }
+  }
+  return true;
+}
+
+// One wave per light node w: every pair of E_w whose smallest shared light
+// node is w.  kFill = false counts pairs per owner, true writes partners.
+template <bool kFill>
+__global__ __launch_bounds__(256) void k_light_pairs(
+    int64_t V, const int64_t* __restrict__ node_ptr, const int32_t* __restrict__ node_edges,
+    const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ edge_ptr,
+    const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ lg_ptr,
+    unsigned long long* pcount, const int64_t* __restrict__ poff, int32_t* partners) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (w >= V || heavy_bit[w] >= 0) return;  // uniform per wave
+  const int64_t lo = node_ptr[w];
+  const int D = int(node_ptr[w + 1] - lo);
+  for (int kc = 0; kc < D; kc += 64) {
+    const int b = kc + lane;
+    const int32_t yb = b < D ? node_edges[lo + b] : 0;
+    const int64_t db = b < D ? lg_ptr[yb + 1] - lg_ptr[yb] : 0;
+    const int aend = min(kc + 64, D) - 1;
+    for (int a = 0; a < aend; ++a) {
+      const int32_t ya = node_edges[lo + a];
+      if (!(b < D && a < b)) continue;
+      if (!smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit)) continue;
+      const int64_t da = lg_ptr[ya + 1] - lg_ptr[ya];
+      const bool a_owns = da > db || (da == db && ya < yb);
+      const int32_t owner = a_owns ? ya : yb, partner = a_owns ? yb : ya;
+      const unsigned long long slot = atomicAdd(&pcount[owner], 1ull);
+      if (kFill) partners[poff[owner] + int64_t(slot)] = partner;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_light_fix(
+    int64_t c0, int64_t c1, int nwE, const int32_t* __restrict__ owners,
+    const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
+    const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
+    const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
+    const int32_t* __restrict__ lg_col, const uint4* __restrict__ rec,
+    const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
+  extern __shared__ uint32_t sm[];
+  uint32_t* bm = sm;          // row j over hyperedge ids
+  uint32_t* rank = sm + nwE;  // set bits before each word
+  __shared__ uint16_t lut[kNumCodes];
+  __shared__ unsigned long long hist[kHistSlots];
+  __shared__ int32_t part[256];
+  __shared__ uint32_t hmask;
+  const int32_t j = owners[blockIdx.x];
+  const int64_t jb = lg_ptr[j];
+  const int dj = int(lg_ptr[j + 1] - jb);
+  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
+  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0;
+  for (int w = threadIdx.x; w < nwE; w += blockDim.x) bm[w] = 0;
+  if (threadIdx.x == 0) {
+    uint32_t h = 0;
+    int n = 0;
+    for (int64_t q = edge_ptr[j]; q < edge_ptr[j + 1]; ++q, ++n)
+      if (heavy_bit[edge_nodes[q]] >= 0) h |= 1u << n;
+    hmask = h;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < dj; p += blockDim.x) {
+    const int32_t x = lg_col[jb + p];
+    atomicOr(&bm[x >> 5], 1u << (x & 31));
+  }
+  __syncthreads();
+  {
+    const int chunk = (nwE + 255) / 256;
+    const int w0 = min(nwE, int(threadIdx.x) * chunk), w1 = min(nwE, w0 + chunk);
+    int32_t c = 0;
+    for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
+    part[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += add;
+      __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - c;
+    for (int w = w0; w < w1; ++w) {
+      rank[w] = uint32_t(run);
+      run += __popc(bm[w]);
+    }
+  }
+  __syncthreads();
+  const uint32_t H = hmask;
+  const uint32_t sizej = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
+  const uint32_t L = (sizej >= 32u ? 0xffffffffu : ((1u << sizej) - 1u)) & ~H;
+  for (int64_t pp = poff[blockIdx.x]; pp < poff[blockIdx.x + 1]; ++pp) {
+    const int32_t k = partners[pp];
+    // record of e_k in row j
+    const uint32_t kw = bm[k >> 5];
+    const int qk = int(rank[k >> 5] + __popc(kw & ((1u << (k & 31)) - 1u)));
+    const uint32_t mjk = rec[jb + qk].x;
+    const int64_t kb = lg_ptr[k];
+    const int dk = int(lg_ptr[k + 1] - kb);
+    const uint32_t sizek = uint32_t(edge_ptr[k + 1] - edge_ptr[k]);
+    for (int r = threadIdx.x; r < dk; r += blockDim.x) {
+      const int32_t i = lg_col[kb + r];
+      if (i < c0 || i >= c1) continue;
+      const uint32_t iw = bm[i >> 5];
+      const uint32_t ibit = 1u << (i & 31);
+      if (!(iw & ibit)) continue;  // not a neighbour of e_j (or i == j)
+      const uint32_t mji = rec[jb + int(rank[i >> 5] + __popc(iw & (ibit - 1u)))].x;
+      const uint32_t ls = __popc(mjk & L & ~mji);
+      if (ls == 0u) continue;  // the pair kernel was exact at this centre
+      const uint32_t wik = __popc(rec[kb + r].x);
+      const uint32_t t = __popc(mji & mjk);
+      const uint32_t r5h = __popc(mjk & H & ~mji);
+      const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
+      const uint32_t pj = __popc(mji);
+      Side K;
+      K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
+      const uint32_t oj = sizej - pj;
+      const bool above = (j > i) && (k > i);
+      if (above || (t | r5h) == 0u) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h)]], ~0ull);
+      if (above) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h + ls)]], 1ull);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x)
+    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
+}
+
+// owners: hyperedges with at least one light partner, compacted.
+__global__ void k_owner_list(int64_t E, const unsigned long long* __restrict__ pcount,
+                             unsigned long long* nown, int32_t* owners, int64_t* ocount) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x >= E || pcount[x] == 0) return;
+  const unsigned long long s = atomicAdd(nown, 1ull);
+  owners[s] = int32_t(x);
+  ocount[s] = int64_t(pcount[x]);
+}
+
+__global__ void k_owner_offsets(int64_t n, const int32_t* __restrict__ owners,
+                                const int64_t* __restrict__ poff, int64_t* eoff) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s < n) eoff[owners[s]] = poff[s];
+}
+
+inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+}  // namespace
+
+mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                            int64_t* d_hist) {
+  hipStream_t st = ctx->stream;
+  const int64_t E = g->E, V = g->V;
+  if (c1 <= c0 || E == 0 || V == 0) return MOCHY_OK;
+  const int nwE = int((E + 31) / 32);
+  const size_t dyn = size_t(nwE) * 8;
+  if (dyn > 60 * 1024)
+    MOCHY_HIP(hipFuncSetAttribute((const void*)k_light_fix, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dyn)));
+  // pcount[E] | nown | owners[E] | ocount[E+1] | poff[E+1] | tmp
+  const size_t tmpn = scan_tmp_elems(E + 1);
+  const size_t n64 = size_t(E) + 1 + size_t(E + 1) * 2 + tmpn;
+  char* buf = nullptr;
+  mochy_status rc = device_alloc(ctx, (void**)&buf, n64 * 8 + size_t(E) * 4);
+  if (rc != MOCHY_OK) return rc;
+  unsigned long long* pcount = (unsigned long long*)buf;
+  unsigned long long* nown = pcount + E;
+  int64_t* ocount = (int64_t*)(nown + 1);
+  int64_t* poff = ocount + (E + 1);
+  int64_t* tmp = poff + (E + 1);
+  int32_t* owners = (int32_t*)(buf + n64 * 8);
+  auto done = [&](mochy_status s) { (void)hipFree(buf); return s; };
+  MOCHY_HIP(hipMemsetAsync(buf, 0, (size_t(E) + 1 + size_t(E + 1)) * 8, st));
+  const unsigned wblocks = blocks(V * 64, 256);
+  k_light_pairs<false><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
+                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
+                                                nullptr, nullptr);
+  k_owner_list<<<blocks(E, 256), 256, 0, st>>>(E, pcount, nown, owners, ocount);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 504, nown, 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int64_t nowners = ctx->h_small[504];
+  if (nowners == 0) return done(MOCHY_OK);
+  launch_exclusive_scan_i64(ocount, poff, nowners + 1, tmp, st);  // ocount[nowners] is 0
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 505, poff + nowners, 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int64_t npairs = ctx->h_small[505];
+  // per-owner offsets indexed by hyperedge id for the fill pass
+  int64_t* eoff = nullptr;
+  int32_t* partners = nullptr;
+  if ((rc = device_alloc(ctx, (void**)&eoff, size_t(E) * 8)) != MOCHY_OK) return done(rc);
+  if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) {
+    (void)hipFree(eoff);
+    return done(rc);
+  }
+  auto done2 = [&](mochy_status s) { (void)hipFree(eoff); (void)hipFree(partners); return done(s); };
+  // scatter owner offsets to hyperedge ids, reset counters, fill
+  k_owner_offsets<<<blocks(nowners, 256), 256, 0, st>>>(nowners, owners, poff, eoff);
+  MOCHY_HIP(hipMemsetAsync(pcount, 0, size_t(E) * 8, st));
+  k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
+                                               g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
+                                               partners);
+  k_light_fix<<<unsigned(nowners), 256, dyn, st>>>(c0, c1, nwE, owners, poff, partners, g->edge_ptr,
+                                                   g->edge_nodes, g->heavy_bit, g->lg_ptr, g->lg_col,
+                                                   g->rec, ctx->d_code_to_id3,
+                                                   (unsigned long long*)d_hist);
+  MOCHY_HIP(hipGetLastError());
+  MOCHY_HIP(hipStreamSynchronize(st));
+  return done2(MOCHY_OK);
+}

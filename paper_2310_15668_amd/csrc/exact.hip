@@ -28,6 +28,7 @@
 // persistent waves.  Counts go to a per-workgroup LDS histogram (several
 // copies, picked by lane, to thin same-bin conflicts), flushed once per
 // workgroup with 64-bit global atomics.
+#include "classify.h"
 #include "common.h"
 
 namespace {
@@ -112,34 +113,6 @@ __global__ void k_sched_scatter(int64_t c0, int64_t c1, const int64_t* __restric
   order[cnt[nb] + int64_t(slot)] = int32_t(i);
 }
 
-// ---------------------------------------------------------------------------
-// Classification of one pair, shared by the main and the correction kernels.
-
-struct Side {          // neighbour k held by a lane
-  uint32_t m, o, s;    // mask in e_i, outside count, popcount(m)
-  unsigned long long h;
-};
-
-__device__ __forceinline__ uint32_t st3(uint32_t c) { return c < 2u ? c : 2u; }
-
-// code = sum_r min(R_r, 2) * 3^r with R1 least significant
-__device__ __forceinline__ uint32_t pair_code(uint32_t a, uint32_t mj, uint32_t pj, uint32_t oj,
-                                              const Side& k, uint32_t t, uint32_t r5) {
-  const uint32_t R1 = a + t - pj - k.s;
-  const uint32_t R2 = oj - r5;
-  const uint32_t R3 = k.o - r5;
-  const uint32_t R4 = pj - t;
-  const uint32_t R6 = k.s - t;
-  uint32_t code = st3(t);                 // R7
-  code = code * 3u + st3(R6);
-  code = code * 3u + st3(r5);             // R5
-  code = code * 3u + st3(R4);
-  code = code * 3u + st3(R3);
-  code = code * 3u + st3(R2);
-  code = code * 3u + st3(R1);
-  return code;
-}
-
 // Walk j over [j0, j1) against the lane's k.  kCountAll: both j and k are
 // above the centre (count every pair); otherwise count only disjoint pairs.
 // kDiag: the j range overlaps the lane block, so require j < kp.
@@ -159,7 +132,7 @@ __device__ __forceinline__ void walk(const uint4* __restrict__ row, int j0, int 
     if (!kCountAll) act = act && ((t | r5) == 0u);
     if (act) {
       const uint32_t pj = __popc(mj);
-      const uint32_t code = pair_code(a, mj, pj, oj, k, t, r5);
+      const uint32_t code = pair_code(a, pj, oj, k, t, r5);
       atomicAdd(&hist[lut[code]], 1ull);
     }
   }
@@ -223,128 +196,6 @@ __global__ __launch_bounds__(256) void k_exact_main(
   }
 }
 
-// ---------------------------------------------------------------------------
-// Correction for pairs of neighbours that share a light node outside e_i.
-// One workgroup per centre.  LDS: the row as a bitmap over hyperedge ids plus
-// per-word ranks (position of a neighbour = rank of its bit).
-
-__device__ __forceinline__ bool in_sorted(const int32_t* s, int n, int32_t v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (s[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo < n && s[lo] == v;
-}
-
-__global__ __launch_bounds__(256) void k_exact_correct(
-    int64_t c0, int nwords, const int64_t* __restrict__ edge_ptr,
-    const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ node_ptr,
-    const int32_t* __restrict__ node_edges, const int8_t* __restrict__ heavy_bit,
-    const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ lg_col,
-    const int32_t* __restrict__ up_first, const uint4* __restrict__ rec,
-    const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
-  extern __shared__ uint32_t sm[];
-  uint32_t* bm = sm;
-  uint32_t* rank = sm + nwords;
-  __shared__ uint16_t lut[kNumCodes];
-  __shared__ unsigned long long hist[kHistSlots];
-  __shared__ int32_t ei[MOCHY_MAX_EDGE];
-  __shared__ int32_t part[256];
-  const int64_t i = c0 + blockIdx.x;
-  const int64_t base = lg_ptr[i];
-  const int d = int(lg_ptr[i + 1] - base);
-  if (d < 2) return;  // uniform for the block, before any barrier
-  const int a = int(edge_ptr[i + 1] - edge_ptr[i]);
-  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
-  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0;
-  for (int w = threadIdx.x; w < nwords; w += blockDim.x) bm[w] = 0;
-  if (threadIdx.x < unsigned(a)) ei[threadIdx.x] = edge_nodes[edge_ptr[i] + threadIdx.x];
-  __syncthreads();
-  for (int p = threadIdx.x; p < d; p += blockDim.x) {
-    const int32_t x = lg_col[base + p];
-    atomicOr(&bm[x >> 5], 1u << (x & 31));
-  }
-  __syncthreads();
-  {
-    const int chunk = (nwords + 255) / 256;
-    const int w0 = min(nwords, int(threadIdx.x) * chunk), w1 = min(nwords, w0 + chunk);
-    int32_t c = 0;
-    for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
-    part[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      const int32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
-      __syncthreads();
-      part[threadIdx.x] += add;
-      __syncthreads();
-    }
-    int32_t run = part[threadIdx.x] - c;
-    for (int w = w0; w < w1; ++w) {
-      rank[w] = uint32_t(run);
-      run += __popc(bm[w]);
-    }
-  }
-  __syncthreads();
-  const int u = up_first[i];
-  const uint32_t ua = uint32_t(a);
-  for (int p = threadIdx.x; p < d; p += blockDim.x) {
-    const uint4 rp = rec[base + p];
-    if (!(rp.y & kRecLight)) continue;
-    const int32_t x = lg_col[base + p];
-    const int64_t xs = edge_ptr[x], xe = edge_ptr[x + 1];
-    for (int64_t qx = xs; qx < xe; ++qx) {
-      const int32_t w = edge_nodes[qx];
-      if (heavy_bit[w] >= 0 || in_sorted(ei, a, w)) continue;
-      for (int64_t r = node_ptr[w]; r < node_ptr[w + 1]; ++r) {
-        const int32_t y = node_edges[r];
-        if (y == i || y == x) continue;
-        const uint32_t word = bm[y >> 5];
-        const uint32_t bit = 1u << (y & 31);
-        if (!(word & bit)) continue;
-        const int q = int(rank[y >> 5] + __popc(word & (bit - 1u)));
-        if (q <= p) continue;
-        // light nodes outside e_i shared by e_x and e_y: count and smallest
-        int64_t pa = xs, pb = edge_ptr[y];
-        const int64_t pe = edge_ptr[y + 1];
-        uint32_t shared = 0;
-        int32_t smallest = 0x7fffffff;
-        while (pa < xe && pb < pe) {
-          const int32_t va = edge_nodes[pa], vb = edge_nodes[pb];
-          if (va < vb) ++pa;
-          else if (va > vb) ++pb;
-          else {
-            if (heavy_bit[va] < 0 && !in_sorted(ei, a, va)) {
-              ++shared;
-              smallest = min(smallest, va);
-            }
-            ++pa; ++pb;
-          }
-        }
-        if (smallest != w) continue;  // handled at the smallest shared light node
-        const uint4 rq = rec[base + q];
-        Side k;
-        k.m = rq.x; k.o = rq.y & 0xffu; k.s = __popc(rq.x);
-        k.h = (unsigned long long)rq.z | ((unsigned long long)rq.w << 32);
-        const uint32_t mj = rp.x, oj = rp.y & 0xffu, pj = __popc(rp.x);
-        const unsigned long long hj = (unsigned long long)rp.z | ((unsigned long long)rp.w << 32);
-        const uint32_t t = __popc(mj & k.m);
-        const uint32_t r5h = __popcll(hj & k.h);
-        const bool above = (p >= u) && (q >= u);
-        // what the main kernel recorded
-        if (above || (t | r5h) == 0u)
-          atomicAdd(&hist[lut[pair_code(ua, mj, pj, oj, k, t, r5h)]], ~0ull);  // -1
-        // the exact class: e_j and e_k meet, so counted iff both are above e_i
-        if (above)
-          atomicAdd(&hist[lut[pair_code(ua, mj, pj, oj, k, t, r5h + shared)]], 1ull);
-      }
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x)
-    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
-}
-
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 }  // namespace
@@ -368,21 +219,26 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   int64_t* total = (int64_t*)(fill + (maxnb + 1));
   unsigned long long* queue = (unsigned long long*)(total + 1);
   int32_t* order = (int32_t*)(scratch + n8 * 8);
+  phase_begin(ctx, kPhSched);
   MOCHY_HIP(hipMemsetAsync(scratch, 0, n8 * 8, st));
   const int64_t rows = c1 - c0;
   k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, g->lg_ptr, nbhist);
   k_sched_scan<<<1, 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
   k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, g->lg_ptr, cnt, fill, order);
+  phase_end(ctx, kPhSched);
   const unsigned grid = unsigned(ctx->num_cus) * 8u;
+  phase_begin(ctx, kPhPairs);
   k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, order, item_start,
                                      cnt, maxnb, total, queue, ctx->d_code_to_id3,
                                      (unsigned long long*)d_hist);
-  const int nwords = int((g->E + 31) / 32);
-  k_exact_correct<<<unsigned(rows), 256, size_t(nwords) * 8, st>>>(
-      c0, nwords, g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
-      g->lg_col, g->up_first, g->rec, ctx->d_code_to_id3, (unsigned long long*)d_hist);
+  phase_end(ctx, kPhPairs);
+  phase_begin(ctx, kPhCorrect);
+  rc = correct_device(ctx, g, c0, c1, d_hist);
+  if (rc != MOCHY_OK) { (void)hipFree(scratch); return rc; }
+  phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
   (void)hipFree(scratch);
   return MOCHY_OK;
 }

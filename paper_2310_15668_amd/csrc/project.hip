@@ -220,8 +220,10 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int32_t), st));
   if (E > 0)
     k_validate<<<blocks(E, 256), 256, 0, st>>>(E, V, nnz, g->edge_ptr, g->edge_nodes, ctx->d_flags);
+  phase_end(ctx, kPhUpload);
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
   const int32_t f0 = *reinterpret_cast<int32_t*>(ctx->h_small);
   if (f0 & kFlagInval) { ctx->err = "malformed CSR (unsorted, out-of-range or empty hyperedge)"; return MOCHY_EINVAL; }
   if (f0 & kFlagRange) { ctx->err = "a hyperedge exceeds MOCHY_MAX_EDGE nodes"; return MOCHY_ERANGE; }
@@ -244,6 +246,7 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   if ((rc = device_alloc(ctx, (void**)&g->up_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
   g->bytes += size_t(V + 1) * 8 + size_t(nnz) * 4 + size_t(V) + size_t(E + 1) * 16 + size_t(E) * 4;
 
+  phase_begin(ctx, kPhTranspose);
   MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(V + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(fill, 0, size_t(V + 1) * 4, st));
   if (nnz > 0)
@@ -254,19 +257,23 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
                                                 g->node_edges);
   // 3. heavy nodes
   if (V > 0) k_heavy<<<1, 1024, 0, st>>>(V, g->node_ptr, g->heavy_bit);
+  phase_end(ctx, kPhTranspose);
 
   // 4-5. degrees and row pointers
   const int nwords = int((E + 31) / 32);
   const size_t bm_bytes = size_t(std::max(nwords, 1)) * 4;
+  phase_begin(ctx, kPhDegree);
   MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(E + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 1, 0, sizeof(int32_t), st));
   if (E > 0)
     k_proj_degree<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
                                                       g->node_edges, nwords, cnt, ctx->d_flags + 1);
   launch_exclusive_scan_i64(cnt, g->lg_ptr, E + 1, tmp, st);
+  phase_end(ctx, kPhDegree);
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + E, 8, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 1, 4, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
   const int64_t twoW = ctx->h_small[0];
   g->W = twoW / 2;
   g->max_deg = *reinterpret_cast<int32_t*>(ctx->h_small + 1);
@@ -275,19 +282,24 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   if ((rc = device_alloc(ctx, (void**)&g->lg_col, size_t(std::max<int64_t>(twoW, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->rec, size_t(std::max<int64_t>(twoW, 1)) * 16)) != MOCHY_OK) { cleanup(); return rc; }
   g->bytes += size_t(twoW) * 20;
+  phase_begin(ctx, kPhRows);
   if (E > 0)
     k_proj_fill<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
                                                     g->node_edges, nwords, g->lg_ptr, g->lg_col,
                                                     g->up_first);
+  phase_end(ctx, kPhRows);
   // 7. records
+  phase_begin(ctx, kPhRecords);
   if (E > 0)
     k_records<<<unsigned(E), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
                                            g->lg_col, g->rec, ctx->d_flags);
   // upper-row prefix (hyperwedge order for sampling)
   k_upper_len<<<blocks(E + 1, 256), 256, 0, st>>>(E, g->lg_ptr, g->up_first, cnt);
   launch_exclusive_scan_i64(cnt, g->up_ptr, E + 1, tmp, st);
+  phase_end(ctx, kPhRecords);
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
   cleanup();
   const int32_t f1 = *reinterpret_cast<int32_t*>(ctx->h_small);
   if (f1 & kFlagDup) { ctx->err = "duplicate hyperedges (pass MOCHY_DEDUP for host input)"; return MOCHY_EDUP; }
