@@ -21,6 +21,26 @@ __global__ void k_fold(const int64_t* __restrict__ hist, const int32_t* __restri
   out26[h] = s;
 }
 
+// Algorithm 5's rescaling in float64: est = raw * |wedges| / (w * r), w = 2
+// for open and 3 for closed motifs (a 3h-motif takes its h-motif's w).
+__global__ void k_aplus_est(const int64_t* __restrict__ hist, const int32_t* __restrict__ parent,
+                            const int32_t* __restrict__ open26, int64_t W, int64_t r,
+                            int64_t* raw26, double* est26, double* est431) {
+  const int t = threadIdx.x;
+  if (t >= 1 && t < kHistSlots) {
+    const double w = open26[parent[t]] ? 2.0 : 3.0;
+    est431[t - 1] = (double(hist[t]) * double(W)) / (w * double(r));
+  }
+  if (t < MOCHY_NUM_H) {
+    int64_t s = 0;
+    for (int id3 = 1; id3 < kHistSlots; ++id3)
+      if (parent[id3] == t + 1) s += hist[id3];
+    raw26[t] = s;
+    const double w = open26[t + 1] ? 2.0 : 3.0;
+    est26[t] = (double(s) * double(W)) / (w * double(r));
+  }
+}
+
 struct RowHash {
   const int64_t* ptr;
   const int32_t* nodes;
@@ -152,13 +172,20 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   if (device_alloc(ctx, (void**)&ctx->d_code_to_id3, sizeof(pt.code_to_id3)) != MOCHY_OK ||
       device_alloc(ctx, (void**)&ctx->d_id3_to_id26, sizeof(parent)) != MOCHY_OK ||
       device_alloc(ctx, (void**)&ctx->d_flags, 16 * sizeof(int32_t)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_small, 512 * sizeof(int64_t)) != MOCHY_OK)
+      device_alloc(ctx, (void**)&ctx->d_small, 512 * sizeof(int64_t)) != MOCHY_OK ||
+      device_alloc(ctx, (void**)&ctx->d_open26, 27 * sizeof(int32_t)) != MOCHY_OK ||
+      device_alloc(ctx, (void**)&ctx->d_dbl, 512 * sizeof(double)) != MOCHY_OK)
+    return fail(MOCHY_ENOMEM);
+  if (hipHostMalloc((void**)&ctx->h_dbl, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
   if (hipHostMalloc((void**)&ctx->h_small, 512 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
   for (auto& e : ctx->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(MOCHY_EDEVICE);
-  if (hipMemcpy(ctx->d_code_to_id3, pt.code_to_id3, sizeof(pt.code_to_id3), hipMemcpyHostToDevice) != hipSuccess ||
+  int32_t open26[27];
+  for (int t = 0; t < 27; ++t) open26[t] = pt.id26_open[t];
+  if (hipMemcpy(ctx->d_open26, open26, sizeof(open26), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ctx->d_code_to_id3, pt.code_to_id3, sizeof(pt.code_to_id3), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(ctx->d_id3_to_id26, parent, sizeof(parent), hipMemcpyHostToDevice) != hipSuccess)
     return fail(MOCHY_EDEVICE);
   *out = ctx;
@@ -173,7 +200,10 @@ extern "C" void mochy_ctx_destroy(mochy_ctx* ctx) {
   (void)hipFree(ctx->d_id3_to_id26);
   (void)hipFree(ctx->d_flags);
   (void)hipFree(ctx->d_small);
+  (void)hipFree(ctx->d_open26);
+  (void)hipFree(ctx->d_dbl);
   if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+  if (ctx->h_dbl) (void)hipHostFree(ctx->h_dbl);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -341,9 +371,34 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
                                             uint64_t seed, int64_t sample_begin, int64_t* raw26,
                                             double* est26, int64_t* raw431, double* est431) {
   if (!ctx) return MOCHY_EINVAL;
-  ctx->err = "not built yet";
-  (void)g; (void)r; (void)seed; (void)sample_begin; (void)raw26; (void)est26; (void)raw431; (void)est431;
-  return MOCHY_EUNSUPPORTED;
+  ctx->err.clear();
+  phases_reset(ctx);
+  if (!g || g->ctx != ctx || r <= 0 || sample_begin < 0 || r > INT64_MAX - sample_begin) {
+    ctx->err = "bad graph, sample count or sample range";
+    return MOCHY_EINVAL;
+  }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  int64_t* d_hist = ctx->d_small + 64;
+  mochy_status rc = sampled_device(ctx, g, r, seed, sample_begin, d_hist);
+  if (rc != MOCHY_OK) return rc;
+  int64_t* d_raw26 = ctx->d_small;
+  k_aplus_est<<<1, 512, 0, st>>>(d_hist, ctx->d_id3_to_id26, ctx->d_open26, g->W, r, d_raw26,
+                                 ctx->d_dbl, ctx->d_dbl + 32);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, d_hist, kHistSlots * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + kHistSlots, d_raw26, MOCHY_NUM_H * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_dbl, ctx->d_dbl, (32 + MOCHY_NUM_3H) * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
+  if (ctx->h_small[0] != 0) {
+    ctx->err = "internal error: sampled triples with an invalid pattern";
+    return MOCHY_EDEVICE;
+  }
+  if (raw431) std::memcpy(raw431, ctx->h_small + 1, MOCHY_NUM_3H * 8);
+  if (raw26) std::memcpy(raw26, ctx->h_small + kHistSlots, MOCHY_NUM_H * 8);
+  if (est26) std::memcpy(est26, ctx->h_dbl, MOCHY_NUM_H * 8);
+  if (est431) std::memcpy(est431, ctx->h_dbl + 32, MOCHY_NUM_3H * 8);
+  return MOCHY_OK;
 }
 
 extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,

@@ -37,6 +37,9 @@ struct mochy_ctx {
   int32_t* d_flags = nullptr;         // device error flags (bit set by validation kernels)
   int64_t* d_small = nullptr;         // small pinned-size scratch for readbacks
   int64_t* h_small = nullptr;         // pinned host mirror
+  int32_t* d_open26 = nullptr;        // [27]: 1 if the h-motif is open
+  double* d_dbl = nullptr;            // [512] double outputs
+  double* h_dbl = nullptr;            // pinned host mirror
   hipEvent_t ev[2 * MOCHY_NUM_PHASES] = {};
   uint32_t phases_run = 0;            // phases recorded since the last reset
   double phase_ms[MOCHY_NUM_PHASES] = {};
