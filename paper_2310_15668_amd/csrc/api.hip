@@ -41,6 +41,64 @@ __global__ void k_aplus_est(const int64_t* __restrict__ hist, const int32_t* __r
   }
 }
 
+// Significance and characteristic profile (Eq. 1, Eq. 2) of graph 0 against
+// graphs 1..ng-1, in float64.  counts[g][t] for the 26 h-motifs (folded from
+// the 3h-motifs) and the 431 3h-motifs; Mr = (sum over copies, exact in
+// int64) / R; Delta = (M - Mr) / (M + Mr + eps); CP = Delta / sqrt(sum of
+// Delta^2 in order t = 1, 2, ...), all zeros if every Delta is 0.  The sum of
+// squares is formed with separately rounded multiplies and adds.
+__global__ void k_profile(const int64_t* __restrict__ hist, const int32_t* __restrict__ parent,
+                          int32_t ng, double eps, int64_t* counts, double* sig26, double* cp26,
+                          double* sig431, double* cp431) {
+  __shared__ double d26[MOCHY_NUM_H];
+  __shared__ double d431[MOCHY_NUM_3H];
+  const int t = threadIdx.x;
+  for (int g = 0; g < ng; ++g) {
+    const int64_t* hg = hist + int64_t(g) * kHistSlots;
+    int64_t* cg = counts + int64_t(g) * (MOCHY_NUM_H + MOCHY_NUM_3H);
+    if (t < MOCHY_NUM_H) {
+      int64_t s = 0;
+      for (int id3 = 1; id3 < kHistSlots; ++id3)
+        if (parent[id3] == t + 1) s += hg[id3];
+      cg[t] = s;
+    }
+    if (t < MOCHY_NUM_3H) cg[MOCHY_NUM_H + t] = hg[t + 1];
+  }
+  __syncthreads();
+  const int R = ng - 1;
+  for (int x = t; x < MOCHY_NUM_H + MOCHY_NUM_3H; x += blockDim.x) {
+    int64_t sum = 0;
+    for (int g = 1; g < ng; ++g) sum += counts[int64_t(g) * (MOCHY_NUM_H + MOCHY_NUM_3H) + x];
+    const double mr = double(sum) / double(R);
+    const double m = double(counts[x]);
+    const double d = __ddiv_rn(__dsub_rn(m, mr), __dadd_rn(__dadd_rn(m, mr), eps));
+    if (x < MOCHY_NUM_H) d26[x] = d; else d431[x - MOCHY_NUM_H] = d;
+  }
+  __syncthreads();
+  if (t == 0 || t == 1) {
+    const int n = t == 0 ? MOCHY_NUM_H : MOCHY_NUM_3H;
+    double* d = t == 0 ? d26 : d431;
+    double* sig = t == 0 ? sig26 : sig431;
+    double* cp = t == 0 ? cp26 : cp431;
+    double s = 0.0;
+    for (int x = 0; x < n; ++x) s = __dadd_rn(s, __dmul_rn(d[x], d[x]));
+    const double norm = __dsqrt_rn(s);
+    for (int x = 0; x < n; ++x) {
+      sig[x] = d[x];
+      cp[x] = s == 0.0 ? 0.0 : __ddiv_rn(d[x], norm);
+    }
+  }
+}
+
+// Adds the per-graph edge and node offsets to one graph's slice of the union.
+__global__ void k_union_offsets(int64_t e_begin, int64_t e_count, int64_t nnz_off, int64_t* edge_ptr,
+                                int64_t n_begin, int64_t n_count, int32_t node_off,
+                                int32_t* edge_nodes) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < e_count) edge_ptr[e_begin + x] += nnz_off;
+  if (x < n_count) edge_nodes[n_begin + x] += node_off;
+}
+
 struct RowHash {
   const int64_t* ptr;
   const int32_t* nodes;
@@ -119,12 +177,15 @@ void phases_collect(mochy_ctx* c) {
     if (!(c->phases_run & (1u << p))) continue;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]) == hipSuccess) c->phase_ms[p] += ms;
+    else (void)hipGetLastError();  // a timing query never fails the computation
   }
   c->phases_run = 0;
+  c->phases_begun = 0;
 }
 
 static void phases_reset(mochy_ctx* c) {
   c->phases_run = 0;
+  c->phases_begun = 0;
   for (double& m : c->phase_ms) m = 0.0;
 }
 
@@ -219,9 +280,33 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
     (void)hipStreamSynchronize(g->ctx->stream);
   }
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
-                  g->lg_col,   g->up_first,   g->up_ptr,   g->rec};
+                  g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
+                  g->gnoff,    g->row_graph};
   for (void* b : bufs) (void)hipFree(b);
   delete g;
+}
+
+static mochy_status set_graph_offsets(mochy_ctx* ctx, mochy_graph* g) {
+  g->ng = int32_t(g->h_geoff.size()) - 1;
+  g->max_graph_edges = 0;
+  for (int x = 0; x < g->ng; ++x)
+    g->max_graph_edges = std::max(g->max_graph_edges, g->h_geoff[x + 1] - g->h_geoff[x]);
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&g->geoff, g->h_geoff.size() * 8)) != MOCHY_OK) return rc;
+  if ((rc = device_alloc(ctx, (void**)&g->gvoff, g->h_gvoff.size() * 8)) != MOCHY_OK) return rc;
+  if ((rc = device_alloc(ctx, (void**)&g->gnoff, g->h_gnoff.size() * 8)) != MOCHY_OK) return rc;
+  MOCHY_HIP(hipMemcpyAsync(g->gnoff, g->h_gnoff.data(), g->h_gnoff.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  MOCHY_HIP(hipMemcpyAsync(g->geoff, g->h_geoff.data(), g->h_geoff.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  MOCHY_HIP(hipMemcpyAsync(g->gvoff, g->h_gvoff.data(), g->h_gvoff.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+  MOCHY_HIP(hipStreamSynchronize(ctx->stream));
+  return MOCHY_OK;
+}
+
+static mochy_status set_single_graph(mochy_ctx* ctx, mochy_graph* g) {
+  g->h_geoff = {0, g->E};
+  g->h_gvoff = {0, g->V};
+  g->h_gnoff = {0, g->nnz};
+  return set_graph_offsets(ctx, g);
 }
 
 extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32_t flags,
@@ -296,14 +381,12 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
     }
   }
   g->bytes = size_t(g->E + 1) * 8 + size_t(g->nnz) * 4;
+  if ((rc = set_single_graph(ctx, g)) != MOCHY_OK) return fail(rc);
   if ((rc = project_device(ctx, g)) != MOCHY_OK) return fail(rc);
   *out = g;
   if (num_hyperwedges) *num_hyperwedges = g->W;
   return MOCHY_OK;
 }
-
-// Largest hyperedge count the exact path's LDS row bitmap (plus ranks) handles.
-constexpr int64_t kMaxEdgesExact = 200000;
 
 static mochy_status finish_counts(mochy_ctx* ctx, int64_t* d_hist, int64_t* counts26,
                                   int64_t* counts431) {
@@ -331,10 +414,6 @@ extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_grap
   if (!g || g->ctx != ctx || c0 < 0 || c1 < c0 || c1 > g->E) {
     ctx->err = "bad graph or centre range";
     return MOCHY_EINVAL;
-  }
-  if (g->E > kMaxEdgesExact) {
-    ctx->err = "exact counting handles at most 200000 hyperedges in this build";
-    return MOCHY_EUNSUPPORTED;
   }
   MOCHY_HIP(hipSetDevice(ctx->device));
   int64_t* d_hist = ctx->d_small + 64;  // [432]
@@ -401,11 +480,144 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
   return MOCHY_OK;
 }
 
+// Builds graphs [g0, g1) of the input as one graph set (disjoint union) on the
+// device and projects it.
+static mochy_status build_set(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g0, int32_t g1,
+                              mochy_graph** out) {
+  hipStream_t st = ctx->stream;
+  *out = nullptr;
+  mochy_graph* g = new (std::nothrow) mochy_graph();
+  if (!g) return MOCHY_ENOMEM;
+  g->ctx = ctx;
+  auto fail = [&](mochy_status s) { mochy_graph_free(g); return s; };
+  phase_begin(ctx, kPhUpload);
+  std::vector<int64_t> nnz(g1 - g0);
+  g->h_geoff.assign(1, 0);
+  g->h_gvoff.assign(1, 0);
+  for (int32_t x = g0; x < g1; ++x) {
+    const mochy_csr& c = graphs[x];
+    if (c.num_edges < 0 || c.num_nodes < 0 || c.num_nodes > INT32_MAX) {
+      ctx->err = "graph " + std::to_string(x) + ": sizes out of range";
+      return fail(MOCHY_EINVAL);
+    }
+    int64_t n = 0;
+    if (!c.on_device) {
+      const mochy_status rc = check_host_csr(ctx, &c);
+      if (rc != MOCHY_OK) { ctx->err = "graph " + std::to_string(x) + ": " + ctx->err; return fail(rc); }
+      n = c.num_edges ? c.edge_ptr[c.num_edges] : 0;
+    } else if (c.num_edges) {
+      int64_t ends[2] = {0, 0};
+      MOCHY_HIP(hipMemcpyAsync(&ends[0], c.edge_ptr, 8, hipMemcpyDeviceToHost, st));
+      MOCHY_HIP(hipMemcpyAsync(&ends[1], c.edge_ptr + c.num_edges, 8, hipMemcpyDeviceToHost, st));
+      MOCHY_HIP(hipStreamSynchronize(st));
+      if (ends[0] != 0 || ends[1] < 0) { ctx->err = "graph " + std::to_string(x) + ": bad edge_ptr"; return fail(MOCHY_EINVAL); }
+      n = ends[1];
+    }
+    nnz[x - g0] = n;
+    g->h_geoff.push_back(g->h_geoff.back() + c.num_edges);
+    g->h_gvoff.push_back(g->h_gvoff.back() + c.num_nodes);
+  }
+  g->E = g->h_geoff.back();
+  g->V = g->h_gvoff.back();
+  if (g->E > INT32_MAX - 1 || g->V > INT32_MAX) { ctx->err = "batch too large"; return fail(MOCHY_ERANGE); }
+  g->nnz = 0;
+  g->h_gnoff.assign(1, 0);
+  for (int64_t n : nnz) {
+    g->nnz += n;
+    g->h_gnoff.push_back(g->nnz);
+  }
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&g->edge_ptr, size_t(g->E + 1) * 8)) != MOCHY_OK) return fail(rc);
+  if ((rc = device_alloc(ctx, (void**)&g->edge_nodes, size_t(g->nnz) * 4)) != MOCHY_OK) return fail(rc);
+  int64_t noff = 0;
+  for (int32_t x = g0; x < g1; ++x) {
+    const mochy_csr& c = graphs[x];
+    const int64_t eb = g->h_geoff[x - g0], ne = c.num_edges, nn = nnz[x - g0];
+    const hipMemcpyKind kind = c.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (ne) MOCHY_HIP(hipMemcpyAsync(g->edge_ptr + eb, c.edge_ptr, size_t(ne) * 8, kind, st));
+    if (nn) MOCHY_HIP(hipMemcpyAsync(g->edge_nodes + noff, c.edge_nodes, size_t(nn) * 4, kind, st));
+    const int64_t mx = std::max(ne, nn);
+    if (mx > 0)
+      k_union_offsets<<<unsigned((mx + 255) / 256), 256, 0, st>>>(eb, ne, noff, g->edge_ptr, noff, nn,
+                                                                  int32_t(g->h_gvoff[x - g0]), g->edge_nodes);
+    noff += nn;
+  }
+  MOCHY_HIP(hipMemcpyAsync(g->edge_ptr + g->E, &g->nnz, 8, hipMemcpyHostToDevice, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  if ((rc = set_graph_offsets(ctx, g)) != MOCHY_OK) return fail(rc);
+  if ((rc = project_device(ctx, g)) != MOCHY_OK) return fail(rc);
+  *out = g;
+  return MOCHY_OK;
+}
+
+// Exact counts of graphs [g0, g1) into d_all[g][kHistSlots]; halves the batch
+// when the device runs out of memory.
+static mochy_status profile_counts(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g0, int32_t g1,
+                                   int64_t* d_all) {
+  mochy_graph* set = nullptr;
+  mochy_status rc = build_set(ctx, graphs, g0, g1, &set);
+  if (rc == MOCHY_OK) {
+    rc = exact_device(ctx, set, 0, set->E, d_all + int64_t(g0) * kHistSlots);
+    mochy_graph_free(set);
+  }
+  if (rc == MOCHY_ENOMEM && g1 - g0 > 1) {
+    ctx->err.clear();
+    const int32_t mid = g0 + (g1 - g0) / 2;
+    if ((rc = profile_counts(ctx, graphs, g0, mid, d_all)) != MOCHY_OK) return rc;
+    return profile_counts(ctx, graphs, mid, g1, d_all);
+  }
+  return rc;
+}
+
 extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,
                                       double eps, int64_t* counts, double* sig26, double* cp26,
                                       double* sig431, double* cp431) {
   if (!ctx) return MOCHY_EINVAL;
-  ctx->err = "not built yet";
-  (void)num_graphs; (void)graphs; (void)eps; (void)counts; (void)sig26; (void)cp26; (void)sig431; (void)cp431;
-  return MOCHY_EUNSUPPORTED;
+  ctx->err.clear();
+  phases_reset(ctx);
+  if (num_graphs < 2 || !graphs || !(eps >= 0.0)) {
+    ctx->err = "need the hypergraph and at least one randomized copy, and eps >= 0";
+    return MOCHY_EINVAL;
+  }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const size_t per = MOCHY_NUM_H + MOCHY_NUM_3H;
+  int64_t* d_all = nullptr;     // [ng][kHistSlots]
+  int64_t* d_counts = nullptr;  // [ng][per]
+  double* d_out = nullptr;      // sig26, cp26, sig431, cp431
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&d_all, size_t(num_graphs) * kHistSlots * 8)) != MOCHY_OK) return rc;
+  auto cleanup = [&]() { (void)hipFree(d_all); (void)hipFree(d_counts); (void)hipFree(d_out); };
+  if ((rc = device_alloc(ctx, (void**)&d_counts, size_t(num_graphs) * per * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&d_out, 2 * per * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = profile_counts(ctx, graphs, 0, num_graphs, d_all)) != MOCHY_OK) { cleanup(); return rc; }
+  phase_begin(ctx, kPhProfile);
+  k_profile<<<1, 512, 0, st>>>(d_all, ctx->d_id3_to_id26, num_graphs, eps, d_counts, d_out,
+                               d_out + MOCHY_NUM_H, d_out + 2 * MOCHY_NUM_H,
+                               d_out + 2 * MOCHY_NUM_H + MOCHY_NUM_3H);
+  phase_end(ctx, kPhProfile);
+  std::vector<int64_t> hc(size_t(num_graphs) * per);
+  std::vector<double> ho(2 * per);
+  std::vector<int64_t> hall(size_t(num_graphs) * kHistSlots);
+  if (hipMemcpyAsync(hc.data(), d_counts, hc.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(ho.data(), d_out, ho.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(hall.data(), d_all, hall.size() * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    cleanup();
+    ctx->err = "device-to-host copy failed";
+    return MOCHY_EDEVICE;
+  }
+  phases_collect(ctx);
+  cleanup();
+  for (int32_t x = 0; x < num_graphs; ++x)
+    if (hall[size_t(x) * kHistSlots] != 0) {
+      ctx->err = "internal error: invalid pattern counted in graph " + std::to_string(x);
+      return MOCHY_EDEVICE;
+    }
+  if (counts) std::memcpy(counts, hc.data(), hc.size() * 8);
+  if (sig26) std::memcpy(sig26, ho.data(), MOCHY_NUM_H * 8);
+  if (cp26) std::memcpy(cp26, ho.data() + MOCHY_NUM_H, MOCHY_NUM_H * 8);
+  if (sig431) std::memcpy(sig431, ho.data() + 2 * MOCHY_NUM_H, MOCHY_NUM_3H * 8);
+  if (cp431) std::memcpy(cp431, ho.data() + 2 * MOCHY_NUM_H + MOCHY_NUM_3H, MOCHY_NUM_3H * 8);
+  return MOCHY_OK;
 }

@@ -41,6 +41,7 @@ struct mochy_ctx {
   double* d_dbl = nullptr;            // [512] double outputs
   double* h_dbl = nullptr;            // pinned host mirror
   hipEvent_t ev[2 * MOCHY_NUM_PHASES] = {};
+  uint32_t phases_begun = 0;          // phases whose start event was recorded
   uint32_t phases_run = 0;            // phases recorded since the last reset
   double phase_ms[MOCHY_NUM_PHASES] = {};
 };
@@ -49,19 +50,29 @@ struct mochy_ctx {
 enum Phase { kPhUpload = 0, kPhTranspose, kPhDegree, kPhRows, kPhRecords, kPhSched, kPhPairs,
              kPhCorrect, kPhDraw, kPhSample, kPhProfile };
 inline void phase_begin(mochy_ctx* c, int p) {
-  (void)hipEventRecord(c->ev[2 * p], c->stream);
+  if (hipEventRecord(c->ev[2 * p], c->stream) == hipSuccess) c->phases_begun |= 1u << p;
 }
 inline void phase_end(mochy_ctx* c, int p) {
-  (void)hipEventRecord(c->ev[2 * p + 1], c->stream);
-  c->phases_run |= 1u << p;
+  if (!(c->phases_begun & (1u << p))) return;
+  if (hipEventRecord(c->ev[2 * p + 1], c->stream) == hipSuccess) c->phases_run |= 1u << p;
 }
 // after the stream is synchronized: fold recorded phases into phase_ms
 void phases_collect(mochy_ctx* c);
 
+// A graph set: one hypergraph or a batch of them stored as a disjoint union
+// (graph g owns hyperedges [geoff[g], geoff[g+1]) and nodes [gvoff[g],
+// gvoff[g+1])); every line-graph row stays inside its graph.
 struct mochy_graph {
   mochy_ctx* ctx = nullptr;
-  int64_t E = 0, V = 0, nnz = 0, W = 0;  // hyperedges, nodes, incidences, hyperwedges
+  int64_t E = 0, V = 0, nnz = 0, W = 0;  // hyperedges, nodes, incidences, hyperwedges (all graphs)
   int32_t max_deg = 0;                   // max line-graph degree
+  int32_t ng = 1;                        // graphs in the set
+  std::vector<int64_t> h_geoff, h_gvoff, h_gnoff;  // host copies of the offsets
+  int64_t max_graph_edges = 0;           // largest graph (sizes the LDS row bitmaps)
+  int64_t* geoff = nullptr;              // [ng+1] device
+  int64_t* gvoff = nullptr;              // [ng+1] device
+  int64_t* gnoff = nullptr;              // [ng+1] device: incidence offsets
+  int32_t* row_graph = nullptr;          // [E] graph of each hyperedge
   int64_t* edge_ptr = nullptr;           // [E+1]
   int32_t* edge_nodes = nullptr;         // [nnz]
   int64_t* node_ptr = nullptr;           // [V+1]
@@ -101,9 +112,9 @@ size_t scan_tmp_elems(int64_t n);
 // project.hip
 mochy_status project_device(mochy_ctx* ctx, mochy_graph* g);
 
-// exact.hip
+// exact.hip: per-graph histograms d_hist[ng][kHistSlots], zeroed inside
 mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
-                          int64_t* d_hist /* kHistSlots, zeroed inside */);
+                          int64_t* d_hist);
 
 // correct.hip: exact fix-up of pairs that share a light node outside the centre
 mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
@@ -115,3 +126,6 @@ mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uin
 
 // api.hip helpers
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);
+
+// Largest graph (hyperedges) whose row bitmap and rank table fit in LDS.
+constexpr int64_t kMaxGraphEdges = 200000;

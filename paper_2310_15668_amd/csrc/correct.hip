@@ -88,20 +88,24 @@ __global__ __launch_bounds__(256) void k_light_pairs(
 }
 
 __global__ __launch_bounds__(256) void k_light_fix(
-    int64_t c0, int64_t c1, int nwE, const int32_t* __restrict__ owners,
+    int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
+    const int32_t* __restrict__ owners,
     const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
     const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint4* __restrict__ rec,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   extern __shared__ uint32_t sm[];
-  uint32_t* bm = sm;          // row j over hyperedge ids
-  uint32_t* rank = sm + nwE;  // set bits before each word
   __shared__ uint16_t lut[kNumCodes];
   __shared__ unsigned long long hist[kHistSlots];
   __shared__ int32_t part[256];
   __shared__ uint32_t hmask;
   const int32_t j = owners[blockIdx.x];
+  const int gj = row_graph[j];
+  const int64_t e0 = geoff[gj];  // row j's graph owns hyperedges [e0, geoff[gj + 1])
+  const int nwE = int((geoff[gj + 1] - e0 + 31) / 32);
+  uint32_t* bm = sm;          // row j over the graph's hyperedge ids
+  uint32_t* rank = sm + nwE;  // set bits before each word
   const int64_t jb = lg_ptr[j];
   const int dj = int(lg_ptr[j + 1] - jb);
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
@@ -116,7 +120,7 @@ __global__ __launch_bounds__(256) void k_light_fix(
   }
   __syncthreads();
   for (int p = threadIdx.x; p < dj; p += blockDim.x) {
-    const int32_t x = lg_col[jb + p];
+    const int64_t x = lg_col[jb + p] - e0;
     atomicOr(&bm[x >> 5], 1u << (x & 31));
   }
   __syncthreads();
@@ -146,8 +150,9 @@ __global__ __launch_bounds__(256) void k_light_fix(
   for (int64_t pp = poff[blockIdx.x]; pp < poff[blockIdx.x + 1]; ++pp) {
     const int32_t k = partners[pp];
     // record of e_k in row j
-    const uint32_t kw = bm[k >> 5];
-    const int qk = int(rank[k >> 5] + __popc(kw & ((1u << (k & 31)) - 1u)));
+    const int64_t kl = k - e0;
+    const uint32_t kw = bm[kl >> 5];
+    const int qk = int(rank[kl >> 5] + __popc(kw & ((1u << (kl & 31)) - 1u)));
     const uint32_t mjk = rec[jb + qk].x;
     const int64_t kb = lg_ptr[k];
     const int dk = int(lg_ptr[k + 1] - kb);
@@ -155,10 +160,11 @@ __global__ __launch_bounds__(256) void k_light_fix(
     for (int r = threadIdx.x; r < dk; r += blockDim.x) {
       const int32_t i = lg_col[kb + r];
       if (i < c0 || i >= c1) continue;
-      const uint32_t iw = bm[i >> 5];
-      const uint32_t ibit = 1u << (i & 31);
+      const int64_t il = i - e0;
+      const uint32_t iw = bm[il >> 5];
+      const uint32_t ibit = 1u << (il & 31);
       if (!(iw & ibit)) continue;  // not a neighbour of e_j (or i == j)
-      const uint32_t mji = rec[jb + int(rank[i >> 5] + __popc(iw & (ibit - 1u)))].x;
+      const uint32_t mji = rec[jb + int(rank[il >> 5] + __popc(iw & (ibit - 1u)))].x;
       const uint32_t ls = __popc(mjk & L & ~mji);
       if (ls == 0u) continue;  // the pair kernel was exact at this centre
       const uint32_t wik = __popc(rec[kb + r].x);
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(256) void k_light_fix(
   }
   __syncthreads();
   for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x)
-    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
+    if (hist[t]) atomicAdd(&hist_out[int64_t(gj) * kHistSlots + t], hist[t]);
 }
 
 // owners: hyperedges with at least one light partner, compacted.
@@ -204,7 +210,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   hipStream_t st = ctx->stream;
   const int64_t E = g->E, V = g->V;
   if (c1 <= c0 || E == 0 || V == 0) return MOCHY_OK;
-  const int nwE = int((E + 31) / 32);
+  const int nwE = int((g->max_graph_edges + 31) / 32);
   const size_t dyn = size_t(nwE) * 8;
   if (dyn > 60 * 1024)
     MOCHY_HIP(hipFuncSetAttribute((const void*)k_light_fix, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -251,7 +257,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);
-  k_light_fix<<<unsigned(nowners), 256, dyn, st>>>(c0, c1, nwE, owners, poff, partners, g->edge_ptr,
+  k_light_fix<<<unsigned(nowners), 256, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners, g->edge_ptr,
                                                    g->edge_nodes, g->heavy_bit, g->lg_ptr, g->lg_col,
                                                    g->rec, ctx->d_code_to_id3,
                                                    (unsigned long long*)d_hist);

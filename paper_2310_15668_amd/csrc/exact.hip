@@ -33,28 +33,39 @@
 
 namespace {
 
-constexpr int kCopies = 4;
-constexpr int kStride = kHistSlots + 1;  // odd stride spreads the copies over banks
+constexpr int kCopies = 4;                 // histogram copies per wave (picked by lane)
+constexpr int kStride = kHistSlots + 1;    // odd stride spreads the copies over banks
+constexpr int kWavesPerGroup = 4;
+constexpr int64_t kFlushVisits = int64_t(1) << 27;  // 16 lanes share a copy: counters < 2^32
 
 // ---------------------------------------------------------------------------
-// Scheduling: rows sorted by number of 64-blocks, descending.
+// Scheduling, graph-major: the items of graph 0 come first, then graph 1, ...;
+// inside a graph, rows are sorted by number of 64-blocks (descending) and
+// items by block index (descending), so the largest items start first.
+// Per graph g, with NB = maxnb + 1 slots:
+//   cnt[g][b]        rows of g with more than b blocks (cnt[g][maxnb] = 0)
+//   item_start[g][b] items of g with a larger block index
+//   gq[g]            items of graphs before g;  seg[g] its rows' slot in `order`
 
-__global__ void k_sched_count(int64_t c0, int64_t c1, const int64_t* __restrict__ lg_ptr,
-                              unsigned long long* nbhist) {
+__global__ void k_sched_count(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
+                              const int32_t* __restrict__ row_graph, unsigned long long* nbhist) {
   const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= c1) return;
   const int64_t d = lg_ptr[i + 1] - lg_ptr[i];
   if (d < 2) return;
-  atomicAdd(&nbhist[(d + kWave - 1) / kWave], 1ull);
+  atomicAdd(&nbhist[int64_t(row_graph[i]) * NB + (d + kWave - 1) / kWave], 1ull);
 }
 
-// Single block: cnt[b] = #rows with more than b blocks; item_start[b] =
-// number of items with a larger block index; total = sum_b cnt[b].
+// One block per graph.
 __global__ __launch_bounds__(1024) void k_sched_scan(int32_t maxnb,
-                                                     const unsigned long long* __restrict__ nbhist,
-                                                     int64_t* cnt, int64_t* item_start,
+                                                     const unsigned long long* __restrict__ nbhist_all,
+                                                     int64_t* cnt_all, int64_t* item_start_all,
                                                      int64_t* total) {
   __shared__ int64_t part[1024];
+  const int64_t NB = maxnb + 1;
+  const unsigned long long* nbhist = nbhist_all + blockIdx.x * NB;
+  int64_t* cnt = cnt_all + blockIdx.x * NB;
+  int64_t* item_start = item_start_all + blockIdx.x * NB;
   const int n = maxnb;  // entries b = 0..maxnb-1; cnt[maxnb] = 0
   const int chunk = (n + 1023) / 1024;
   // suffix sums computed as prefix sums over the reversed index r = n-1-b
@@ -97,20 +108,51 @@ __global__ __launch_bounds__(1024) void k_sched_scan(int32_t maxnb,
       item_start[n - 1 - r] = run;
       run += cnt[n - 1 - r];
     }
-    if (threadIdx.x == 1023) *total = part[1023];
+    if (threadIdx.x == 1023) total[blockIdx.x] = part[1023];
   }
 }
 
-__global__ void k_sched_scatter(int64_t c0, int64_t c1, const int64_t* __restrict__ lg_ptr,
-                                const int64_t* __restrict__ cnt, unsigned long long* fill,
-                                int32_t* order) {
+// Single block: gq = exclusive prefix of the per-graph item totals (gq[ng] =
+// all items), seg[g] = first slot of graph g's rows in `order`.
+__global__ __launch_bounds__(1024) void k_sched_graphs(int32_t ng, int64_t c0, int64_t c1,
+                                                       const int64_t* __restrict__ geoff,
+                                                       const int64_t* __restrict__ total,
+                                                       int64_t* gq, int64_t* seg) {
+  __shared__ int64_t part[1024];
+  const int chunk = (ng + 1023) / 1024;
+  const int g0 = min(ng, int(threadIdx.x) * chunk), g1 = min(ng, g0 + chunk);
+  int64_t s = 0;
+  for (int g = g0; g < g1; ++g) s += total[g];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int g = g0; g < g1; ++g) {
+    gq[g] = run;
+    run += total[g];
+    const int64_t lo = geoff[g] < c0 ? c0 : (geoff[g] > c1 ? c1 : geoff[g]);
+    seg[g] = lo - c0;
+  }
+  if (threadIdx.x == 1023) gq[ng] = part[1023];
+}
+
+__global__ void k_sched_scatter(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
+                                const int32_t* __restrict__ row_graph,
+                                const int64_t* __restrict__ cnt, const int64_t* __restrict__ seg,
+                                unsigned long long* fill, int32_t* order) {
   const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= c1) return;
   const int64_t d = lg_ptr[i + 1] - lg_ptr[i];
   if (d < 2) return;
+  const int64_t g = row_graph[i];
   const int64_t nb = (d + kWave - 1) / kWave;
-  const unsigned long long slot = atomicAdd(&fill[nb], 1ull);
-  order[cnt[nb] + int64_t(slot)] = int32_t(i);
+  const unsigned long long slot = atomicAdd(&fill[g * NB + nb], 1ull);
+  order[seg[g] + cnt[g * NB + nb] + int64_t(slot)] = int32_t(i);
 }
 
 // Walk j over [j0, j1) against the lane's k.  kCountAll: both j and k are
@@ -119,7 +161,7 @@ __global__ void k_sched_scatter(int64_t c0, int64_t c1, const int64_t* __restric
 template <bool kCountAll, bool kDiag>
 __device__ __forceinline__ void walk(const uint4* __restrict__ row, int j0, int j1, uint32_t a,
                                      const Side& k, int kp, bool valid,
-                                     const uint16_t* __restrict__ lut, unsigned long long* hist) {
+                                     const uint16_t* __restrict__ lut, uint32_t* hist) {
   for (int j = j0; j < j1; ++j) {
     const uint4 rj = row[j];
     const uint32_t mj = rj.x;
@@ -133,36 +175,67 @@ __device__ __forceinline__ void walk(const uint4* __restrict__ row, int j0, int 
     if (act) {
       const uint32_t pj = __popc(mj);
       const uint32_t code = pair_code(a, pj, oj, k, t, r5);
-      atomicAdd(&hist[lut[code]], 1ull);
+      atomicAdd(&hist[lut[code]], 1u);
     }
   }
+}
+
+// Adds a wave's histogram copies into graph g's global counts and clears them.
+__device__ __forceinline__ void flush_wave(uint32_t* whist, int lane, int64_t g,
+                                           unsigned long long* hist_out) {
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < kHistSlots; t += kWave) {
+    unsigned long long s = 0;
+    for (int c = 0; c < kCopies; ++c) {
+      s += whist[c * kStride + t];
+      whist[c * kStride + t] = 0u;
+    }
+    if (s) atomicAdd(&hist_out[g * kHistSlots + t], s);
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 __global__ __launch_bounds__(256) void k_exact_main(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ up_first, const uint4* __restrict__ rec,
     const int32_t* __restrict__ order, const int64_t* __restrict__ item_start,
-    const int64_t* __restrict__ cnt, int32_t maxnb, const int64_t* __restrict__ total_items,
-    unsigned long long* queue, const uint16_t* __restrict__ code_to_id3,
-    unsigned long long* hist_out) {
+    const int64_t* __restrict__ cnt, int32_t maxnb, const int64_t* __restrict__ gq,
+    const int64_t* __restrict__ seg, int32_t ng, unsigned long long* queue,
+    const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   __shared__ uint16_t lut[kNumCodes];
-  __shared__ unsigned long long hist[kCopies * kStride];
+  __shared__ uint32_t hist[kWavesPerGroup * kCopies * kStride];
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
-  for (int t = threadIdx.x; t < kCopies * kStride; t += blockDim.x) hist[t] = 0;
+  for (int t = threadIdx.x; t < kWavesPerGroup * kCopies * kStride; t += blockDim.x) hist[t] = 0u;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long* myhist = hist + (lane & (kCopies - 1)) * kStride;
-  const int64_t total = total_items[0];
-  int b = maxnb - 1;
+  const int wave = threadIdx.x / kWave;
+  uint32_t* whist = hist + wave * (kCopies * kStride);
+  uint32_t* myhist = whist + (lane & (kCopies - 1)) * kStride;
+  const int64_t NB = maxnb + 1;
+  const int64_t total = gq[ng];
+  int g = 0, b = maxnb - 1, dirty_g = -1;
+  int64_t visits = 0;
   for (;;) {
     unsigned long long qq = 0;
     if (lane == 0) qq = atomicAdd(queue, 1ull);
     const int64_t q = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(int(qq >> 32)) << 32) |
                                 (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(int(qq)));
     if (q >= total) break;
-    // items are ordered by block index descending; q only grows per wave
-    while (b > 0 && q >= item_start[b] + cnt[b]) --b;
-    const int32_t i = order[q - item_start[b]];
+    // items are graph-major; q only grows per wave
+    while (q >= gq[g + 1]) {
+      ++g;
+      b = maxnb - 1;
+    }
+    if (dirty_g >= 0 && (dirty_g != g || visits > kFlushVisits)) {
+      flush_wave(whist, lane, dirty_g, hist_out);
+      visits = 0;
+    }
+    dirty_g = g;
+    const int64_t ql = q - gq[g];
+    const int64_t* cg = cnt + g * NB;
+    const int64_t* sg = item_start + g * NB;
+    while (b > 0 && ql >= sg[b] + cg[b]) --b;
+    const int32_t i = order[seg[g] + ql - sg[b]];
     const int64_t base = lg_ptr[i];
     const int d = int(lg_ptr[i + 1] - base);
     const int u = up_first[i];
@@ -180,6 +253,7 @@ __global__ __launch_bounds__(256) void k_exact_main(
     }
     const int blo = b * kWave;
     const int kmax = min(blo + kWave, d);
+    visits += int64_t(kmax);
     // j below the centre: count disjoint pairs only
     const int ua = min(u, blo);
     walk<false, false>(row, 0, ua, a, k, kp, valid, lut, myhist);
@@ -188,12 +262,7 @@ __global__ __launch_bounds__(256) void k_exact_main(
     walk<true, false>(row, u, blo, a, k, kp, valid, lut, myhist);
     walk<true, true>(row, max(u, blo), kmax, a, k, kp, valid, lut, myhist);
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) {
-    unsigned long long s = 0;
-    for (int c = 0; c < kCopies; ++c) s += hist[c * kStride + t];
-    if (s) atomicAdd(&hist_out[t], s);
-  }
+  if (dirty_g >= 0) flush_wave(whist, lane, dirty_g, hist_out);
 }
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -203,33 +272,39 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                           int64_t* d_hist) {
   hipStream_t st = ctx->stream;
-  MOCHY_HIP(hipMemsetAsync(d_hist, 0, kHistSlots * 8, st));
+  const int ng = g->ng;
+  MOCHY_HIP(hipMemsetAsync(d_hist, 0, size_t(ng) * kHistSlots * 8, st));
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
   const int32_t maxnb = (g->max_deg + kWave - 1) / kWave;
-  // scratch: nbhist[maxnb+1], cnt[maxnb+1], item_start[maxnb], fill[maxnb+1], total, queue, order[E]
-  const size_t n8 = size_t(maxnb + 1) * 4 + 4;
-  const size_t bytes = n8 * 8 + size_t(c1 - c0) * 4;
+  const int64_t NB = maxnb + 1;
+  const int64_t rows = c1 - c0;
+  // scratch (8-byte slots): nbhist, cnt, item_start, fill [ng*NB each], total [ng],
+  // gq [ng+1], seg [ng], queue [1]; then order [rows] int32
+  const size_t n8 = size_t(ng) * NB * 4 + size_t(ng) * 3 + 2;
   char* scratch = nullptr;
-  mochy_status rc = device_alloc(ctx, (void**)&scratch, bytes);
+  mochy_status rc = device_alloc(ctx, (void**)&scratch, n8 * 8 + size_t(rows) * 4);
   if (rc != MOCHY_OK) return rc;
   unsigned long long* nbhist = (unsigned long long*)scratch;
-  int64_t* cnt = (int64_t*)(nbhist + (maxnb + 1));
-  int64_t* item_start = cnt + (maxnb + 1);
-  unsigned long long* fill = (unsigned long long*)(item_start + (maxnb + 1));
-  int64_t* total = (int64_t*)(fill + (maxnb + 1));
-  unsigned long long* queue = (unsigned long long*)(total + 1);
+  int64_t* cnt = (int64_t*)(nbhist + ng * NB);
+  int64_t* item_start = cnt + ng * NB;
+  unsigned long long* fill = (unsigned long long*)(item_start + ng * NB);
+  int64_t* total = (int64_t*)(fill + ng * NB);
+  int64_t* gq = total + ng;
+  int64_t* seg = gq + (ng + 1);
+  unsigned long long* queue = (unsigned long long*)(seg + ng);
   int32_t* order = (int32_t*)(scratch + n8 * 8);
   phase_begin(ctx, kPhSched);
   MOCHY_HIP(hipMemsetAsync(scratch, 0, n8 * 8, st));
-  const int64_t rows = c1 - c0;
-  k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, g->lg_ptr, nbhist);
-  k_sched_scan<<<1, 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
-  k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, g->lg_ptr, cnt, fill, order);
+  k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, nbhist);
+  k_sched_scan<<<unsigned(ng), 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
+  k_sched_graphs<<<1, 1024, 0, st>>>(ng, c0, c1, g->geoff, total, gq, seg);
+  k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, cnt,
+                                                     seg, fill, order);
   phase_end(ctx, kPhSched);
   const unsigned grid = unsigned(ctx->num_cus) * 8u;
   phase_begin(ctx, kPhPairs);
   k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, order, item_start,
-                                     cnt, maxnb, total, queue, ctx->d_code_to_id3,
+                                     cnt, maxnb, gq, seg, ng, queue, ctx->d_code_to_id3,
                                      (unsigned long long*)d_hist);
   phase_end(ctx, kPhPairs);
   phase_begin(ctx, kPhCorrect);

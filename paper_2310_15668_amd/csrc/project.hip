@@ -18,17 +18,27 @@
 
 namespace {
 
-__global__ void k_validate(int64_t E, int64_t V, int64_t nnz, const int64_t* __restrict__ ptr,
-                           const int32_t* __restrict__ nodes, int32_t* flags) {
+// Each hyperedge is checked against its own graph: incidences inside the
+// graph's slice, node ids inside the graph's node range, strictly ascending.
+__global__ void k_validate(int64_t E, int32_t ng, const int64_t* __restrict__ geoff,
+                           const int64_t* __restrict__ gvoff, const int64_t* __restrict__ gnoff,
+                           const int64_t* __restrict__ ptr, const int32_t* __restrict__ nodes,
+                           int32_t* flags) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= E) return;
+  int lo = 0, hi = ng;  // last graph with geoff[g] <= e
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (geoff[mid] <= e) lo = mid; else hi = mid;
+  }
   const int64_t s = ptr[e], t = ptr[e + 1];
-  if (s < 0 || t > nnz || t <= s) { atomicOr(flags, kFlagInval); return; }
+  if (s < gnoff[lo] || t > gnoff[lo + 1] || t <= s) { atomicOr(flags, kFlagInval); return; }
   if (t - s > MOCHY_MAX_EDGE) { atomicOr(flags, kFlagRange); return; }
-  int32_t prev = -1;
+  const int64_t v0 = gvoff[lo], v1 = gvoff[lo + 1];
+  int64_t prev = v0 - 1;
   for (int64_t q = s; q < t; ++q) {
-    const int32_t v = nodes[q];
-    if (v < 0 || int64_t(v) >= V || v <= prev) { atomicOr(flags, kFlagInval); return; }
+    const int64_t v = nodes[q];
+    if (v < v0 || v >= v1 || v <= prev) { atomicOr(flags, kFlagInval); return; }
     prev = v;
   }
 }
@@ -51,15 +61,18 @@ __global__ void k_node_fill(int64_t E, const int64_t* __restrict__ ptr,
   }
 }
 
-// One block of 1024 threads: 64 rounds of "largest degree not yet taken".
-__global__ __launch_bounds__(1024) void k_heavy(int64_t V, const int64_t* __restrict__ node_ptr,
+// One block of 1024 threads per graph: 64 rounds of "largest degree not yet
+// taken" over the graph's nodes.
+__global__ __launch_bounds__(1024) void k_heavy(const int64_t* __restrict__ gvoff,
+                                                const int64_t* __restrict__ node_ptr,
                                                 int8_t* heavy_bit) {
   __shared__ unsigned long long best[1024];
-  for (int64_t v = threadIdx.x; v < V; v += 1024) heavy_bit[v] = -1;
+  const int64_t v0 = gvoff[blockIdx.x], v1 = gvoff[blockIdx.x + 1];
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += 1024) heavy_bit[v] = -1;
   __syncthreads();
   for (int round = 0; round < kHeavyBits; ++round) {
     unsigned long long mine = 0;
-    for (int64_t v = threadIdx.x; v < V; v += 1024) {
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += 1024) {
       if (heavy_bit[v] >= 0) continue;
       const unsigned long long deg = (unsigned long long)(node_ptr[v + 1] - node_ptr[v]);
       const unsigned long long key = (deg << 32) | (0xffffffffull - (unsigned long long)v);
@@ -80,8 +93,9 @@ __global__ __launch_bounds__(1024) void k_heavy(int64_t V, const int64_t* __rest
   }
 }
 
-// Builds the neighbour bitmap of row i in LDS (nwords 32-bit words).
-__device__ void build_row_bitmap(int64_t i, const int64_t* __restrict__ ptr,
+// Builds the neighbour bitmap of row i in LDS: bit x - e0 for neighbour x,
+// where the row's graph owns hyperedges [e0, e0 + 32 * nwords).
+__device__ void build_row_bitmap(int64_t i, int64_t e0, const int64_t* __restrict__ ptr,
                                  const int32_t* __restrict__ nodes,
                                  const int64_t* __restrict__ node_ptr,
                                  const int32_t* __restrict__ node_edges, uint32_t* bm, int nwords) {
@@ -91,22 +105,35 @@ __device__ void build_row_bitmap(int64_t i, const int64_t* __restrict__ ptr,
     const int32_t v = nodes[q];
     const int64_t lo = node_ptr[v], hi = node_ptr[v + 1];
     for (int64_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
-      const int32_t x = node_edges[r];
-      if (x != i) atomicOr(&bm[x >> 5], 1u << (x & 31));
+      const int64_t x = node_edges[r];
+      if (x != i) atomicOr(&bm[(x - e0) >> 5], 1u << ((x - e0) & 31));
     }
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void graph_range(int64_t i, const int32_t* __restrict__ row_graph,
+                                            const int64_t* __restrict__ geoff, int64_t& e0,
+                                            int& nwords) {
+  const int gi = row_graph[i];
+  e0 = geoff[gi];
+  nwords = int((geoff[gi + 1] - e0 + 31) / 32);
 }
 
 __global__ __launch_bounds__(256) void k_proj_degree(int64_t E, const int64_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ nodes,
                                                      const int64_t* __restrict__ node_ptr,
                                                      const int32_t* __restrict__ node_edges,
-                                                     int nwords, int64_t* deg, int32_t* max_deg) {
+                                                     const int32_t* __restrict__ row_graph,
+                                                     const int64_t* __restrict__ geoff,
+                                                     int64_t* deg, int32_t* max_deg) {
   extern __shared__ uint32_t bm[];
   __shared__ int32_t red[256];
   const int64_t i = blockIdx.x;
-  build_row_bitmap(i, ptr, nodes, node_ptr, node_edges, bm, nwords);
+  int64_t e0;
+  int nwords;
+  graph_range(i, row_graph, geoff, e0, nwords);
+  build_row_bitmap(i, e0, ptr, nodes, node_ptr, node_edges, bm, nwords);
   int32_t c = 0;
   for (int w = threadIdx.x; w < nwords; w += blockDim.x) c += __popc(bm[w]);
   red[threadIdx.x] = c;
@@ -125,12 +152,17 @@ __global__ __launch_bounds__(256) void k_proj_fill(int64_t E, const int64_t* __r
                                                    const int32_t* __restrict__ nodes,
                                                    const int64_t* __restrict__ node_ptr,
                                                    const int32_t* __restrict__ node_edges,
-                                                   int nwords, const int64_t* __restrict__ lg_ptr,
+                                                   const int32_t* __restrict__ row_graph,
+                                                   const int64_t* __restrict__ geoff,
+                                                   const int64_t* __restrict__ lg_ptr,
                                                    int32_t* lg_col, int32_t* up_first) {
   extern __shared__ uint32_t bm[];
   __shared__ int32_t part[256];
   const int64_t i = blockIdx.x;
-  build_row_bitmap(i, ptr, nodes, node_ptr, node_edges, bm, nwords);
+  int64_t e0;
+  int nwords;
+  graph_range(i, row_graph, geoff, e0, nwords);
+  build_row_bitmap(i, e0, ptr, nodes, node_ptr, node_edges, bm, nwords);
   // each thread owns a contiguous chunk of words
   const int chunk = (nwords + 255) / 256;
   const int w0 = min(nwords, int(threadIdx.x) * chunk), w1 = min(nwords, w0 + chunk);
@@ -146,14 +178,15 @@ __global__ __launch_bounds__(256) void k_proj_fill(int64_t E, const int64_t* __r
   }
   int32_t pos = part[threadIdx.x] - c;  // exclusive
   int32_t* out = lg_col + lg_ptr[i];
-  const int wi = int(i >> 5);
+  const int64_t il = i - e0;
+  const int wi = int(il >> 5);
   for (int w = w0; w < w1; ++w) {
     uint32_t bits = bm[w];
-    if (w == wi) up_first[i] = pos + __popc(bits & ((1u << (i & 31)) - 1u));
+    if (w == wi) up_first[i] = pos + __popc(bits & ((1u << (il & 31)) - 1u));
     while (bits) {
       const int b = __ffs(bits) - 1;
       bits &= bits - 1;
-      out[pos++] = (w << 5) | b;
+      out[pos++] = int32_t(e0 + ((w << 5) | b));
     }
   }
 }
@@ -203,23 +236,33 @@ __global__ void k_upper_len(int64_t E, const int64_t* __restrict__ lg_ptr,
   if (i == E) up_len[E] = 0;
 }
 
+__global__ void k_row_graph(int64_t E, int32_t ng, const int64_t* __restrict__ geoff,
+                            int32_t* row_graph) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  int lo = 0, hi = ng;  // last g with geoff[g] <= i
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (geoff[mid] <= i) lo = mid; else hi = mid;
+  }
+  row_graph[i] = lo;
+}
+
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 }  // namespace
 
-// Largest hyperedge count whose row bitmap (and rank table) fits in LDS.
-constexpr int64_t kMaxEdgesBitmap = 400000;
-
 mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E, V = g->V, nnz = g->nnz;
-  if (E > kMaxEdgesBitmap) {
-    ctx->err = "hypergraphs above 400000 hyperedges need the line-graph-free mode, not in this build";
+  if (g->max_graph_edges > kMaxGraphEdges) {
+    ctx->err = "hypergraphs above 200000 hyperedges need the line-graph-free mode, not in this build";
     return MOCHY_EUNSUPPORTED;
   }
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int32_t), st));
   if (E > 0)
-    k_validate<<<blocks(E, 256), 256, 0, st>>>(E, V, nnz, g->edge_ptr, g->edge_nodes, ctx->d_flags);
+    k_validate<<<blocks(E, 256), 256, 0, st>>>(E, g->ng, g->geoff, g->gvoff, g->gnoff, g->edge_ptr,
+                                               g->edge_nodes, ctx->d_flags);
   phase_end(ctx, kPhUpload);
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
@@ -244,6 +287,8 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   if ((rc = device_alloc(ctx, (void**)&g->lg_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->up_first, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->up_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->row_graph, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
+  if (E > 0) k_row_graph<<<blocks(E, 256), 256, 0, st>>>(E, g->ng, g->geoff, g->row_graph);
   g->bytes += size_t(V + 1) * 8 + size_t(nnz) * 4 + size_t(V) + size_t(E + 1) * 16 + size_t(E) * 4;
 
   phase_begin(ctx, kPhTranspose);
@@ -256,18 +301,19 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
     k_node_fill<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr, fill,
                                                 g->node_edges);
   // 3. heavy nodes
-  if (V > 0) k_heavy<<<1, 1024, 0, st>>>(V, g->node_ptr, g->heavy_bit);
+  if (V > 0) k_heavy<<<unsigned(g->ng), 1024, 0, st>>>(g->gvoff, g->node_ptr, g->heavy_bit);
   phase_end(ctx, kPhTranspose);
 
   // 4-5. degrees and row pointers
-  const int nwords = int((E + 31) / 32);
+  const int nwords = int((g->max_graph_edges + 31) / 32);
   const size_t bm_bytes = size_t(std::max(nwords, 1)) * 4;
   phase_begin(ctx, kPhDegree);
   MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(E + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 1, 0, sizeof(int32_t), st));
   if (E > 0)
     k_proj_degree<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
-                                                      g->node_edges, nwords, cnt, ctx->d_flags + 1);
+                                                      g->node_edges, g->row_graph, g->geoff, cnt,
+                                                      ctx->d_flags + 1);
   launch_exclusive_scan_i64(cnt, g->lg_ptr, E + 1, tmp, st);
   phase_end(ctx, kPhDegree);
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + E, 8, hipMemcpyDeviceToHost, st));
@@ -285,8 +331,8 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   phase_begin(ctx, kPhRows);
   if (E > 0)
     k_proj_fill<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
-                                                    g->node_edges, nwords, g->lg_ptr, g->lg_col,
-                                                    g->up_first);
+                                                    g->node_edges, g->row_graph, g->geoff, g->lg_ptr,
+                                                    g->lg_col, g->up_first);
   phase_end(ctx, kPhRows);
   // 7. records
   phase_begin(ctx, kPhRecords);

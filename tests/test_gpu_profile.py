@@ -1,0 +1,117 @@
+"""GPU parity of significance / characteristic profile (Eq. 1, Eq. 2) and of the
+batched count of a hypergraph with its randomized copies.
+
+Counts: bit-exact (int64) against the oracle and against one-graph-at-a-time
+launches.  Significance and CP: within 1e-12 relative of the float64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import cp, native
+from workloads import from_edge_lists, make_config, powerlaw_hypergraph, stub_matching_copy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2310_15668_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def run_profile(ctx, graphs, eps=1.0):
+    import paper_2310_15668_amd as M
+    print(f"[gpu] profile of {len(graphs)} graphs, |E| = {[h.num_edges for h in graphs][:6]}...", flush=True)
+    return M.mochy_profile(ctx, [(h.edge_ptr, h.edge_nodes, h.num_nodes) for h in graphs], eps)
+
+
+def sequential(ctx, graphs):
+    import paper_2310_15668_amd as M
+    out = []
+    for h in graphs:
+        g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+        c26, c431 = M.mochy_count_exact(ctx, g)
+        g.close()
+        out.append(np.concatenate([c26, c431]))
+    return np.array(out)
+
+
+def check_cp(counts, sig26, cp26, sig431, cp431, eps=1.0):
+    for lo, hi, sig, prof in ((0, 26, sig26, cp26), (26, 457, sig431, cp431)):
+        M = counts[0, lo:hi].tolist()
+        rand = [row[lo:hi].tolist() for row in counts[1:]]
+        d = cp.significance(M, rand, eps)
+        c = cp.characteristic_profile(d)
+        np.testing.assert_allclose(sig, d, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(prof, c, rtol=1e-12, atol=1e-300)
+
+
+def test_tiny_with_copies_matches_oracle(ctx):
+    base = make_config("tiny")
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 108)]
+    counts, sig26, cp26, sig431, cp431 = run_profile(ctx, graphs)
+    for k, h in enumerate(graphs):
+        r26, r431, _ = native.mochy_e(h, nthreads=8)
+        assert (counts[k, :26] == r26).all() and (counts[k, 26:] == r431).all(), k
+    check_cp(counts, sig26, cp26, sig431, cp431)
+    assert abs(float(np.sum(cp26 ** 2)) - 1.0) < 1e-12
+
+
+def test_batched_equals_sequential(ctx):
+    base = powerlaw_hypergraph(1500, 6000, 2, 12, 2.5, 1.1, seed=3)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 116)]
+    counts, *_ = run_profile(ctx, graphs)
+    seq = sequential(ctx, graphs)
+    assert (counts == seq).all()
+    sizes = {h.num_edges for h in graphs}
+    assert len(sizes) > 1  # uneven sizes after collapsing repeated members
+
+
+def test_uneven_and_degenerate_members(ctx):
+    graphs = [make_config("tiny"), from_edge_lists([[0, 1], [2, 3]], 4),
+              from_edge_lists([[0, 1], [1, 2], [2, 0]], 3), make_config("tiny", scale=0.5)]
+    counts, sig26, cp26, sig431, cp431 = run_profile(ctx, graphs, eps=0.5)
+    assert (counts == sequential(ctx, graphs)).all()
+    check_cp(counts, sig26, cp26, sig431, cp431, eps=0.5)
+
+
+def test_device_inputs(ctx):
+    import torch
+    import paper_2310_15668_amd as M
+    base = make_config("tiny")
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 104)]
+    dev = [(torch.from_numpy(h.edge_ptr).cuda(), torch.from_numpy(h.edge_nodes).cuda(), h.num_nodes)
+           for h in graphs]
+    torch.cuda.synchronize()
+    print("[gpu] profile from device-resident CSRs", flush=True)
+    a = M.mochy_profile(ctx, dev)
+    b = run_profile(ctx, graphs)
+    for x, y in zip(a, b):
+        assert (x == y).all()
+    # a node id outside its own graph's range is rejected even though the
+    # shifted id would land inside the union
+    bad_p = torch.tensor([0, 2], dtype=torch.int64, device="cuda")
+    bad_n = torch.tensor([0, 7], dtype=torch.int32, device="cuda")
+    with pytest.raises(M.MochyError) as e:
+        M.mochy_profile(ctx, [dev[0], (bad_p, bad_n, 3), dev[1]])
+    assert e.value.status == -1
+
+
+def test_scaled_batched_config(ctx):
+    # the batched CP workload at 5% scale: base + 64 copies in one batch
+    base = make_config("batched_base", scale=0.05)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 164)]
+    counts, sig26, cp26, sig431, cp431 = run_profile(ctx, graphs)
+    assert (counts == sequential(ctx, graphs)).all()
+    check_cp(counts, sig26, cp26, sig431, cp431)
+
+
+def test_small_batched_config_against_oracle(ctx):
+    base = make_config("batched_base", scale=0.02)
+    graphs = [base] + [stub_matching_copy(base, s) for s in (100, 101)]
+    counts, *_ = run_profile(ctx, graphs)
+    for k, h in enumerate(graphs):
+        r26, r431, _ = native.mochy_e(h, nthreads=16)
+        assert (counts[k, 26:] == r431).all(), k
