@@ -26,12 +26,53 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "exact.hip")
+COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_main_medium_counters.md")
 WORKLOAD = ("medium exact MoCHy-E: 20000 nodes, 100000 drawn hyperedges (duplicates removed), "
             "sizes 2..25 P(s)~s^-2.5, Zipf(1.0) node popularity, seed 1")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter
+    summary, or None if there is none or the kernel source changed since."""
+    if not os.path.exists(COUNTERS_SUMMARY):
+        return None
+    vals = {}
+    with open(COUNTERS_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != source_digest(PAIR_KERNEL_SRC):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, for scaling the byte counters."""
+    import torch
+    n = 1 << 30
+    src = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
 def cpu_baseline(h, seconds):
@@ -69,16 +110,22 @@ def cpu_baseline(h, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build counts motifs on one device "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -148,7 +195,7 @@ def main():
                    "connected_triples": triples, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_exact_main (MoCHy-E pair enumeration)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "model": "8 + 4*min(|e_i|,|e_j|,|e_k|) bytes per MoCHy-E candidate",
                      "kernel_ms": pair_ms, "candidates_per_s": st["candidates"] / (pair_ms * 1e-3)},
         "phases_ms": {k: v / K for k, v in phase_sum.items() if v},

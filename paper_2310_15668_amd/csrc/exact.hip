@@ -33,19 +33,22 @@
 
 namespace {
 
-constexpr int kCopies = 4;                 // histogram copies per wave (picked by lane)
+constexpr int kCopies = 2;                 // histogram copies per wave (picked by lane)
 constexpr int kStride = kHistSlots + 1;    // odd stride spreads the copies over banks
 constexpr int kWavesPerGroup = 4;
-constexpr int64_t kFlushVisits = int64_t(1) << 27;  // 16 lanes share a copy: counters < 2^32
+constexpr int64_t kFlushVisits = int64_t(1) << 26;  // 32 lanes share a copy: counters < 2^32
 
 // ---------------------------------------------------------------------------
-// Scheduling, graph-major: the items of graph 0 come first, then graph 1, ...;
-// inside a graph, rows are sorted by number of 64-blocks (descending) and
-// items by block index (descending), so the largest items start first.
-// Per graph g, with NB = maxnb + 1 slots:
-//   cnt[g][b]        rows of g with more than b blocks (cnt[g][maxnb] = 0)
-//   item_start[g][b] items of g with a larger block index
-//   gq[g]            items of graphs before g;  seg[g] its rows' slot in `order`
+// Scheduling, graph-major: the rows of graph 0 come first, then graph 1, ...;
+// inside a graph, rows are sorted by number of 64-blocks (descending) and a
+// row's items (its blocks, largest block index first) are consecutive, so
+// big work starts first and the waves working on one row share its records
+// in L2.  Per graph g, with NB = maxnb + 1 slots:
+//   cnt[g][b]   rows of g with more than b blocks (cnt[g][maxnb] = 0), i.e.
+//               the first slot of g's rows with b+... blocks in `order`
+//   seg[g]      first slot of graph g's rows in `order`
+// `order` lists rows (-1 in unused slots); rstart = prefix sums of the rows'
+// block counts, so item q is block (nb - 1 - (q - rstart[k])) of row order[k].
 
 __global__ void k_sched_count(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
                               const int32_t* __restrict__ row_graph, unsigned long long* nbhist) {
@@ -141,6 +144,19 @@ __global__ __launch_bounds__(1024) void k_sched_graphs(int32_t ng, int64_t c0, i
   if (threadIdx.x == 1023) gq[ng] = part[1023];
 }
 
+// Blocks per slot of `order` (0 for unused slots), the input of rstart.
+__global__ void k_item_counts(int64_t n, const int32_t* __restrict__ order,
+                              const int64_t* __restrict__ lg_ptr, int64_t* nbk) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k > n) return;
+  int64_t v = 0;
+  if (k < n && order[k] >= 0) {
+    const int32_t i = order[k];
+    v = (lg_ptr[i + 1] - lg_ptr[i] + kWave - 1) / kWave;
+  }
+  nbk[k] = v;
+}
+
 __global__ void k_sched_scatter(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
                                 const int32_t* __restrict__ row_graph,
                                 const int64_t* __restrict__ cnt, const int64_t* __restrict__ seg,
@@ -198,9 +214,8 @@ __device__ __forceinline__ void flush_wave(uint32_t* whist, int lane, int64_t g,
 __global__ __launch_bounds__(256) void k_exact_main(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ up_first, const uint4* __restrict__ rec,
-    const int32_t* __restrict__ order, const int64_t* __restrict__ item_start,
-    const int64_t* __restrict__ cnt, int32_t maxnb, const int64_t* __restrict__ gq,
-    const int64_t* __restrict__ seg, int32_t ng, unsigned long long* queue,
+    const int32_t* __restrict__ order, const int64_t* __restrict__ rstart, int64_t nslots,
+    const int32_t* __restrict__ row_graph, unsigned long long* queue,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   __shared__ uint16_t lut[kNumCodes];
   __shared__ uint32_t hist[kWavesPerGroup * kCopies * kStride];
@@ -211,9 +226,8 @@ __global__ __launch_bounds__(256) void k_exact_main(
   const int wave = threadIdx.x / kWave;
   uint32_t* whist = hist + wave * (kCopies * kStride);
   uint32_t* myhist = whist + (lane & (kCopies - 1)) * kStride;
-  const int64_t NB = maxnb + 1;
-  const int64_t total = gq[ng];
-  int g = 0, b = maxnb - 1, dirty_g = -1;
+  const int64_t total = rstart[nslots];
+  int dirty_g = -1;
   int64_t visits = 0;
   for (;;) {
     unsigned long long qq = 0;
@@ -221,21 +235,21 @@ __global__ __launch_bounds__(256) void k_exact_main(
     const int64_t q = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(int(qq >> 32)) << 32) |
                                 (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(int(qq)));
     if (q >= total) break;
-    // items are graph-major; q only grows per wave
-    while (q >= gq[g + 1]) {
-      ++g;
-      b = maxnb - 1;
+    // slot k of `order` with rstart[k] <= q < rstart[k + 1]
+    int64_t lo = 0, hi = nslots;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (rstart[mid] <= q) lo = mid; else hi = mid;
     }
+    const int32_t i = order[lo];
+    const int g = row_graph[i];
     if (dirty_g >= 0 && (dirty_g != g || visits > kFlushVisits)) {
       flush_wave(whist, lane, dirty_g, hist_out);
       visits = 0;
     }
     dirty_g = g;
-    const int64_t ql = q - gq[g];
-    const int64_t* cg = cnt + g * NB;
-    const int64_t* sg = item_start + g * NB;
-    while (b > 0 && ql >= sg[b] + cg[b]) --b;
-    const int32_t i = order[seg[g] + ql - sg[b]];
+    const int nbi = int(rstart[lo + 1] - rstart[lo]);
+    const int b = nbi - 1 - int(q - rstart[lo]);
     const int64_t base = lg_ptr[i];
     const int d = int(lg_ptr[i + 1] - base);
     const int u = up_first[i];
@@ -279,8 +293,9 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int64_t NB = maxnb + 1;
   const int64_t rows = c1 - c0;
   // scratch (8-byte slots): nbhist, cnt, item_start, fill [ng*NB each], total [ng],
-  // gq [ng+1], seg [ng], queue [1]; then order [rows] int32
-  const size_t n8 = size_t(ng) * NB * 4 + size_t(ng) * 3 + 2;
+  // gq [ng+1], seg [ng], queue [1], rstart [rows+1], tmp; then order [rows] int32
+  const size_t tmpn = scan_tmp_elems(rows + 1);
+  const size_t n8 = size_t(ng) * NB * 4 + size_t(ng) * 3 + 2 + size_t(rows + 1) * 2 + tmpn;
   char* scratch = nullptr;
   mochy_status rc = device_alloc(ctx, (void**)&scratch, n8 * 8 + size_t(rows) * 4);
   if (rc != MOCHY_OK) return rc;
@@ -292,19 +307,25 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   int64_t* gq = total + ng;
   int64_t* seg = gq + (ng + 1);
   unsigned long long* queue = (unsigned long long*)(seg + ng);
+  int64_t* nbk = (int64_t*)(queue + 1);
+  int64_t* rstart = nbk + (rows + 1);
+  int64_t* tmp = rstart + (rows + 1);
   int32_t* order = (int32_t*)(scratch + n8 * 8);
   phase_begin(ctx, kPhSched);
-  MOCHY_HIP(hipMemsetAsync(scratch, 0, n8 * 8, st));
+  MOCHY_HIP(hipMemsetAsync(scratch, 0, (size_t(ng) * NB * 4 + size_t(ng) * 3 + 2) * 8, st));
+  MOCHY_HIP(hipMemsetAsync(order, 0xff, size_t(rows) * 4, st));
   k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, nbhist);
   k_sched_scan<<<unsigned(ng), 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
   k_sched_graphs<<<1, 1024, 0, st>>>(ng, c0, c1, g->geoff, total, gq, seg);
   k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, cnt,
                                                      seg, fill, order);
+  k_item_counts<<<blocks(rows + 1, 256), 256, 0, st>>>(rows, order, g->lg_ptr, nbk);
+  launch_exclusive_scan_i64(nbk, rstart, rows + 1, tmp, st);
   phase_end(ctx, kPhSched);
   const unsigned grid = unsigned(ctx->num_cus) * 8u;
   phase_begin(ctx, kPhPairs);
-  k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, order, item_start,
-                                     cnt, maxnb, gq, seg, ng, queue, ctx->d_code_to_id3,
+  k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, order, rstart, rows,
+                                     g->row_graph, queue, ctx->d_code_to_id3,
                                      (unsigned long long*)d_hist);
   phase_end(ctx, kPhPairs);
   phase_begin(ctx, kPhCorrect);
