@@ -244,17 +244,16 @@ int64_t orc_line_graph_degrees(int64_t E, int64_t V, const int64_t* ptr, const i
 // centre: the middle hyperedge of an open instance, the smallest index of a
 // closed one.  omega(e_j, e_k) is |e_j ∩ e_k|, the value the line graph
 // stores, obtained here by merging the node lists.
-void orc_mochy_e(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes, int64_t c0,
-                 int64_t c1, int theta, const int32_t* canon_to_id3, int64_t* out3 /*432*/,
-                 int nthreads) {
-  Graph g(E, V, ptr, nodes);
+static void mochy_e_over(const Graph& g, const int64_t* centers, int64_t n, int theta,
+                         const int32_t* canon_to_id3, int64_t* out3, int nthreads) {
   std::vector<int64_t> total(432, 0);
 #pragma omp parallel num_threads(nthreads)
   {
     std::vector<int64_t> local(432, 0);
     std::vector<std::pair<int32_t, int32_t>> nb;
 #pragma omp for schedule(dynamic, 1)
-    for (int64_t i = c0; i < c1; ++i) {
+    for (int64_t c = 0; c < n; ++c) {
+      const int64_t i = centers[c];
       g.neighbors(i, nb);
       const int64_t a = g.size(i);
       for (size_t x = 0; x < nb.size(); ++x)
@@ -272,6 +271,24 @@ void orc_mochy_e(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes,
     for (int t = 0; t < 432; ++t) total[t] += local[t];
   }
   memcpy(out3, total.data(), 432 * sizeof(int64_t));
+}
+
+void orc_mochy_e(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes, int64_t c0,
+                 int64_t c1, int theta, const int32_t* canon_to_id3, int64_t* out3 /*432*/,
+                 int nthreads) {
+  Graph g(E, V, ptr, nodes);
+  std::vector<int64_t> centers;
+  for (int64_t i = c0; i < c1; ++i) centers.push_back(i);
+  mochy_e_over(g, centers.data(), int64_t(centers.size()), theta, canon_to_id3, out3, nthreads);
+}
+
+// The same for an explicit list of centres (each instance is attributed to
+// one centre by Algorithm 2's condition, so any subset is well defined).
+void orc_mochy_e_centers(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes,
+                         const int64_t* centers, int64_t n, int theta,
+                         const int32_t* canon_to_id3, int64_t* out3 /*432*/, int nthreads) {
+  Graph g(E, V, ptr, nodes);
+  mochy_e_over(g, centers, n, theta, canon_to_id3, out3, nthreads);
 }
 
 // MoCHy-E candidates of centres [c0, c1): sum of C(d_i, 2).

@@ -49,6 +49,8 @@ def lib():
     L.orc_line_graph_degrees.restype = ctypes.c_int64
     L.orc_mochy_e.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64,
                               ctypes.c_int64, ctypes.c_int, _i32p, _i64p, ctypes.c_int]
+    L.orc_mochy_e_centers.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, ctypes.c_int64,
+                                      ctypes.c_int, _i32p, _i64p, ctypes.c_int]
     L.orc_candidates.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64, ctypes.c_int64]
     L.orc_candidates.restype = ctypes.c_int64
     L.orc_line_graph_triangles.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int]
@@ -126,6 +128,17 @@ def mochy_e(h, c0=0, c1=None, theta=1, nthreads=None):
     t = _table()
     lib().orc_mochy_e(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), int(c0), int(c1),
                       int(theta), _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
+    return fold26(out), out[1:].copy(), int(out[0])
+
+
+def mochy_e_centers(h, centers, theta=1, nthreads=None):
+    """(counts26, counts431, invalid) of plain MoCHy-E over an explicit centre list."""
+    ptr, nodes = _csr(h)
+    c = np.ascontiguousarray(centers, dtype=np.int64)
+    out = np.zeros(432, dtype=np.int64)
+    t = _table()
+    lib().orc_mochy_e_centers(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), _p(c, _i64p),
+                              int(c.size), int(theta), _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
     return fold26(out), out[1:].copy(), int(out[0])
 
 

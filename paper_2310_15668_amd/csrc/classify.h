@@ -24,13 +24,14 @@ __device__ __forceinline__ uint32_t pair_code(uint32_t a, uint32_t pj, uint32_t 
   const uint32_t R3 = k.o - r5;
   const uint32_t R4 = pj - t;
   const uint32_t R6 = k.s - t;
-  uint32_t code = st3(t);                 // R7
-  code = code * 3u + st3(R6);
-  code = code * 3u + st3(r5);             // R5
-  code = code * 3u + st3(R4);
-  code = code * 3u + st3(R3);
-  code = code * 3u + st3(R2);
-  code = code * 3u + st3(R1);
+  // Horner steps as 24-bit multiply-adds (full-rate on CDNA)
+  uint32_t code = st3(t);                                   // R7
+  code = __umul24(code, 3u) + st3(R6);
+  code = __umul24(code, 3u) + st3(r5);                      // R5
+  code = __umul24(code, 3u) + st3(R4);
+  code = __umul24(code, 3u) + st3(R3);
+  code = __umul24(code, 3u) + st3(R2);
+  code = __umul24(code, 3u) + st3(R1);
   return code;
 }
 

@@ -175,25 +175,42 @@ __global__ void k_sched_scatter(int64_t c0, int64_t c1, int32_t NB, const int64_
 // above the centre (count every pair); otherwise count only disjoint pairs.
 // kDiag: the j range overlaps the lane block, so require j < kp.
 template <bool kCountAll, bool kDiag>
+__device__ __forceinline__ void pair_step(const uint4& rj, int j, uint32_t a, const Side& k,
+                                          uint32_t khl, uint32_t khh, int kp, bool valid,
+                                          const uint16_t* __restrict__ lut, uint32_t* hist) {
+  const uint32_t mj = rj.x;
+  bool act = valid;
+  if (kDiag) act = act && (j < kp);
+  if (!kCountAll) {
+    // below the centre only disjoint pairs count: test with ANDs, no popcounts
+    act = act && (((mj & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u);
+  }
+  if (act) {
+    const uint32_t t = kCountAll ? uint32_t(__popc(mj & k.m)) : 0u;
+    const uint32_t r5 = kCountAll ? uint32_t(__popc(rj.z & khl) + __popc(rj.w & khh)) : 0u;
+    const uint32_t code = pair_code(a, __popc(mj), rj.y & 0xffu, k, t, r5);
+    atomicAdd(&hist[lut[code]], 1u);
+  }
+}
+
+// Walk j over [j0, j1) against the lane's k, four records per step (the
+// four uniform loads are issued together).  kCountAll: both j and k are
+// above the centre (count every pair); otherwise count only disjoint pairs.
+// kDiag: the j range overlaps the lane block, so require j < kp.
+template <bool kCountAll, bool kDiag>
 __device__ __forceinline__ void walk(const uint4* __restrict__ row, int j0, int j1, uint32_t a,
                                      const Side& k, int kp, bool valid,
                                      const uint16_t* __restrict__ lut, uint32_t* hist) {
-  for (int j = j0; j < j1; ++j) {
-    const uint4 rj = row[j];
-    const uint32_t mj = rj.x;
-    const uint32_t oj = rj.y & 0xffu;
-    const unsigned long long hj = (unsigned long long)rj.z | ((unsigned long long)rj.w << 32);
-    const uint32_t t = __popc(mj & k.m);
-    const uint32_t r5 = __popcll(hj & k.h);
-    bool act = valid;
-    if (kDiag) act = act && (j < kp);
-    if (!kCountAll) act = act && ((t | r5) == 0u);
-    if (act) {
-      const uint32_t pj = __popc(mj);
-      const uint32_t code = pair_code(a, pj, oj, k, t, r5);
-      atomicAdd(&hist[lut[code]], 1u);
-    }
+  const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    const uint4 r0 = row[j], r1 = row[j + 1], r2 = row[j + 2], r3 = row[j + 3];
+    pair_step<kCountAll, kDiag>(r0, j, a, k, khl, khh, kp, valid, lut, hist);
+    pair_step<kCountAll, kDiag>(r1, j + 1, a, k, khl, khh, kp, valid, lut, hist);
+    pair_step<kCountAll, kDiag>(r2, j + 2, a, k, khl, khh, kp, valid, lut, hist);
+    pair_step<kCountAll, kDiag>(r3, j + 3, a, k, khl, khh, kp, valid, lut, hist);
   }
+  for (; j < j1; ++j) pair_step<kCountAll, kDiag>(row[j], j, a, k, khl, khh, kp, valid, lut, hist);
 }
 
 // Adds a wave's histogram copies into graph g's global counts and clears them.

@@ -155,3 +155,52 @@ def test_centre_ranges_add_up(ctx):
     again = M.mochy_count_exact(ctx, g)[1]
     assert (again == full).all()  # deterministic
     g.close()
+
+
+@pytest.fixture(scope="module")
+def medium():
+    return make_config("medium")
+
+
+@pytest.fixture(scope="module")
+def medium_graph(ctx, medium):
+    import paper_2310_15668_amd as M
+    print("[gpu] project full medium hypergraph", flush=True)
+    g = M.mochy_project(ctx, medium.edge_ptr, medium.edge_nodes, medium.num_nodes)
+    yield g
+    g.close()
+
+
+def test_medium_full_size_centre_slices(ctx, medium, medium_graph):
+    # Algorithm 2 attributes each instance to one centre, so any centre range
+    # of the full-size graph can be checked against the oracle exactly.
+    import paper_2310_15668_amd as M
+    deg, w = native.line_graph_degrees(medium, 16)
+    assert w == medium_graph.num_hyperwedges
+    cand = deg * (deg - 1) // 2
+    hubby = int(np.argmin(np.abs(deg - 8000)))  # a centre with ~3e7 pairs, many 64-blocks
+    ranges = [(hubby, hubby + 1)]
+    csum = np.concatenate([[0], np.cumsum(cand)])
+    for a in range(0, medium.num_edges - 8, 997):  # 8-centre windows of moderate size
+        if 2e7 <= csum[a + 8] - csum[a] <= 2.5e8:
+            ranges.append((a, a + 8))
+        if len(ranges) == 3:
+            break
+    for a, b in ranges:
+        print(f"[gpu] medium centres [{a},{b}) candidates={int(cand[a:b].sum())}", flush=True)
+        g26, g431 = M.mochy_count_exact_range(ctx, medium_graph, a, b)
+        r26, r431, inv = native.mochy_e(medium, a, b, nthreads=16)
+        assert inv == 0 and (g431 == r431).all() and (g26 == r26).all(), (a, b)
+
+
+def test_medium_full_size_identity(ctx, medium, medium_graph):
+    # each open instance is one candidate of Algorithm 2, each closed one three
+    import paper_2310_15668_amd as M
+    deg, _ = native.line_graph_degrees(medium, 16)
+    print("[gpu] full medium exact count", flush=True)
+    c26, c431 = M.mochy_count_exact(ctx, medium_graph)
+    opened = [t - 1 for t in range(17, 23)]
+    so = int(c26[opened].sum())
+    sc = int(c26.sum()) - so
+    assert so + 3 * sc == int((deg * (deg - 1) // 2).sum())
+    assert (native.fold26(np.concatenate([[0], c431])) == c26).all()
