@@ -76,7 +76,7 @@ def copy_calibration():
 
 
 def cpu_baseline(h, seconds):
-    """The oracle (plain MoCHy-E, OpenMP over centres) on a prefix of centres."""
+    """The oracle (plain MoCHy-E, OpenMP over centres) on a bounded sample of centres."""
     import numpy as np
     from oracle import native
     try:
@@ -87,25 +87,28 @@ def cpu_baseline(h, seconds):
     deg, _ = native.line_graph_degrees(h, cores)
     cand = deg * (deg - 1) // 2
 
+    # centres of bounded size (at most 3e7 candidates each, so no single hub
+    # centre serializes the OpenMP loop over centres), evenly spread
+    cap = 3e7
+    pool = np.nonzero((cand > 0) & (cand <= cap))[0]
+
     def run(n):
-        # n centres spread evenly over the hypergraph (OpenMP works over centres)
-        stride = max(1, h.num_edges // n)
-        centres = np.arange(stride // 2, h.num_edges, stride, dtype=np.int64)[:n]
+        n = min(n, pool.size)
+        stride = max(1, pool.size // n)
+        centres = pool[stride // 2::stride][:n].astype(np.int64)
         t0 = time.perf_counter()
         c26, _, _ = native.mochy_e_centers(h, centres, nthreads=cores)
         dt = time.perf_counter() - t0
-        return stride, centres.size, int(c26.sum()), int(cand[centres].sum()), dt
+        return centres.size, int(c26.sum()), int(cand[centres].sum()), dt
 
-    # calibrate on a small sample, then take about `seconds` of work with at
-    # least two centres per thread
-    stride, n, tri, nc, dt = run(cores)
-    per_centre = dt / max(n, 1)
-    n = int(max(2 * cores, min(64 * cores, seconds / max(per_centre, 1e-6))))
-    stride, n, tri, nc, dt = run(n)
+    n, tri, nc, dt = run(4 * cores)  # calibration
+    n = int(max(4 * cores, seconds * n / max(dt, 1e-3)))
+    n, tri, nc, dt = run(n)
     return {
         "value": tri / dt, "unit": "triples/s", "cores": cores, "kind": "oracle",
-        "sample": f"{n} centres (every {stride}-th) of the medium hypergraph: {nc} MoCHy-E "
-                  f"candidates, {tri} connected triples attributed to them, {dt:.1f} s",
+        "sample": f"{n} evenly spread centres of the medium hypergraph among those with at most "
+                  f"3e7 candidates: {nc} MoCHy-E candidates, {tri} connected triples attributed "
+                  f"to them, {dt:.1f} s",
         "candidates_per_s": nc / dt,
     }
 
