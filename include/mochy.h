@@ -64,8 +64,10 @@ typedef struct {
 } mochy_csr;
 
 /* mochy_project flags */
-#define MOCHY_DEDUP 1u  /* host input only: drop repeated hyperedges, keeping the first;
-                           later ids shift down */
+#define MOCHY_DEDUP 1u    /* host input only: drop repeated hyperedges, keeping the first;
+                             later ids shift down */
+#define MOCHY_LG_FREE 4u  /* do not store the line graph (section 4.3's on-the-fly
+                             neighbourhoods); implied above 200000 hyperedges */
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to use,
  * or NULL to create a private one (default priority).  Builds the pattern
@@ -80,7 +82,14 @@ const char* mochy_last_error(const mochy_ctx* ctx);
  * the full line graph rows N_{e_i} (ascending hyperedge ids) with
  * omega(e_i, e_j) = |e_i ∩ e_j| folded into per-neighbour region masks, and
  * returns it.  *num_hyperwedges = |wedges| = number of adjacent unordered
- * pairs.  Errors: MOCHY_EINVAL, MOCHY_EDUP, MOCHY_ERANGE, MOCHY_ENOMEM,
+ * pairs.
+ * Line-graph-free mode (flag MOCHY_LG_FREE, and always for more than 200000
+ * hyperedges): no rows are stored; the graph keeps E_v, a copy of each
+ * neighbour's node list per slot of E_v (sum of |e|^2 node ids, which must
+ * stay below 2^32, else MOCHY_ERANGE), the line-graph degrees and the
+ * hyperwedge order, and serves mochy_count_sampled (neighbourhoods formed on
+ * demand, section 4.3); mochy_count_exact then returns MOCHY_EUNSUPPORTED.
+ * Errors: MOCHY_EINVAL, MOCHY_EDUP, MOCHY_ERANGE, MOCHY_ENOMEM,
  * MOCHY_EDEVICE.  Free the result with mochy_graph_free. */
 mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* g, uint32_t flags,
                            mochy_graph** out, int64_t* num_hyperwedges);
@@ -143,15 +152,18 @@ int32_t mochy_parent_motif(int32_t id3);
  * line-graph degree, out[5] MoCHy-E candidates sum_i C(d_i, 2) (pairs
  * Algorithm 2 considers), out[6] sum over those candidates of
  * min(|e_i|, |e_j|, |e_k|) (the size factor of Lemma 2's triple
- * intersection), out[7] sum_i d_i^2.  out: host, 8 int64. */
+ * intersection; -1 for a line-graph-free graph), out[7] sum_i d_i^2.
+ * out: host, 8 int64. */
 mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* out);
 
 /* Milliseconds spent in each device phase by the most recent call on this
  * context, from HIP events recorded on the context stream (0 for phases the
  * call did not run).  Phases: 0 upload+validate, 1 transpose + heavy-node
- * pick, 2 line-graph degrees, 3 line-graph rows, 4 region records,
+ * pick, 2 line-graph degrees, 3 line-graph rows (line-graph-free mode: the
+ * per-slot node lists and heavy-node tables), 4 region records,
  * 5 exact scheduling, 6 exact pair kernel, 7 exact light-node correction,
- * 8 sampling draws, 9 sampled enumeration, 10 profile significance + CP.
+ * 8 sampling draws (line-graph-free mode: with grouping by row and the pick
+ * of e_j), 9 sampled enumeration, 10 profile significance + CP.
  * ms: host, MOCHY_NUM_PHASES doubles. */
 #define MOCHY_NUM_PHASES 11
 mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);

@@ -132,7 +132,7 @@ inline void add_hist(std::vector<int64_t>& local, int id3) { local[id3] += 1; }
 
 extern "C" {
 
-int orc_abi_version() { return 3; }
+int orc_abi_version() { return 4; }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy
 // as 1, 2, 3", SC'11): ten rounds of the 4x32 S-box; each round multiplies
@@ -337,37 +337,74 @@ int64_t orc_line_graph_triangles(int64_t E, int64_t V, const int64_t* ptr, const
   return tri;
 }
 
-// MoCHy-A+ (Algorithm 5), hit counts before rescaling, for sample numbers
-// n in [n0, n1).  Hyperwedges are ordered lexicographically by (i, j), i < j.
-// Sample n draws Philox4x32-10 with counter (lo32 n, hi32 n, 0, 0) and key
-// (lo32 seed, hi32 seed); u = (x1 << 32) | x0; the hyperwedge index is
-// floor(u * |wedges| / 2^64).  For the sampled wedge {e_i, e_j}, every
-// e_k in N_i ∪ N_j minus {e_i, e_j} adds one to raw[h(i, j, k)].
-// If `indices` is non-null, sample n uses hyperwedge indices[n] instead of
-// Philox (used to visit every hyperwedge exactly once).
-int64_t orc_aplus_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes, int64_t n0,
-                      int64_t n1, uint64_t seed, const int64_t* indices, int theta,
-                      const int32_t* canon_to_id3, int64_t* raw3 /*432*/, int nthreads) {
+// Sorted N_{e_i} built on demand from E_v (section 4.3's on-the-fly
+// neighbourhood: the union of E_v over v in e_i, minus e_i itself), so that
+// no line graph has to be stored.  `mark` is a per-thread scratch of size |E|
+// holding, for each hyperedge, the stamp of the last build that listed it;
+// every build takes a fresh stamp.
+static void neighbor_list(const Graph& g, int64_t i, std::vector<int64_t>& mark, int64_t& stamp,
+                          std::vector<int32_t>& out) {
+  out.clear();
+  const int64_t st = ++stamp;
+  for (int64_t q = g.ptr[i]; q < g.ptr[i + 1]; ++q) {
+    const int32_t v = g.nodes[q];
+    for (int64_t r = g.vptr[v]; r < g.vptr[v + 1]; ++r) {
+      const int64_t x = g.vedges[r];
+      if (x != i && mark[x] != st) { mark[x] = st; out.push_back((int32_t)x); }
+    }
+  }
+  std::sort(out.begin(), out.end());
+}
+
+// Hyperwedge order for sampling: hyperwedges {e_i, e_j}, i < j, listed by
+// (i, j) lexicographically; up_ptr[i] = number of hyperwedges whose smaller
+// hyperedge is below i (exclusive prefix of the upper degrees
+// |{j > i : e_i ∩ e_j non-empty}|).  Returns |wedges|.
+int64_t orc_wedge_prefix(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes,
+                         int64_t* up_ptr /*E+1*/, int nthreads) {
   Graph g(E, V, ptr, nodes);
-  // Algorithm 1: full neighbourhoods (sorted), the upper part gives the wedge order.
-  std::vector<std::vector<int32_t>> nbr(E);
+  std::vector<int64_t> up(E, 0);
 #pragma omp parallel num_threads(nthreads)
   {
     std::vector<int64_t> mark(E, -1);
 #pragma omp for schedule(dynamic, 64)
     for (int64_t i = 0; i < E; ++i) {
+      int64_t d = 0;
       for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q)
         for (int64_t r = g.vptr[nodes[q]]; r < g.vptr[nodes[q] + 1]; ++r) {
-          int64_t x = g.vedges[r];
-          if (x != i && mark[x] != i) { mark[x] = i; nbr[i].push_back((int32_t)x); }
+          const int64_t x = g.vedges[r];
+          if (x > i && mark[x] != i) { mark[x] = i; ++d; }
         }
-      std::sort(nbr[i].begin(), nbr[i].end());
+      up[i] = d;
     }
   }
-  std::vector<int64_t> up_ptr(E + 1, 0), first_up(E, 0);
-  for (int64_t i = 0; i < E; ++i) {
-    first_up[i] = std::upper_bound(nbr[i].begin(), nbr[i].end(), (int32_t)i) - nbr[i].begin();
-    up_ptr[i + 1] = up_ptr[i] + (int64_t)nbr[i].size() - first_up[i];
+  up_ptr[0] = 0;
+  for (int64_t i = 0; i < E; ++i) up_ptr[i + 1] = up_ptr[i] + up[i];
+  return up_ptr[E];
+}
+
+// MoCHy-A+ (Algorithm 5), hit counts before rescaling, for sample numbers
+// n in [n0, n1).  Hyperwedges are ordered as in orc_wedge_prefix.  Sample n
+// draws Philox4x32-10 with counter (lo32 n, hi32 n, 0, 0) and key
+// (lo32 seed, hi32 seed); u = (x1 << 32) | x0; the hyperwedge index is
+// floor(u * |wedges| / 2^64).  For the sampled wedge {e_i, e_j}, every
+// e_k in N_i ∪ N_j minus {e_i, e_j} adds one to raw[h(i, j, k)].
+// Both neighbourhoods are built on demand for each sample, so the line graph
+// is never stored.  If `indices` is non-null, sample n uses hyperwedge
+// indices[n] instead of Philox (used to visit every hyperwedge exactly once).
+// `up_ptr_in` (E+1 entries, from orc_wedge_prefix) may be passed to skip
+// recomputing the hyperwedge order; NULL computes it.
+int64_t orc_aplus_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes, int64_t n0,
+                      int64_t n1, uint64_t seed, const int64_t* indices, const int64_t* up_ptr_in,
+                      int theta, const int32_t* canon_to_id3, int64_t* raw3 /*432*/,
+                      int nthreads) {
+  Graph g(E, V, ptr, nodes);
+  std::vector<int64_t> up_own;
+  const int64_t* up_ptr = up_ptr_in;
+  if (!up_ptr) {
+    up_own.assign(E + 1, 0);
+    orc_wedge_prefix(E, V, ptr, nodes, up_own.data(), nthreads);
+    up_ptr = up_own.data();
   }
   const uint64_t W = (uint64_t)up_ptr[E];
   std::vector<int64_t> total(432, 0);
@@ -375,8 +412,10 @@ int64_t orc_aplus_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* n
 #pragma omp parallel num_threads(nthreads)
   {
     std::vector<int64_t> local(432, 0);
-    std::vector<int32_t> uni;
-#pragma omp for schedule(dynamic, 256)
+    std::vector<int64_t> mark(E, -1);
+    std::vector<int32_t> ni, nj, uni;
+    int64_t stamp = -1;
+#pragma omp for schedule(dynamic, 1)
     for (int64_t n = n0; n < n1; ++n) {
       uint64_t idx;
       if (indices) {
@@ -389,10 +428,13 @@ int64_t orc_aplus_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* n
         uint64_t u = ((uint64_t)x[1] << 32) | x[0];
         idx = (uint64_t)(((unsigned __int128)u * W) >> 64);
       }
-      int64_t i = std::upper_bound(up_ptr.begin(), up_ptr.end(), (int64_t)idx) - up_ptr.begin() - 1;
-      int64_t j = nbr[i][first_up[i] + ((int64_t)idx - up_ptr[i])];
+      const int64_t i = std::upper_bound(up_ptr, up_ptr + E + 1, (int64_t)idx) - up_ptr - 1;
+      neighbor_list(g, i, mark, stamp, ni);
+      const int64_t first_up = std::upper_bound(ni.begin(), ni.end(), (int32_t)i) - ni.begin();
+      const int64_t j = ni[first_up + ((int64_t)idx - up_ptr[i])];
+      neighbor_list(g, j, mark, stamp, nj);
       uni.clear();
-      std::set_union(nbr[i].begin(), nbr[i].end(), nbr[j].begin(), nbr[j].end(), std::back_inserter(uni));
+      std::set_union(ni.begin(), ni.end(), nj.begin(), nj.end(), std::back_inserter(uni));
       const int64_t wij = g.overlap(i, j);
       for (int32_t k : uni) {
         if (k == i || k == j) continue;

@@ -56,8 +56,10 @@ def lib():
     L.orc_line_graph_triangles.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int]
     L.orc_line_graph_triangles.restype = ctypes.c_int64
     L.orc_aplus_raw.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64,
-                                ctypes.c_int64, ctypes.c_uint64, _i64p, ctypes.c_int, _i32p, _i64p,
-                                ctypes.c_int]
+                                ctypes.c_int64, ctypes.c_uint64, _i64p, _i64p, ctypes.c_int, _i32p,
+                                _i64p, ctypes.c_int]
+    L.orc_wedge_prefix.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, ctypes.c_int]
+    L.orc_wedge_prefix.restype = ctypes.c_int64
     L.orc_aplus_raw.restype = ctypes.c_int64
     _lib = L
     return L
@@ -156,10 +158,20 @@ def line_graph_triangles(h, nthreads=None):
                                               _p(nodes, _i32p), _threads(nthreads)))
 
 
-def aplus_raw(h, r=None, seed=0, n0=0, indices=None, theta=1, nthreads=None):
+def wedge_prefix(h, nthreads=None):
+    """(up_ptr int64[|E|+1], |wedges|): the hyperwedge order used for sampling."""
+    ptr, nodes = _csr(h)
+    up = np.zeros(h.num_edges + 1, dtype=np.int64)
+    w = lib().orc_wedge_prefix(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p),
+                               _p(up, _i64p), _threads(nthreads))
+    return up, int(w)
+
+
+def aplus_raw(h, r=None, seed=0, n0=0, indices=None, theta=1, nthreads=None, up_ptr=None):
     """(raw26, raw431, invalid, |wedges|) of MoCHy-A+ samples n in [n0, n0 + r).
 
     With ``indices`` the samples use those hyperwedge indices instead of Philox.
+    ``up_ptr`` (from :func:`wedge_prefix`) skips recomputing the hyperwedge order.
     """
     ptr, nodes = _csr(h)
     out = np.zeros(432, dtype=np.int64)
@@ -169,7 +181,12 @@ def aplus_raw(h, r=None, seed=0, n0=0, indices=None, theta=1, nthreads=None):
         n0, n1, ip = 0, idx.size, _p(idx, _i64p)
     else:
         n1, ip = n0 + int(r), None
+    up = None
+    if up_ptr is not None:
+        up = np.ascontiguousarray(up_ptr, dtype=np.int64)
+        assert up.size == h.num_edges + 1
     w = lib().orc_aplus_raw(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), int(n0),
-                            int(n1), ctypes.c_uint64(seed & (2 ** 64 - 1)), ip, int(theta),
+                            int(n1), ctypes.c_uint64(seed & (2 ** 64 - 1)), ip,
+                            _p(up, _i64p) if up is not None else None, int(theta),
                             _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
     return fold26(out), out[1:].copy(), int(out[0]), int(w)

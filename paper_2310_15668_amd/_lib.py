@@ -18,6 +18,7 @@ MOCHY_OK = 0
 STATUS = {0: "MOCHY_OK", -1: "MOCHY_EINVAL", -2: "MOCHY_EDUP", -3: "MOCHY_ERANGE",
           -4: "MOCHY_ENOMEM", -5: "MOCHY_EDEVICE", -6: "MOCHY_EUNSUPPORTED"}
 MOCHY_DEDUP = 1
+MOCHY_LG_FREE = 4
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 

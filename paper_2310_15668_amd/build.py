@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmochy.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["patterns.cpp", "scan.hip", "project.hip", "exact.hip", "correct.hip", "sampled.hip", "profile.hip", "api.hip"]
+SOURCES = ["patterns.cpp", "scan.hip", "project.hip", "exact.hip", "correct.hip", "sampled.hip",
+           "free.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

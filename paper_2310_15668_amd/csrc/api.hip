@@ -281,7 +281,8 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
   }
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
-                  g->gnoff,    g->row_graph};
+                  g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
+                  g->hpair};
   for (void* b : bufs) (void)hipFree(b);
   delete g;
 }
@@ -382,7 +383,9 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
   }
   g->bytes = size_t(g->E + 1) * 8 + size_t(g->nnz) * 4;
   if ((rc = set_single_graph(ctx, g)) != MOCHY_OK) return fail(rc);
-  if ((rc = project_device(ctx, g)) != MOCHY_OK) return fail(rc);
+  const bool lg_free = (flags & MOCHY_LG_FREE) || g->E > kMaxGraphEdges;
+  rc = lg_free ? project_free_device(ctx, g) : project_device(ctx, g);
+  if (rc != MOCHY_OK) return fail(rc);
   *out = g;
   if (num_hyperwedges) *num_hyperwedges = g->W;
   return MOCHY_OK;
@@ -415,6 +418,11 @@ extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_grap
     ctx->err = "bad graph or centre range";
     return MOCHY_EINVAL;
   }
+  if (g->lg_free) {
+    ctx->err = "exact counting walks stored line-graph rows; this graph was projected without "
+               "them (MOCHY_LG_FREE or more than 200000 hyperedges): use mochy_count_sampled";
+    return MOCHY_EUNSUPPORTED;
+  }
   MOCHY_HIP(hipSetDevice(ctx->device));
   int64_t* d_hist = ctx->d_small + 64;  // [432]
   mochy_status rc = exact_device(ctx, g, c0, c1, d_hist);
@@ -438,11 +446,18 @@ extern "C" mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, 
   hipStream_t st = ctx->stream;
   unsigned long long* d = (unsigned long long*)(ctx->d_small + 500);
   MOCHY_HIP(hipMemsetAsync(d, 0, 3 * 8, st));
-  if (g->E > 0) k_stats<<<unsigned(g->E), 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->rec, d);
+  if (g->lg_free) {
+    const mochy_status rc = free_graph_stats(ctx, g, d);
+    if (rc != MOCHY_OK) return rc;
+  } else if (g->E > 0) {
+    k_stats<<<unsigned(g->E), 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->rec, d);
+  }
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 500, d, 3 * 8, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
   out[0] = g->E; out[1] = g->V; out[2] = g->nnz; out[3] = g->W; out[4] = g->max_deg;
-  out[5] = ctx->h_small[500]; out[6] = ctx->h_small[501]; out[7] = ctx->h_small[502];
+  out[5] = ctx->h_small[500];
+  out[6] = g->lg_free ? -1 : ctx->h_small[501];
+  out[7] = ctx->h_small[502];
   return MOCHY_OK;
 }
 
@@ -459,7 +474,8 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   int64_t* d_hist = ctx->d_small + 64;
-  mochy_status rc = sampled_device(ctx, g, r, seed, sample_begin, d_hist);
+  mochy_status rc = g->lg_free ? sampled_free_device(ctx, g, r, seed, sample_begin, d_hist)
+                               : sampled_device(ctx, g, r, seed, sample_begin, d_hist);
   if (rc != MOCHY_OK) return rc;
   int64_t* d_raw26 = ctx->d_small;
   k_aplus_est<<<1, 512, 0, st>>>(d_hist, ctx->d_id3_to_id26, ctx->d_open26, g->W, r, d_raw26,

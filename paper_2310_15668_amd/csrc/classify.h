@@ -1,5 +1,5 @@
-// Region classification of a pair of neighbours of a centre e_i, shared by
-// the exact kernels (Lemma 2: region sizes from |e_i|, the two overlaps with
+// Region classification of a triple of hyperedges, shared by the exact and
+// sampled kernels (Lemma 2: region sizes from |e_i|, the two overlaps with
 // e_i, the triple overlap and the overlap of e_j and e_k outside e_i).
 #pragma once
 
@@ -32,6 +32,21 @@ __device__ __forceinline__ uint32_t pair_code(uint32_t a, uint32_t pj, uint32_t 
   code = __umul24(code, 3u) + st3(R3);
   code = __umul24(code, 3u) + st3(R2);
   code = __umul24(code, 3u) + st3(R1);
+  return code;
+}
+
+// The same code from the three sizes and the four overlaps of Lemma 2:
+// a = |e_i|, b = |e_j|, c = |e_k|, p = |e_i ∩ e_j|, q = |e_j ∩ e_k|,
+// s = |e_k ∩ e_i|, t = |e_i ∩ e_j ∩ e_k|.
+__device__ __forceinline__ uint32_t triple_code(uint32_t a, uint32_t b, uint32_t c, uint32_t p,
+                                                uint32_t q, uint32_t s, uint32_t t) {
+  uint32_t code = st3(t);                                   // R7
+  code = __umul24(code, 3u) + st3(s - t);                   // R6
+  code = __umul24(code, 3u) + st3(q - t);                   // R5
+  code = __umul24(code, 3u) + st3(p - t);                   // R4
+  code = __umul24(code, 3u) + st3(c + t - s - q);           // R3
+  code = __umul24(code, 3u) + st3(b + t - p - q);           // R2
+  code = __umul24(code, 3u) + st3(a + t - p - s);           // R1
   return code;
 }
 

@@ -83,8 +83,16 @@ struct mochy_graph {
   int32_t* up_first = nullptr;           // [E]: position in row i of the first neighbour > i
   int64_t* up_ptr = nullptr;             // [E+1]: prefix sums of upper-row lengths (wedge order)
   uint4* rec = nullptr;                  // [2W]: per (centre, neighbour) region record
+  // line-graph-free mode (no lg_ptr / lg_col / up_first / rec)
+  bool lg_free = false;
+  uint32_t* xoff = nullptr;              // [nnz+1]: slot p of E_v -> start of e_k's nodes in xnodes
+  int32_t* xnodes = nullptr;             // [xoff[nnz]]: node list of the hyperedge at each slot
+  int64_t* deg = nullptr;                // [E]: line-graph degrees
+  uint32_t* hsize = nullptr;             // [64][kSizeSlots]: hyperedges holding heavy node b, by size
+  uint32_t* hpair = nullptr;             // [64][64][kSizeSlots]: holding heavy nodes b1 and b2, by size
   size_t bytes = 0;                      // device bytes held
 };
+constexpr int kSizeSlots = MOCHY_MAX_EDGE + 1;
 
 // Per (centre i, neighbour x) record, 16 bytes:
 //   x: bit p set iff the p-th node of e_i (ascending) is in e_x
@@ -109,8 +117,17 @@ void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64
                                hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 
-// project.hip
+// project.hip: validation, transpose and heavy nodes (project_incidence),
+// then the line graph
+mochy_status project_incidence(mochy_ctx* ctx, mochy_graph* g);
 mochy_status project_device(mochy_ctx* ctx, mochy_graph* g);
+
+// free.hip: line-graph-free projection and MoCHy-A+ (single graphs)
+mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g);
+mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
+                                 int64_t n0, int64_t* d_hist);
+// adds sum_i C(d_i, 2) to d_out[0] and sum_i d_i^2 to d_out[2]
+mochy_status free_graph_stats(mochy_ctx* ctx, const mochy_graph* g, unsigned long long* d_out);
 
 // exact.hip: per-graph histograms d_hist[ng][kHistSlots], zeroed inside
 mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,

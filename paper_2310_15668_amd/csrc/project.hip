@@ -1,5 +1,6 @@
 // Line-graph construction on the device (Algorithm 1, section 4.1).
 //
+// project_incidence (steps 1-3) is shared with the line-graph-free mode.
 // Steps, all on the context stream:
 //   1. validate the CSR (sorted, in range, non-empty, size <= MOCHY_MAX_EDGE);
 //   2. transpose it into E_v (node -> hyperedges): count, scan, scatter;
@@ -252,13 +253,9 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 
 }  // namespace
 
-mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
+mochy_status project_incidence(mochy_ctx* ctx, mochy_graph* g) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E, V = g->V, nnz = g->nnz;
-  if (g->max_graph_edges > kMaxGraphEdges) {
-    ctx->err = "hypergraphs above 200000 hyperedges need the line-graph-free mode, not in this build";
-    return MOCHY_EUNSUPPORTED;
-  }
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int32_t), st));
   if (E > 0)
     k_validate<<<blocks(E, 256), 256, 0, st>>>(E, g->ng, g->geoff, g->gvoff, g->gnoff, g->edge_ptr,
@@ -277,19 +274,20 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   int64_t* cnt = nullptr;
   unsigned int* fill = nullptr;
   mochy_status rc;
-  if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK) return rc;
-  if ((rc = device_alloc(ctx, (void**)&cnt, size_t(std::max(V, E) + 1) * 8)) != MOCHY_OK) return rc;
-  if ((rc = device_alloc(ctx, (void**)&fill, size_t(V + 1) * 4)) != MOCHY_OK) return rc;
   auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(cnt); (void)hipFree(fill); };
+  if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&cnt, size_t(std::max(V, E) + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&fill, size_t(V + 1) * 4)) != MOCHY_OK) {
+    cleanup();
+    return rc;
+  }
   if ((rc = device_alloc(ctx, (void**)&g->node_ptr, size_t(V + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->node_edges, size_t(std::max<int64_t>(nnz, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->heavy_bit, size_t(std::max<int64_t>(V, 1)))) != MOCHY_OK) { cleanup(); return rc; }
-  if ((rc = device_alloc(ctx, (void**)&g->lg_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
-  if ((rc = device_alloc(ctx, (void**)&g->up_first, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->up_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->row_graph, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if (E > 0) k_row_graph<<<blocks(E, 256), 256, 0, st>>>(E, g->ng, g->geoff, g->row_graph);
-  g->bytes += size_t(V + 1) * 8 + size_t(nnz) * 4 + size_t(V) + size_t(E + 1) * 16 + size_t(E) * 4;
+  g->bytes += size_t(V + 1) * 8 + size_t(nnz) * 4 + size_t(V) + size_t(E + 1) * 8 + size_t(E) * 4;
 
   phase_begin(ctx, kPhTranspose);
   MOCHY_HIP(hipMemsetAsync(cnt, 0, size_t(V + 1) * 8, st));
@@ -303,6 +301,32 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   // 3. heavy nodes
   if (V > 0) k_heavy<<<unsigned(g->ng), 1024, 0, st>>>(g->gvoff, g->node_ptr, g->heavy_bit);
   phase_end(ctx, kPhTranspose);
+  MOCHY_HIP(hipStreamSynchronize(st));
+  cleanup();
+  return MOCHY_OK;
+}
+
+mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
+  hipStream_t st = ctx->stream;
+  const int64_t E = g->E;
+  if (g->max_graph_edges > kMaxGraphEdges) {
+    ctx->err = "a graph of a batch exceeds 200000 hyperedges (the line-graph-free mode takes single graphs)";
+    return MOCHY_EUNSUPPORTED;
+  }
+  mochy_status rc = project_incidence(ctx, g);
+  if (rc != MOCHY_OK) return rc;
+  const size_t tmpn = scan_tmp_elems(E + 1);
+  int64_t* tmp = nullptr;
+  int64_t* cnt = nullptr;
+  auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(cnt); };
+  if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&cnt, size_t(E + 1) * 8)) != MOCHY_OK) {
+    cleanup();
+    return rc;
+  }
+  if ((rc = device_alloc(ctx, (void**)&g->lg_ptr, size_t(E + 1) * 8)) != MOCHY_OK) { cleanup(); return rc; }
+  if ((rc = device_alloc(ctx, (void**)&g->up_first, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
+  g->bytes += size_t(E + 1) * 8 + size_t(E) * 4;
 
   // 4-5. degrees and row pointers
   const int nwords = int((g->max_graph_edges + 31) / 32);

@@ -14,32 +14,9 @@
 // region sizes then follow Lemma 2 exactly.
 #include "classify.h"
 #include "common.h"
+#include "rng.h"
 
 namespace {
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): per round, the two
-// multiplier constants multiply counter words 0 and 2; the new state is
-// (hi(w2*M1) ^ w1 ^ k0, lo(w2*M1), hi(w0*M0) ^ w3 ^ k1, lo(w0*M0)); the key
-// advances by the two Weyl constants between rounds.
-__device__ __forceinline__ uint4 philox_4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
-  constexpr uint32_t kMul0 = 0xD2511F53u, kMul1 = 0xCD9E8D57u;
-  constexpr uint32_t kWeyl0 = 0x9E3779B9u, kWeyl1 = 0xBB67AE85u;
-#pragma unroll
-  for (int round = 0; round < 10; ++round) {
-    const uint32_t h0 = __umulhi(kMul0, c.x), l0 = kMul0 * c.x;
-    const uint32_t h1 = __umulhi(kMul1, c.z), l1 = kMul1 * c.z;
-    c = make_uint4(h1 ^ c.y ^ k0, l1, h0 ^ c.w ^ k1, l0);
-    k0 += kWeyl0;
-    k1 += kWeyl1;
-  }
-  return c;
-}
-
-__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
 
 __global__ __launch_bounds__(256) void k_aplus(
     int64_t n0, int64_t r, uint64_t seed, uint64_t W, int64_t E,
@@ -54,23 +31,13 @@ __global__ __launch_bounds__(256) void k_aplus(
   for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
   for (;;) {
     unsigned long long sq = 0;
     if (lane == 0) sq = atomicAdd(queue, 1ull);
     const int64_t s = int64_t(uniform64(sq));
     if (s >= r) break;
-    const uint64_t n = uint64_t(n0) + uint64_t(s);
-    const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 0u, 0u), k0, k1);
-    const uint64_t u = (uint64_t(x.y) << 32) | x.x;
-    const int64_t idx = int64_t(__umul64hi(u, W));
-    // row i: the last i with up_ptr[i] <= idx
-    int64_t lo = 0, hi = E;
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (up_ptr[mid] <= idx) lo = mid; else hi = mid;
-    }
-    const int64_t i = lo;
+    const int64_t idx = int64_t(sample_wedge(uint64_t(n0) + uint64_t(s), seed, W));
+    const int64_t i = wedge_row(up_ptr, E, idx);
     const int64_t ab = lg_ptr[i];
     const int64_t pj = int64_t(up_first[i]) + (idx - up_ptr[i]);
     const int32_t j = lg_col[ab + pj];

@@ -129,3 +129,27 @@ def test_prefix_additivity():
     a = native.aplus_raw(h, r=1234, seed=7, n0=0, nthreads=4)[1]
     b = native.aplus_raw(h, r=3000 - 1234, seed=7, n0=1234, nthreads=4)[1]
     assert (a + b == full).all()
+
+
+def test_wedge_prefix_by_brute_force():
+    # up_ptr[i+1] - up_ptr[i] = |{j > i : e_i ∩ e_j non-empty}| (Algorithm 1's
+    # hyperwedges, listed by their smaller hyperedge)
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        V = int(rng.integers(3, 12))
+        edges = sorted({tuple(sorted(rng.choice(V, size=int(rng.integers(1, min(V, 5) + 1)),
+                                                replace=False).tolist())) for _ in range(15)})
+        h = from_edge_lists(edges, V)
+        up, W = native.wedge_prefix(h, 2)
+        sets = [set(e) for e in edges]
+        brute = [sum(1 for j in range(i + 1, len(sets)) if sets[i] & sets[j]) for i in range(len(sets))]
+        assert up.tolist() == [0] + np.cumsum(brute).tolist()
+        assert W == native.line_graph_degrees(h, 2)[1]
+
+
+def test_sampling_with_given_order_is_unchanged():
+    h = make_config("tiny")
+    up, _ = native.wedge_prefix(h, 4)
+    a = native.aplus_raw(h, r=3000, seed=11, n0=5, nthreads=4)
+    b = native.aplus_raw(h, r=3000, seed=11, n0=5, nthreads=4, up_ptr=up)
+    assert (a[1] == b[1]).all() and a[3] == b[3]
