@@ -66,7 +66,7 @@ typedef struct {
 /* mochy_project flags */
 #define MOCHY_DEDUP 1u    /* host input only: drop repeated hyperedges, keeping the first;
                              later ids shift down */
-#define MOCHY_LG_FREE 4u  /* do not store the line graph (section 4.3's on-the-fly
+#define MOCHY_LG_FREE 4u  /* do not store the line graph (section 4.4's on-the-fly
                              neighbourhoods); implied above 200000 hyperedges */
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to use,
@@ -88,7 +88,7 @@ const char* mochy_last_error(const mochy_ctx* ctx);
  * neighbour's node list per slot of E_v (sum of |e|^2 node ids, which must
  * stay below 2^32, else MOCHY_ERANGE), the line-graph degrees and the
  * hyperwedge order, and serves mochy_count_sampled (neighbourhoods formed on
- * demand, section 4.3); mochy_count_exact then returns MOCHY_EUNSUPPORTED.
+ * demand, section 4.4); mochy_count_exact then returns MOCHY_EUNSUPPORTED.
  * Errors: MOCHY_EINVAL, MOCHY_EDUP, MOCHY_ERANGE, MOCHY_ENOMEM,
  * MOCHY_EDEVICE.  Free the result with mochy_graph_free. */
 mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* g, uint32_t flags,

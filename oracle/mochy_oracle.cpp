@@ -337,7 +337,7 @@ int64_t orc_line_graph_triangles(int64_t E, int64_t V, const int64_t* ptr, const
   return tri;
 }
 
-// Sorted N_{e_i} built on demand from E_v (section 4.3's on-the-fly
+// Sorted N_{e_i} built on demand from E_v (section 4.4's on-the-fly
 // neighbourhood: the union of E_v over v in e_i, minus e_i itself), so that
 // no line graph has to be stored.  `mark` is a per-thread scratch of size |E|
 // holding, for each hyperedge, the stamp of the last build that listed it;

@@ -1,7 +1,7 @@
 // Line-graph-free mode: MoCHy-A+ (Algorithm 5) on hypergraphs whose line
 // graph does not fit in device memory.  Neighbourhoods are formed on demand
 // from the incidence and its transpose (the on-the-fly neighbourhoods of
-// section 4.3), never stored.
+// section 4.4), never stored.
 //
 // Projection keeps, besides the incidence and E_v:
 //   * expanded lists: for every slot (v, e_k) of E_v a copy of e_k's node

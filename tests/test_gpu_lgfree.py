@@ -1,5 +1,5 @@
 """GPU parity of the line-graph-free mode (neighbourhoods formed on demand,
-section 4.3) against the oracle: hyperwedge count and MoCHy-A+ raw hits must
+section 4.4) against the oracle: hyperwedge count and MoCHy-A+ raw hits must
 be bit-exact for the same Philox stream.
 
 Every case prints what it runs before it touches the GPU.
