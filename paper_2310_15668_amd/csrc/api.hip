@@ -282,7 +282,7 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
-                  g->hpair};
+                  g->hpair,    g->htriple};
   for (void* b : bufs) (void)hipFree(b);
   delete g;
 }

@@ -90,6 +90,7 @@ struct mochy_graph {
   int64_t* deg = nullptr;                // [E]: line-graph degrees
   uint32_t* hsize = nullptr;             // [64][kSizeSlots]: hyperedges holding heavy node b, by size
   uint32_t* hpair = nullptr;             // [64][64][kSizeSlots]: holding heavy nodes b1 and b2, by size
+  uint32_t* htriple = nullptr;           // [C(64,3)][kSizeSlots]: holding three heavy nodes, by size
   size_t bytes = 0;                      // device bytes held
 };
 constexpr int kSizeSlots = MOCHY_MAX_EDGE + 1;

@@ -11,13 +11,13 @@
 //     with an ownership rule: e_k in N_i is counted at the smallest node of
 //     e_i ∩ e_k, so each neighbour is seen once with no per-row set;
 //   * for the 64 heavy nodes, how many hyperedges of each size hold a heavy
-//     node, and hold a pair of heavy nodes.
+//     node, a pair and a triple of heavy nodes.
 //
 // Sampling runs in chunks of samples: draw the hyperwedge index of each
 // sample and its row i; group samples by row; pick j, the m-th neighbour of
 // e_i above i, from a bitmap of N_i built in LDS; enumerate N_i ∪ N_j.  The
 // enumeration visits the lists E_v of u = e_i ∪ e_j except for the (at most
-// two) heavy nodes with the longest lists; hyperedges reached through the
+// three) heavy nodes with the longest lists; hyperedges reached through the
 // skipped lists only are counted in bulk per size from the heavy-node tables
 // (their class depends only on which skipped nodes they hold and on |e_k|),
 // by inclusion-exclusion against the walked ones.
@@ -69,13 +69,17 @@ __device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v, int lane) {
 
 // ---------------------------------------------------------------- projection
 
-// size of the hyperedge at every slot of E_v (slot nnz holds 0)
+// Expanded lists are padded with -1 to a multiple of 4 nodes, so each is read
+// as independent 16-byte loads.
+constexpr int kXPad = 4;
+
+// padded size of the hyperedge at every slot of E_v (slot nnz holds 0)
 __global__ void k_xsize(int64_t nnz, const int64_t* __restrict__ edge_ptr,
                         const int32_t* __restrict__ node_edges, int64_t* out) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p < nnz) {
     const int32_t k = node_edges[p];
-    out[p] = edge_ptr[k + 1] - edge_ptr[k];
+    out[p] = (edge_ptr[k + 1] - edge_ptr[k] + kXPad - 1) / kXPad * kXPad;
   }
   if (p == 0) out[nnz] = 0;
 }
@@ -89,32 +93,53 @@ __global__ void k_xfill(int64_t nnz, const int64_t* __restrict__ edge_ptr,
   if (p >= nnz) return;
   const int32_t k = node_edges[p];
   const int64_t s = edge_ptr[k], c = edge_ptr[k + 1] - s;
-  const int64_t o = x64[p];
+  const int64_t o = x64[p], o1 = x64[p + 1];
   xoff[p] = uint32_t(o);
-  for (int64_t t = 0; t < c; ++t) xnodes[o + t] = edge_nodes[s + t];
+  for (int64_t t = 0; t < o1 - o; ++t) xnodes[o + t] = t < c ? edge_nodes[s + t] : -1;
 }
 
-// per hyperedge: +1 to hsize[b][|e|] for each heavy node b it holds and to
-// hpair[b1][b2][|e|] (both orders) for each pair of them
+// The first 8 entries of a padded list (entries past its end read as -1).
+__device__ __forceinline__ void load8(const int32_t* __restrict__ xnodes, uint32_t xs, uint32_t xe,
+                                      int4& q0, int4& q1) {
+  const int4* src = reinterpret_cast<const int4*>(xnodes + xs);
+  q0 = src[0];
+  q1 = xe - xs > uint32_t(kXPad) ? src[1] : make_int4(-1, -1, -1, -1);
+}
+
+// position of the heavy-index triple x0 < x1 < x2 among all such triples
+__device__ __forceinline__ int triple_index(int x0, int x1, int x2) {
+  return x2 * (x2 - 1) * (x2 - 2) / 6 + x1 * (x1 - 1) / 2 + x0;
+}
+constexpr int kHeavyTriples = kHeavyBits * (kHeavyBits - 1) * (kHeavyBits - 2) / 6;
+
+// per hyperedge of size c: +1 to hsize[b][c] for each heavy node b it holds,
+// to hpair[b1][b2][c] (both orders) for each pair and to htriple[{b1,b2,b3}][c]
+// for each triple of them
 __global__ void k_heavy_tables(int64_t E, const int64_t* __restrict__ edge_ptr,
                                const int32_t* __restrict__ edge_nodes,
                                const int8_t* __restrict__ heavy_bit, uint32_t* hsize,
-                               uint32_t* hpair) {
+                               uint32_t* hpair, uint32_t* htriple) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= E) return;
   const int64_t s = edge_ptr[e];
   const int c = int(edge_ptr[e + 1] - s);
-  unsigned long long seen = 0;
+  unsigned long long held = 0;
   for (int q = 0; q < c; ++q) {
     const int hb = heavy_bit[edge_nodes[s + q]];
-    if (hb < 0) continue;
-    atomicAdd(&hsize[hb * kSizeSlots + c], 1u);
-    for (unsigned long long m = seen; m; m &= m - 1) {
-      const int h2 = __ffsll((long long)m) - 1;
-      atomicAdd(&hpair[(hb * kHeavyBits + h2) * kSizeSlots + c], 1u);
-      atomicAdd(&hpair[(h2 * kHeavyBits + hb) * kSizeSlots + c], 1u);
+    if (hb >= 0) held |= 1ull << hb;
+  }
+  for (unsigned long long m0 = held; m0; m0 &= m0 - 1) {
+    const int x0 = __ffsll((long long)m0) - 1;
+    atomicAdd(&hsize[x0 * kSizeSlots + c], 1u);
+    for (unsigned long long m1 = m0 & (m0 - 1); m1; m1 &= m1 - 1) {
+      const int x1 = __ffsll((long long)m1) - 1;
+      atomicAdd(&hpair[(x0 * kHeavyBits + x1) * kSizeSlots + c], 1u);
+      atomicAdd(&hpair[(x1 * kHeavyBits + x0) * kSizeSlots + c], 1u);
+      for (unsigned long long m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) {
+        const int x2 = __ffsll((long long)m2) - 1;
+        atomicAdd(&htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots + c], 1u);
+      }
     }
-    seen |= 1ull << hb;
   }
 }
 
@@ -161,20 +186,35 @@ __global__ __launch_bounds__(256) void k_free_degree(
     const int64_t p = base[x] + (q - pre[x]);
     const int32_t k = node_edges[p];
     if (k == int32_t(i)) continue;
-    const uint32_t xs = xoff[p], c = xoff[p + 1] - xs;
+    const uint32_t xs = xoff[p], xe = xoff[p + 1];
+    int4 q0, q1;
+    load8(xnodes, xs, xe, q0, q1);
+    // e_k is owned here iff no node of e_k below v lies in e_i (nodes are
+    // ascending, so only the ones before v are tested)
     bool owned = true;
-    for (uint32_t t = 0; t < c; ++t) {
-      const int32_t u = xnodes[xs + t];
-      if (u >= v) break;
-      if (in_sorted(ei, a, u)) { owned = false; break; }
+    auto below = [&](int32_t u) {
+      if (u >= 0 && u < v && owned && in_sorted(ei, a, u)) owned = false;
+    };
+    below(q0.x); below(q0.y); below(q0.z); below(q0.w);
+    below(q1.x); below(q1.y); below(q1.z); below(q1.w);
+    for (uint32_t t = xs + 2 * kXPad; t < xe && owned; t += kXPad) {
+      const int4 q = *reinterpret_cast<const int4*>(xnodes + t);
+      if (q.x >= v) break;
+      below(q.x); below(q.y); below(q.z); below(q.w);
     }
     if (!owned) continue;
     ++cnt;
     if (k > int32_t(i)) ++ucnt;
-    if (c == uint32_t(a)) {
-      uint32_t hit = 0;
-      for (uint32_t t = 0; t < c; ++t) hit += in_sorted(ei, a, xnodes[xs + t]) ? 1u : 0u;
-      if (hit == c) dup = true;
+    if (xe - xs >= uint32_t(a) && xe - xs < uint32_t(a) + kXPad) {
+      // same padded length as e_i: a repeat iff e_k has a nodes, all in e_i
+      int c = 0, hit = 0;
+      for (uint32_t t = xs; t < xe; ++t) {
+        const int32_t u = xnodes[t];
+        if (u < 0) break;
+        ++c;
+        hit += in_sorted(ei, a, u) ? 1 : 0;
+      }
+      if (c == a && hit == a) dup = true;
     }
   }
   if (dup) atomicOr(flags, kFlagDup);
@@ -342,51 +382,81 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
 }
 
 // Enumeration: one wave per sampled pair (i, j).
+//
+// u = e_i ∪ e_j lives in a per-wave hash table of 128 buckets of 4 slots;
+// slot = ((node + 1) << 4) | flags, 0 = free, flags = in e_i (bit 0), in e_j
+// (bit 1), and the rank 1..3 of a skipped node (bits 2-3, 0 if walked).  A
+// lookup reads one bucket (16 bytes) and compares its four slots without
+// branching; a member whose bucket is full goes to a short overflow list.
 constexpr int kEnumWaves = 4;
-constexpr int kHash = 128;                 // open-addressing table of u = e_i ∪ e_j
-constexpr uint32_t kFI = 1, kFJ = 2, kFSkip = 4, kFW2 = 8;
+constexpr int kBuckets = 128;
+constexpr int kSkip = 3;                   // heavy lists counted in bulk
+constexpr int kPatterns = (1 << kSkip) - 1;
+constexpr uint32_t kFI = 1, kFJ = 2;
 constexpr int kBatch = 4;                  // samples taken from the queue at a time
 
 struct EnumLds {
-  int32_t hk[kHash];                       // node id, -1 = free
-  uint8_t hf[kHash];                       // kFI | kFJ | kFSkip | kFW2
+  uint4 tab[kBuckets];
+  uint32_t ovf[2 * MOCHY_MAX_EDGE];
   int32_t ei[MOCHY_MAX_EDGE], ej[MOCHY_MAX_EDGE];
   int32_t wn[2 * MOCHY_MAX_EDGE];          // walked nodes
   int64_t wb[2 * MOCHY_MAX_EDGE];          // node_ptr of each walked node
   int64_t pre[2 * MOCHY_MAX_EDGE + 1];     // prefix of walked list lengths
-  uint32_t tally[3 * kSizeSlots];          // walked e_k holding skipped nodes, by pattern and size
-  unsigned long long hist[kHistSlots];
+  uint32_t tally[kPatterns * kSizeSlots];  // walked e_k by skipped nodes held and size
+  uint32_t novf;
 };
 
-__device__ __forceinline__ uint32_t node_hash(int32_t z) {
+__device__ __forceinline__ uint32_t bucket_of(int32_t z) {
   return (uint32_t(z) * 2654435761u) >> 25;  // 7 bits
 }
 
-__device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z) {
-  uint32_t h = node_hash(z);
-  for (;;) {
-    const int32_t kk = L.hk[h];
-    if (kk == z) return L.hf[h];
-    if (kk < 0) return 0u;
-    h = (h + 1) & (kHash - 1);
-  }
+// flags of node z (0 if z is not in u, or z = -1 padding)
+__device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t novf) {
+  const uint32_t key = uint32_t(z + 1) << 4;
+  const uint4 q = L.tab[bucket_of(z)];
+  uint32_t f = (q.x & ~15u) == key ? q.x : 0u;
+  f |= (q.y & ~15u) == key ? q.y : 0u;
+  f |= (q.z & ~15u) == key ? q.z : 0u;
+  f |= (q.w & ~15u) == key ? q.w : 0u;
+  for (uint32_t t = 0; t < novf; ++t) f |= (L.ovf[t] & ~15u) == key ? L.ovf[t] : 0u;
+  return f & 15u;
 }
 
-__global__ __launch_bounds__(256) void k_enum(
+// hyperedges of size c holding every heavy node of `mask` (bits index hb[])
+__device__ __forceinline__ int64_t superset_count(uint32_t mask, const int* hb, int c,
+                                                  const uint32_t* __restrict__ hsize,
+                                                  const uint32_t* __restrict__ hpair,
+                                                  const uint32_t* __restrict__ htriple) {
+  int h[kSkip], n = 0;
+  for (int x = 0; x < kSkip; ++x)
+    if (mask & (1u << x)) h[n++] = hb[x];
+  if (n == 1) return hsize[h[0] * kSizeSlots + c];
+  if (n == 2) return hpair[(h[0] * kHeavyBits + h[1]) * kSizeSlots + c];
+  int x0 = h[0], x1 = h[1], x2 = h[2];  // sort the three heavy indices
+  if (x0 > x1) { const int t = x0; x0 = x1; x1 = t; }
+  if (x1 > x2) { const int t = x1; x1 = x2; x2 = t; }
+  if (x0 > x1) { const int t = x0; x0 = x1; x1 = t; }
+  return htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots + c];
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_enum(
     int64_t cnt, int64_t E, const int2* __restrict__ pairs, const int64_t* __restrict__ edge_ptr,
     const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ node_ptr,
     const int8_t* __restrict__ heavy_bit, const uint32_t* __restrict__ xoff,
     const int32_t* __restrict__ xnodes, const uint32_t* __restrict__ hsize,
-    const uint32_t* __restrict__ hpair, const uint16_t* __restrict__ code_to_id3,
-    unsigned long long* queue, unsigned long long* hist_out, int32_t* flags) {
+    const uint32_t* __restrict__ hpair, const uint32_t* __restrict__ htriple,
+    const uint16_t* __restrict__ code_to_id3, unsigned long long* queue,
+    unsigned long long* hist_out, int32_t* flags) {
   __shared__ uint16_t lut[kNumCodes];
+  __shared__ unsigned long long hist[kHistSlots];  // shared by the block's waves
   __shared__ EnumLds lds[kEnumWaves];
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
+  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0ull;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   EnumLds& L = lds[wave];
-  for (int t = lane; t < kHash; t += kWave) L.hk[t] = -1;
-  for (int t = lane; t < 3 * kSizeSlots; t += kWave) L.tally[t] = 0u;
-  for (int t = lane; t < kHistSlots; t += kWave) L.hist[t] = 0ull;
+  for (int t = lane; t < kBuckets; t += kWave) L.tab[t] = make_uint4(0u, 0u, 0u, 0u);
+  for (int t = lane; t < kPatterns * kSizeSlots; t += kWave) L.tally[t] = 0u;
+  if (lane == 0) L.novf = 0u;
   __syncthreads();
   bool bad = false;
   for (;;) {
@@ -418,34 +488,35 @@ __global__ __launch_bounds__(256) void k_enum(
       const bool mem = u >= 0;
       const uint32_t wij = uint32_t(__popcll(__ballot(lane < a && (f & kFJ))));
       int64_t nb = 0, du = 0;
-      int hb = -1;
+      int hbit = -1;
       if (mem) {
         nb = node_ptr[u];
         du = node_ptr[u + 1] - nb;
-        hb = heavy_bit[u];
+        hbit = heavy_bit[u];
       }
-      // the two heavy members with the longest lists are not walked
-      const uint64_t key = (mem && hb >= 0) ? ((uint64_t(du) << 6) | uint64_t(lane)) : 0ull;
-      const uint64_t k1 = wave_max_u64(key);
-      const int l1 = k1 ? int(k1 & 63) : -1;
-      const uint64_t k2 = wave_max_u64(lane == l1 ? 0ull : key);
-      const int l2 = k2 ? int(k2 & 63) : -1;
-      if (lane == l1) f |= kFSkip;
-      if (lane == l2) f |= kFSkip | kFW2;
-      const int hb1 = l1 >= 0 ? __shfl(hb, l1) : -1;
-      const int hb2 = l2 >= 0 ? __shfl(hb, l2) : -1;
-      const uint32_t f1 = l1 >= 0 ? uint32_t(__shfl(int(f), l1)) : 0u;
-      const uint32_t f2 = l2 >= 0 ? uint32_t(__shfl(int(f), l2)) : 0u;
+      // the kSkip heavy members with the longest lists are not walked
+      uint64_t key = (mem && hbit >= 0) ? ((uint64_t(du) << 6) | uint64_t(lane)) : 0ull;
+      int nskip = 0;
+      int hb[kSkip] = {-1, -1, -1};
+      uint32_t sf[kSkip] = {0u, 0u, 0u};  // in-e_i / in-e_j flags of the skipped nodes
+      for (int x = 0; x < kSkip; ++x) {
+        const uint64_t top = wave_max_u64(key);
+        if (!top) break;
+        const int l = int(top & 63);
+        if (lane == l) { f |= uint32_t(x + 1) << 2; key = 0ull; }
+        hb[x] = __shfl(hbit, l);
+        sf[x] = uint32_t(__shfl(int(f), l)) & 3u;
+        ++nskip;
+      }
       int slot = -1;
       if (mem) {
-        uint32_t h = node_hash(u);
-        for (;;) {
-          if (atomicCAS(&L.hk[h], -1, u) == -1) { slot = int(h); break; }
-          h = (h + 1) & (kHash - 1);
-        }
-        L.hf[slot] = uint8_t(f);
+        const uint32_t packed = (uint32_t(u + 1) << 4) | f;
+        uint32_t* bk = reinterpret_cast<uint32_t*>(&L.tab[bucket_of(u)]);
+        for (int t = 0; t < 4 && slot < 0; ++t)
+          if (atomicCAS(&bk[t], 0u, packed) == 0u) slot = t;
+        if (slot < 0) L.ovf[atomicAdd(&L.novf, 1u)] = packed;
       }
-      const bool walk = mem && !(f & kFSkip);
+      const bool walk = mem && (f >> 2) == 0u;
       const uint64_t wm = __ballot(walk);
       const int nw = __popcll(wm);
       const int wpos = __popcll(wm & ((1ull << lane) - 1ull));
@@ -457,67 +528,85 @@ __global__ __launch_bounds__(256) void k_enum(
       }
       if (lane == 0) L.pre[0] = 0;
       wave_sync();
+      const uint32_t novf = L.novf;
       const int64_t T = L.pre[nw];
       int x = 0;
       for (int64_t q = lane; q < T; q += kWave) {
         while (L.pre[x + 1] <= q) ++x;
         const int32_t v = L.wn[x];
         const int64_t p = L.wb[x] + (q - L.pre[x]);
-        const uint32_t xs = xoff[p], c = xoff[p + 1] - xs;
-        uint32_t wi = 0, wj = 0, t3 = 0, pat = 0;
+        const uint32_t xs = xoff[p], xe = xoff[p + 1];
+        int4 q0, q1;
+        load8(xnodes, xs, xe, q0, q1);
+        uint32_t c = 0, wi = 0, wj = 0, t3 = 0, pat = 0;
         int32_t first = -1;
-        for (uint32_t t = 0; t < c; ++t) {
-          const int32_t z = xnodes[xs + t];
-          const uint32_t ff = lookup(L, z);
-          if (!ff) continue;
-          wi += ff & kFI;
+        auto take = [&](int32_t z) {
+          const uint32_t ff = lookup(L, z, novf);
+          const uint32_t rk = ff >> 2;
+          c += z >= 0 ? 1u : 0u;
+          wi += ff & 1u;
           wj += (ff >> 1) & 1u;
           t3 += (ff & 3u) == 3u ? 1u : 0u;
-          if (ff & kFSkip) pat |= (ff & kFW2) ? 2u : 1u;
-          else if (first < 0) first = z;
+          pat |= rk ? (1u << (rk - 1u)) : 0u;
+          first = (first < 0 && ff && !rk) ? z : first;
+        };
+        take(q0.x); take(q0.y); take(q0.z); take(q0.w);
+        take(q1.x); take(q1.y); take(q1.z); take(q1.w);
+        for (uint32_t t = xs + 2 * kXPad; t < xe; t += kXPad) {
+          const int4 qq = *reinterpret_cast<const int4*>(xnodes + t);
+          take(qq.x); take(qq.y); take(qq.z); take(qq.w);
         }
         // e_k = e_i or e_j: a hyperedge of that size inside it (no repeats)
         const bool self = (c == uint32_t(a) && wi == c) || (c == uint32_t(b) && wj == c);
         if (first != v || self) continue;  // counted at the smallest walked node of e_k
-        atomicAdd(&L.hist[lut[triple_code(a, b, c, wij, wj, wi, t3)]], 1ull);
+        atomicAdd(&hist[lut[triple_code(a, b, c, wij, wj, wi, t3)]], 1ull);
         if (pat) atomicAdd(&L.tally[(pat - 1) * kSizeSlots + c], 1u);
       }
       wave_sync();
-      // bulk: e_k whose only members of u are skipped nodes, by size c = lane
-      if (l1 >= 0 && lane >= 1 && lane <= MOCHY_MAX_EDGE) {
+      // bulk: e_k whose members of u are all skipped nodes (pattern T of them),
+      // by size c = lane; inclusion-exclusion over the supersets of T
+      if (nskip > 0 && lane >= 1 && lane <= MOCHY_MAX_EDGE) {
         const int c = lane;
-        const int64_t h1 = hsize[hb1 * kSizeSlots + c];
-        const int64_t h2 = l2 >= 0 ? int64_t(hsize[hb2 * kSizeSlots + c]) : 0;
-        const int64_t pc = l2 >= 0 ? int64_t(hpair[(hb1 * kHeavyBits + hb2) * kSizeSlots + c]) : 0;
-        int64_t n[3] = {h1 - pc - L.tally[c], h2 - pc - L.tally[kSizeSlots + c],
-                        pc - L.tally[2 * kSizeSlots + c]};
-        // e_i and e_j themselves are in the tables but not in N_i ∪ N_j
-        const uint32_t pi = ((f1 & kFI) ? 1u : 0u) | ((f2 & kFI) ? 2u : 0u);
-        const uint32_t pj = ((f1 & kFJ) ? 1u : 0u) | ((f2 & kFJ) ? 2u : 0u);
-        if (pi && a == c) n[pi - 1] -= 1;
-        if (pj && b == c) n[pj - 1] -= 1;
-        for (uint32_t pat = 1; pat <= 3; ++pat) {
-          const int64_t m = n[pat - 1];
-          if (m == 0) continue;
-          if (m < 0) { bad = true; continue; }
-          const uint32_t g1 = (pat & 1u) ? f1 : 0u, g2 = (pat & 2u) ? f2 : 0u;
-          const uint32_t sik = (g1 & kFI ? 1u : 0u) + (g2 & kFI ? 1u : 0u);
-          const uint32_t sjk = (g1 & kFJ ? 1u : 0u) + (g2 & kFJ ? 1u : 0u);
-          const uint32_t tt = ((g1 & 3u) == 3u ? 1u : 0u) + ((g2 & 3u) == 3u ? 1u : 0u);
-          atomicAdd(&L.hist[lut[triple_code(a, b, uint32_t(c), wij, sjk, sik, tt)]],
-                    (unsigned long long)m);
+        const uint32_t all = (1u << nskip) - 1u;
+        int64_t F[kPatterns + 1];
+        for (uint32_t m = 1; m <= all; ++m) F[m] = superset_count(m, hb, c, hsize, hpair, htriple);
+        uint32_t pi = 0, pj = 0;  // skipped nodes held by e_i, e_j
+        for (int y = 0; y < nskip; ++y) {
+          pi |= (sf[y] & kFI) ? 1u << y : 0u;
+          pj |= (sf[y] & kFJ) ? 1u << y : 0u;
+        }
+        for (uint32_t m = 1; m <= all; ++m) {
+          int64_t n = 0;
+          for (uint32_t sup = m; sup <= all; sup = (sup + 1) | m)  // supersets of m within all
+            n += (__popc(sup ^ m) & 1) ? -F[sup] : F[sup];
+          n -= L.tally[(m - 1) * kSizeSlots + c];
+          // e_i and e_j themselves are in the tables but not in N_i ∪ N_j
+          if (pi == m && a == c) n -= 1;
+          if (pj == m && b == c) n -= 1;
+          if (n == 0) continue;
+          if (n < 0) { bad = true; continue; }
+          uint32_t sik = 0, sjk = 0, tt = 0;
+          for (int y = 0; y < nskip; ++y) {
+            if (!(m & (1u << y))) continue;
+            sik += sf[y] & kFI;
+            sjk += (sf[y] >> 1) & 1u;
+            tt += sf[y] == 3u ? 1u : 0u;
+          }
+          atomicAdd(&hist[lut[triple_code(a, b, uint32_t(c), wij, sjk, sik, tt)]],
+                    (unsigned long long)n);
         }
       }
       wave_sync();
-      if (slot >= 0) L.hk[slot] = -1;
-      for (int t = lane; t < 3 * kSizeSlots; t += kWave) L.tally[t] = 0u;
+      if (mem && slot >= 0) reinterpret_cast<uint32_t*>(&L.tab[bucket_of(u)])[slot] = 0u;
+      for (int t = lane; t < kPatterns * kSizeSlots; t += kWave) L.tally[t] = 0u;
+      if (lane == 0) L.novf = 0u;
       wave_sync();
     }
   }
   if (bad) atomicOr(flags, 2);
-  wave_sync();
-  for (int t = lane; t < kHistSlots; t += kWave)
-    if (L.hist[t]) atomicAdd(&hist_out[t], L.hist[t]);
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x)
+    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
 }
 
 }  // namespace
@@ -527,6 +616,10 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
   if (g->ng != 1) {
     ctx->err = "the line-graph-free mode takes single graphs";
     return MOCHY_EUNSUPPORTED;
+  }
+  if (g->V >= (int64_t(1) << 28)) {
+    ctx->err = "the line-graph-free mode takes fewer than 2^28 nodes";
+    return MOCHY_ERANGE;
   }
   mochy_status rc = project_incidence(ctx, g);
   if (rc != MOCHY_OK) return rc;
@@ -543,11 +636,13 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
       (rc = device_alloc(ctx, (void**)&g->deg, size_t(std::max<int64_t>(E, 1)) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->hsize, size_t(kHeavyBits) * kSizeSlots * 4)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->hpair,
-                         size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4)) != MOCHY_OK) {
+                         size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&g->htriple, size_t(kHeavyTriples) * kSizeSlots * 4)) != MOCHY_OK) {
     cleanup();
     return rc;
   }
-  g->bytes += size_t(nnz + 1) * 4 + size_t(E) * 8 + size_t(kHeavyBits) * (kHeavyBits + 1) * kSizeSlots * 4;
+  g->bytes += size_t(nnz + 1) * 4 + size_t(E) * 8 +
+              size_t(kHeavyBits * (kHeavyBits + 1) + kHeavyTriples) * kSizeSlots * 4;
 
   // expanded lists
   phase_begin(ctx, kPhRows);
@@ -558,7 +653,7 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
   const int64_t xtotal = ctx->h_small[0];
   if (xtotal >= (int64_t(1) << 32)) {
     cleanup();
-    ctx->err = "line-graph-free mode: sum of squared hyperedge sizes reaches 2^32";
+    ctx->err = "line-graph-free mode: the per-slot node lists would exceed 2^32 entries";
     return MOCHY_ERANGE;
   }
   if ((rc = device_alloc(ctx, (void**)&g->xnodes, size_t(std::max<int64_t>(xtotal, 1)) * 4)) != MOCHY_OK) {
@@ -571,9 +666,10 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
                                                                   g->xnodes);
   MOCHY_HIP(hipMemsetAsync(g->hsize, 0, size_t(kHeavyBits) * kSizeSlots * 4, st));
   MOCHY_HIP(hipMemsetAsync(g->hpair, 0, size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4, st));
+  MOCHY_HIP(hipMemsetAsync(g->htriple, 0, size_t(kHeavyTriples) * kSizeSlots * 4, st));
   if (E > 0)
     k_heavy_tables<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit,
-                                                   g->hsize, g->hpair);
+                                                   g->hsize, g->hpair, g->htriple);
   phase_end(ctx, kPhRows);
 
   // degrees and the hyperwedge order
@@ -663,7 +759,8 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
     phase_begin(ctx, kPhSample);
     k_enum<<<unsigned(ctx->num_cus) * 8u, kEnumWaves * kWave, 0, st>>>(
         cnt, E, pairs, g->edge_ptr, g->edge_nodes, g->node_ptr, g->heavy_bit, g->xoff, g->xnodes,
-        g->hsize, g->hpair, ctx->d_code_to_id3, enum_queue, (unsigned long long*)d_hist, flags);
+        g->hsize, g->hpair, g->htriple, ctx->d_code_to_id3, enum_queue,
+        (unsigned long long*)d_hist, flags);
     phase_end(ctx, kPhSample);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
