@@ -7,6 +7,7 @@ back to anything else.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import os
 
 import numpy as np
@@ -120,9 +121,12 @@ class Context:
         if st != MOCHY_OK:
             raise MochyError(st, "mochy_ctx_create")
         self.handle = h
+        self._graphs = weakref.WeakSet()  # graphs projected on this context
 
     def close(self):
         if self.handle:
+            for g in list(self._graphs):  # a graph may not outlive its context
+                g.close()
             lib().mochy_ctx_destroy(self.handle)
             self.handle = None
 
@@ -175,6 +179,7 @@ class Graph:
                   "mochy_project")
         self.ctx, self.handle, self.num_hyperwedges = ctx, h, int(w.value)
         self.num_edges = int(c.num_edges)
+        ctx._graphs.add(self)
 
     def close(self):
         if self.handle:

@@ -383,17 +383,18 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
 
 // Enumeration: one wave per sampled pair (i, j).
 //
-// u = e_i ∪ e_j lives in a per-wave hash table of 128 buckets of 4 slots;
+// u = e_i ∪ e_j lives in a per-wave hash table of 64 buckets of 4 slots;
 // slot = ((node + 1) << 4) | flags, 0 = free, flags = in e_i (bit 0), in e_j
 // (bit 1), and the rank 1..3 of a skipped node (bits 2-3, 0 if walked).  A
 // lookup reads one bucket (16 bytes) and compares its four slots without
 // branching; a member whose bucket is full goes to a short overflow list.
 constexpr int kEnumWaves = 4;
-constexpr int kBuckets = 128;
+constexpr int kBuckets = 64;
 constexpr int kSkip = 3;                   // heavy lists counted in bulk
 constexpr int kPatterns = (1 << kSkip) - 1;
 constexpr uint32_t kFI = 1, kFJ = 2;
 constexpr int kBatch = 4;                  // samples taken from the queue at a time
+constexpr int kMaxChunks = kWave * (MOCHY_MAX_EDGE / kXPad);  // chunks of one window
 
 struct EnumLds {
   uint4 tab[kBuckets];
@@ -403,14 +404,22 @@ struct EnumLds {
   int64_t wb[2 * MOCHY_MAX_EDGE];          // node_ptr of each walked node
   int64_t pre[2 * MOCHY_MAX_EDGE + 1];     // prefix of walked list lengths
   uint32_t tally[kPatterns * kSizeSlots];  // walked e_k by skipped nodes held and size
+  // one window of 64 visits, split into 4-node chunks
+  uint32_t vx[kWave];                      // start of the visit's node list in xnodes
+  uint32_t vc[kWave];                      // its first chunk in the window
+  int32_t vv[kWave];                       // the walked node it was reached through
+  unsigned long long acc[kWave];           // packed sums of its chunks
+  uint8_t cmap[kMaxChunks];                // chunk -> visit (lane)
   uint32_t novf;
 };
 
 __device__ __forceinline__ uint32_t bucket_of(int32_t z) {
-  return (uint32_t(z) * 2654435761u) >> 25;  // 7 bits
+  return (uint32_t(z) * 2654435761u) >> 26;  // 6 bits
 }
 
-// flags of node z (0 if z is not in u, or z = -1 padding)
+// flags of node z (0 if z is not in u, or z = -1 padding); the overflow list
+// is scanned only for the (rare) samples that have one
+template <bool kOvf>
 __device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t novf) {
   const uint32_t key = uint32_t(z + 1) << 4;
   const uint4 q = L.tab[bucket_of(z)];
@@ -418,8 +427,110 @@ __device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t
   f |= (q.y & ~15u) == key ? q.y : 0u;
   f |= (q.z & ~15u) == key ? q.z : 0u;
   f |= (q.w & ~15u) == key ? q.w : 0u;
-  for (uint32_t t = 0; t < novf; ++t) f |= (L.ovf[t] & ~15u) == key ? L.ovf[t] : 0u;
+  if (kOvf)
+    for (uint32_t t = 0; t < novf; ++t) f |= (L.ovf[t] & ~15u) == key ? L.ovf[t] : 0u;
   return f & 15u;
+}
+
+// Packed per-visit sums (6 bits each): |e_k|, |e_k ∩ e_i|, |e_k ∩ e_j|,
+// |e_k ∩ e_i ∩ e_j|, walked members of u in e_k below the visit's node, and
+// (2 bits each) the three skipped nodes held.
+constexpr int kSc = 0, kSi = 6, kSj = 12, kSt = 18, kSb = 24, kSp = 30;
+
+template <bool kOvf>
+__device__ __forceinline__ unsigned long long chunk_sums(const EnumLds& L, int4 z4, int32_t v,
+                                                         uint32_t novf) {
+  unsigned long long s = 0;
+  auto one = [&](int32_t z) {
+    const uint32_t ff = lookup<kOvf>(L, z, novf);
+    const uint32_t rk = ff >> 2;
+    uint32_t w = z >= 0 ? 1u : 0u;
+    w += (ff & 1u) << kSi;
+    w += ((ff >> 1) & 1u) << kSj;
+    w += ((ff & 3u) == 3u ? 1u : 0u) << kSt;
+    w += (ff && !rk && z < v) ? 1u << kSb : 0u;
+    s += w;
+    s += rk ? 1ull << (kSp + 2 * (rk - 1u)) : 0ull;
+  };
+  one(z4.x); one(z4.y); one(z4.z); one(z4.w);
+  return s;
+}
+
+// Walks the lists of the non-skipped members of u for one sample, 64 visits
+// (flattened over the lists) at a time.  The node lists of a window's visits
+// are consecutive in xnodes within a list, so the window is cut into 4-node
+// chunks that the lanes take one each (coalesced 16-byte loads); a chunk's
+// sums go to its visit by an LDS add.  Then each lane classifies its own
+// visit: e_k is counted at its smallest walked member (no walked member of u
+// below the visit's node) and is neither e_i nor e_j; equal motif ids in a row
+// are summed in a register before the LDS add.
+template <bool kOvf>
+__device__ __forceinline__ void walk_lists(EnumLds& L, int lane, int64_t T, uint32_t a, uint32_t b,
+                                           uint32_t wij, uint32_t novf,
+                                           const uint32_t* __restrict__ xoff,
+                                           const int32_t* __restrict__ xnodes,
+                                           const uint16_t* lut, unsigned long long* hist) {
+  if (T <= 0) return;
+  int x = 0;
+  int64_t lend = L.pre[1];
+  int64_t base = L.wb[0];
+  int32_t v = L.wn[0];
+  uint32_t run_id = 0, run_n = 0;
+  for (int64_t q0 = 0; q0 < T; q0 += kWave) {
+    const int64_t q = q0 + lane;
+    uint32_t nch = 0, xs = 0;
+    if (q < T) {
+      while (lend <= q) {  // cursor to the list holding visit q
+        ++x;
+        lend = L.pre[x + 1];
+        base = L.wb[x] - L.pre[x];
+        v = L.wn[x];
+      }
+      xs = xoff[base + q];
+      nch = (xoff[base + q + 1] - xs) / kXPad;
+    }
+    uint32_t incl = nch;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t o = uint32_t(__shfl_up(int(incl), off));
+      if (lane >= off) incl += o;
+    }
+    const uint32_t first_chunk = incl - nch;
+    const uint32_t nchunks = uint32_t(__shfl(int(incl), kWave - 1));
+    L.vx[lane] = xs;
+    L.vc[lane] = first_chunk;
+    L.vv[lane] = v;
+    L.acc[lane] = 0ull;
+    for (uint32_t t = 0; t < nch; ++t) L.cmap[first_chunk + t] = uint8_t(lane);
+    wave_sync();
+    for (uint32_t k = lane; k < nchunks; k += kWave) {
+      const int owner = L.cmap[k];
+      const int4 z4 = *reinterpret_cast<const int4*>(xnodes + L.vx[owner] + (k - L.vc[owner]) * kXPad);
+      atomicAdd(&L.acc[owner], chunk_sums<kOvf>(L, z4, L.vv[owner], novf));
+    }
+    wave_sync();
+    if (q < T) {
+      const unsigned long long s = L.acc[lane];
+      const uint32_t c = uint32_t(s >> kSc) & 63u, wi = uint32_t(s >> kSi) & 63u;
+      const uint32_t wj = uint32_t(s >> kSj) & 63u, t3 = uint32_t(s >> kSt) & 63u;
+      const uint32_t below = uint32_t(s >> kSb) & 63u;
+      uint32_t pat = 0;
+      for (int y = 0; y < kSkip; ++y) pat |= ((s >> (kSp + 2 * y)) & 3ull) ? 1u << y : 0u;
+      // e_k = e_i or e_j: a hyperedge of that size inside it (no repeats)
+      const bool self = (c == a && wi == c) || (c == b && wj == c);
+      if (below == 0 && !self) {
+        const uint32_t id = lut[triple_code(a, b, c, wij, wj, wi, t3)];
+        if (id != run_id) {
+          if (run_n) atomicAdd(&hist[run_id], (unsigned long long)run_n);
+          run_id = id;
+          run_n = 0;
+        }
+        ++run_n;
+        if (pat) atomicAdd(&L.tally[(pat - 1) * kSizeSlots + c], 1u);
+      }
+    }
+    wave_sync();
+  }
+  if (run_n) atomicAdd(&hist[run_id], (unsigned long long)run_n);
 }
 
 // hyperedges of size c holding every heavy node of `mask` (bits index hb[])
@@ -530,38 +641,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
       wave_sync();
       const uint32_t novf = L.novf;
       const int64_t T = L.pre[nw];
-      int x = 0;
-      for (int64_t q = lane; q < T; q += kWave) {
-        while (L.pre[x + 1] <= q) ++x;
-        const int32_t v = L.wn[x];
-        const int64_t p = L.wb[x] + (q - L.pre[x]);
-        const uint32_t xs = xoff[p], xe = xoff[p + 1];
-        int4 q0, q1;
-        load8(xnodes, xs, xe, q0, q1);
-        uint32_t c = 0, wi = 0, wj = 0, t3 = 0, pat = 0;
-        int32_t first = -1;
-        auto take = [&](int32_t z) {
-          const uint32_t ff = lookup(L, z, novf);
-          const uint32_t rk = ff >> 2;
-          c += z >= 0 ? 1u : 0u;
-          wi += ff & 1u;
-          wj += (ff >> 1) & 1u;
-          t3 += (ff & 3u) == 3u ? 1u : 0u;
-          pat |= rk ? (1u << (rk - 1u)) : 0u;
-          first = (first < 0 && ff && !rk) ? z : first;
-        };
-        take(q0.x); take(q0.y); take(q0.z); take(q0.w);
-        take(q1.x); take(q1.y); take(q1.z); take(q1.w);
-        for (uint32_t t = xs + 2 * kXPad; t < xe; t += kXPad) {
-          const int4 qq = *reinterpret_cast<const int4*>(xnodes + t);
-          take(qq.x); take(qq.y); take(qq.z); take(qq.w);
-        }
-        // e_k = e_i or e_j: a hyperedge of that size inside it (no repeats)
-        const bool self = (c == uint32_t(a) && wi == c) || (c == uint32_t(b) && wj == c);
-        if (first != v || self) continue;  // counted at the smallest walked node of e_k
-        atomicAdd(&hist[lut[triple_code(a, b, c, wij, wj, wi, t3)]], 1ull);
-        if (pat) atomicAdd(&L.tally[(pat - 1) * kSizeSlots + c], 1u);
-      }
+      if (novf == 0)
+        walk_lists<false>(L, lane, T, a, b, wij, 0u, xoff, xnodes, lut, hist);
+      else
+        walk_lists<true>(L, lane, T, a, b, wij, novf, xoff, xnodes, lut, hist);
       wave_sync();
       // bulk: e_k whose members of u are all skipped nodes (pattern T of them),
       // by size c = lane; inclusion-exclusion over the supersets of T
