@@ -1,6 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark: exact h-motif / 3h-motif counting (MoCHy-E) on one MI355X.
 
+--workload medium-exact (default) is described below; --workload large-aplus
+times MoCHy-A+ on the large hypergraph without a stored line graph, and
+--workload batched-cp the batched significance/CP call against sequential
+calls (see the functions of the same names).
+
 Workload: the medium synthetic hypergraph (20,000 nodes, 100,000 drawn
 hyperedges, sizes 2..25 with P(s) ~ s^-2.5, Zipf(1.0) node popularity,
 seed 1, duplicates removed).  Its CSR is resident in HBM before timing.
@@ -113,11 +118,168 @@ def cpu_baseline(h, seconds):
     }
 
 
+def device_csr(h):
+    import torch
+    return (torch.from_numpy(h.edge_ptr).cuda(), torch.from_numpy(h.edge_nodes).cuda(), h.num_nodes)
+
+
+def large_aplus(args):
+    """MoCHy-A+ on the large hypergraph without a stored line graph: one step =
+    projection (validation, transpose, per-slot node lists, degrees, hyperwedge
+    order) + r samples (draw, group by row, pick e_j, enumerate N_i ∪ N_j)."""
+    import numpy as np
+    import torch
+    import paper_2310_15668_amd as M
+    from paper_2310_15668_amd import _lib
+    from workloads import make_config
+
+    h = make_config("large")
+    log(f"workload |E|={h.num_edges} |V|={h.num_nodes} nnz={h.nnz}")
+    dp, dn, V = device_csr(h)
+    torch.cuda.synchronize()
+    ctx = M.Context(0, torch.cuda.current_stream().cuda_stream)
+    g = M.mochy_project(ctx, dp, dn, V)
+    W = g.num_hyperwedges
+    st = M.mochy_graph_stats(ctx, g)
+    g.close()
+    r = args.samples if args.samples else W * 5 // 100
+    log(f"|wedges|={W} r={r} ({100.0 * r / W:.3g}% of the hyperwedges)")
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        g = M.mochy_project(ctx, dp, dn, V)
+        M.mochy_count_sampled(ctx, g, min(r, 1 << 22), args.seed)
+        g.close()
+    phase_sum = {k: 0.0 for k in _lib.PHASES}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        log(f"step {s + 1}/{args.steps}")
+        g = M.mochy_project(ctx, dp, dn, V)
+        for k, v in M.mochy_phase_ms(ctx).items():
+            phase_sum[k] += v
+        # samples [0, r) in calls of at most 2^28 (consecutive Philox counters,
+        # so the hits add up to one call's); est = hits * |wedges| / (w * r)
+        raw26 = np.zeros(26, dtype=np.int64)
+        est26 = np.zeros(26)
+        for n0 in range(0, r, 1 << 28):
+            rr = min(1 << 28, r - n0)
+            c26, e26, _, _ = M.mochy_count_sampled(ctx, g, rr, args.seed, n0)
+            raw26 += c26
+            est26 += e26 * (rr / r)
+            for k, v in M.mochy_phase_ms(ctx).items():
+                phase_sum[k] += v
+            log(f"  samples {n0 + rr}/{r}")
+        g.close()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    K = max(args.steps, 1)
+    pairs = int(raw26.sum())
+    enum_ms = phase_sum["sample_enum"] / K
+    model = 24  # bytes per (sample, e_k) pair: 16 + 4 * min size, sizes >= 2
+    achieved = model * pairs / (enum_ms * 1e-3) / 1e9
+    out = {
+        "metric": "(sample, e_k) pairs classified/s (MoCHy-A+)",
+        "value": pairs / (dt / K), "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3 / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "large sampled MoCHy-A+: 1,000,000 nodes, 2,000,000 drawn hyperedges "
+                               "(duplicates removed), sizes 2..25 P(s)~s^-2.8, Zipf(0.9), seed 2; "
+                               "no stored line graph",
+                   "hyperedges": st["num_edges"], "hyperwedges": W, "samples": r,
+                   "sample_fraction": r / W, "seed": args.seed, "max_line_degree": st["max_line_degree"],
+                   "samples_per_s": r / (dt / K), "estimated_connected_triples": float(est26.sum()),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "k_enum (enumeration of N_i ∪ N_j)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "model": "16 + 4*min(|e_i|,|e_j|,|e_k|) >= 24 bytes per (sample, e_k) pair",
+                     "kernel_ms": enum_ms, "pairs_per_s": pairs / (enum_ms * 1e-3)},
+        "phases_ms": {k: v / K for k, v in phase_sum.items() if v},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batched_cp(args):
+    """Significance and CP of the batched base hypergraph against 64
+    stub-matched copies: one mochy_profile call (all 65 graphs projected and
+    counted together) versus 65 sequential project + count calls."""
+    import numpy as np
+    import torch
+    import paper_2310_15668_amd as M
+    from workloads import make_config, stub_matching_copy
+    from workloads.generators import BATCHED_COPY_SEEDS
+
+    base = make_config("batched_base", scale=args.scale)
+    graphs = [base] + [stub_matching_copy(base, s) for s in BATCHED_COPY_SEEDS]
+    log(f"scale {args.scale}: base |E|={base.num_edges}, {len(graphs)} graphs, "
+        f"{sum(g.num_edges for g in graphs)} hyperedges in all")
+    dev = [device_csr(g) for g in graphs]
+    torch.cuda.synchronize()
+    ctx = M.Context(0, torch.cuda.current_stream().cuda_stream)
+
+    def sequential():
+        rows = []
+        for p, n, V in dev:
+            g = M.mochy_project(ctx, p, n, V)
+            c26, c431 = M.mochy_count_exact(ctx, g)
+            g.close()
+            rows.append(np.concatenate([c26, c431]))
+        return np.array(rows)
+
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        M.mochy_profile(ctx, dev[:3])
+    times_b, times_s = [], []
+    for s in range(args.steps):
+        log(f"step {s + 1}/{args.steps}: batched")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        counts, sig26, cp26, sig431, cp431 = M.mochy_profile(ctx, dev)
+        torch.cuda.synchronize()
+        times_b.append(time.perf_counter() - t0)
+        log(f"step {s + 1}/{args.steps}: sequential")
+        t0 = time.perf_counter()
+        seq = sequential()
+        torch.cuda.synchronize()
+        times_s.append(time.perf_counter() - t0)
+        if not (seq == counts).all():
+            raise SystemExit("batched and sequential counts differ")
+    ctx.close()
+    tb, ts = min(times_b), min(times_s)
+    triples = int(counts[:, :26].sum())
+    out = {
+        "metric": "batched CP speedup over 65 sequential project+count calls",
+        "value": ts / tb, "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched CP: base hypergraph (50,000 nodes, 150,000 drawn hyperedges, "
+                               f"sizes 2..20 P(s)~s^-2.5, Zipf(1.1), seed 3) and 64 stub-matched copies "
+                               f"(seeds 100..163), all scaled by {args.scale}",
+                   "scale": args.scale, "graphs": len(graphs),
+                   "hyperedges": [g.num_edges for g in graphs][:3] + ["..."],
+                   "connected_triples_all_graphs": triples, "parallelism": "single GPU"},
+        "batched_s": tb, "sequential_s": ts,
+        "batched_triples_per_s": triples / tb, "sequential_triples_per_s": triples / ts,
+        "identical_counts": True,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 3; 1 for large-aplus)")
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="medium-exact",
+                    choices=["medium-exact", "large-aplus", "batched-cp"])
+    ap.add_argument("--samples", type=int, default=0,
+                    help="large-aplus: samples per step (default 5%% of the hyperwedges)")
+    ap.add_argument("--seed", type=int, default=2, help="large-aplus: Philox key")
+    ap.add_argument("--scale", type=float, default=0.2,
+                    help="batched-cp: scale of the base hypergraph and its copies")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -125,12 +287,20 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build counts motifs on one device "
+        print("bench.py runs on exactly one GPU: motifs are counted on one device "
               "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 1 if args.workload == "large-aplus" else 3
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "large-aplus":
+        large_aplus(args)
+        return
+    if args.workload == "batched-cp":
+        batched_cp(args)
         return
 
     import numpy as np
