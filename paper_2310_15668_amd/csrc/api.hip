@@ -195,13 +195,35 @@ extern "C" mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms) {
   return MOCHY_OK;
 }
 
+// Graph and scratch buffers are stream-ordered allocations on the context's
+// stream when the device has memory pools, so that a free never waits for
+// work queued by other contexts on other streams.
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
-  const hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+  const size_t n = std::max<size_t>(bytes, 8);
+  const hipError_t e = ctx->async_alloc ? hipMallocAsync(p, n, ctx->stream) : hipMalloc(p, n);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+    return MOCHY_ENOMEM;
+  }
+  return MOCHY_OK;
+}
+
+void device_free(mochy_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->async_alloc) (void)hipFreeAsync(p, ctx->stream);
+  else (void)hipFree(p);
+}
+
+// Buffers that live as long as the context.
+static mochy_status ctx_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    ctx->err = "device allocation failed";
     return MOCHY_ENOMEM;
   }
   return MOCHY_OK;
@@ -230,13 +252,17 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   const PatternTables& pt = pattern_tables();
   int32_t parent[kHistSlots];
   for (int t = 0; t < kHistSlots; ++t) parent[t] = pt.id3_to_id26[t];
-  if (device_alloc(ctx, (void**)&ctx->d_code_to_id3, sizeof(pt.code_to_id3)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_id3_to_id26, sizeof(parent)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_flags, 16 * sizeof(int32_t)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_small, 512 * sizeof(int64_t)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_open26, 27 * sizeof(int32_t)) != MOCHY_OK ||
-      device_alloc(ctx, (void**)&ctx->d_dbl, 512 * sizeof(double)) != MOCHY_OK)
+  if (ctx_alloc(ctx, (void**)&ctx->d_code_to_id3, sizeof(pt.code_to_id3)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_id3_to_id26, sizeof(parent)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_flags, 16 * sizeof(int32_t)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_small, 512 * sizeof(int64_t)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_open26, 27 * sizeof(int32_t)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_dbl, 512 * sizeof(double)) != MOCHY_OK)
     return fail(MOCHY_ENOMEM);
+  int pools = 0;
+  ctx->async_alloc = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) ==
+                         hipSuccess && pools != 0;
+  (void)hipGetLastError();
   if (hipHostMalloc((void**)&ctx->h_dbl, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
   if (hipHostMalloc((void**)&ctx->h_small, 512 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
@@ -275,15 +301,15 @@ extern "C" const char* mochy_last_error(const mochy_ctx* ctx) { return ctx ? ctx
 
 extern "C" void mochy_graph_free(mochy_graph* g) {
   if (!g) return;
-  if (g->ctx) {
-    (void)hipSetDevice(g->ctx->device);
-    (void)hipStreamSynchronize(g->ctx->stream);
-  }
+  if (g->ctx) (void)hipSetDevice(g->ctx->device);  // frees are ordered on the context stream
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
                   g->hpair,    g->htriple};
-  for (void* b : bufs) (void)hipFree(b);
+  for (void* b : bufs) {
+    if (g->ctx) device_free(g->ctx, b);
+    else (void)hipFree(b);
+  }
   delete g;
 }
 
@@ -603,7 +629,7 @@ extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const 
   double* d_out = nullptr;      // sig26, cp26, sig431, cp431
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&d_all, size_t(num_graphs) * kHistSlots * 8)) != MOCHY_OK) return rc;
-  auto cleanup = [&]() { (void)hipFree(d_all); (void)hipFree(d_counts); (void)hipFree(d_out); };
+  auto cleanup = [&]() { device_free(ctx, d_all); device_free(ctx, d_counts); device_free(ctx, d_out); };
   if ((rc = device_alloc(ctx, (void**)&d_counts, size_t(num_graphs) * per * 8)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&d_out, 2 * per * 8)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = profile_counts(ctx, graphs, 0, num_graphs, d_all)) != MOCHY_OK) { cleanup(); return rc; }

@@ -30,6 +30,7 @@ struct mochy_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
@@ -142,8 +143,9 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
                             int64_t n0, int64_t* d_hist);
 
-// api.hip helpers
+// api.hip helpers: allocation and release ordered on the context stream
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);
+void device_free(mochy_ctx* ctx, void* p);
 
 // Largest graph (hyperedges) whose row bitmap and rank table fit in LDS.
 constexpr int64_t kMaxGraphEdges = 200000;

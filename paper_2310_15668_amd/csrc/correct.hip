@@ -227,7 +227,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* poff = ocount + (E + 1);
   int64_t* tmp = poff + (E + 1);
   int32_t* owners = (int32_t*)(buf + n64 * 8);
-  auto done = [&](mochy_status s) { (void)hipFree(buf); return s; };
+  auto done = [&](mochy_status s) { device_free(ctx, buf); return s; };
   MOCHY_HIP(hipMemsetAsync(buf, 0, (size_t(E) + 1 + size_t(E + 1)) * 8, st));
   const unsigned wblocks = blocks(V * 64, 256);
   k_light_pairs<false><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
@@ -247,10 +247,10 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int32_t* partners = nullptr;
   if ((rc = device_alloc(ctx, (void**)&eoff, size_t(E) * 8)) != MOCHY_OK) return done(rc);
   if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) {
-    (void)hipFree(eoff);
+    device_free(ctx, eoff);
     return done(rc);
   }
-  auto done2 = [&](mochy_status s) { (void)hipFree(eoff); (void)hipFree(partners); return done(s); };
+  auto done2 = [&](mochy_status s) { device_free(ctx, eoff); device_free(ctx, partners); return done(s); };
   // scatter owner offsets to hyperedge ids, reset counters, fill
   k_owner_offsets<<<blocks(nowners, 256), 256, 0, st>>>(nowners, owners, poff, eoff);
   MOCHY_HIP(hipMemsetAsync(pcount, 0, size_t(E) * 8, st));

@@ -347,11 +347,11 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_end(ctx, kPhPairs);
   phase_begin(ctx, kPhCorrect);
   rc = correct_device(ctx, g, c0, c1, d_hist);
-  if (rc != MOCHY_OK) { (void)hipFree(scratch); return rc; }
+  if (rc != MOCHY_OK) { device_free(ctx, scratch); return rc; }
   phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
   phases_collect(ctx);
-  (void)hipFree(scratch);
+  device_free(ctx, scratch);
   return MOCHY_OK;
 }

@@ -711,7 +711,7 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
   int64_t* tmp = nullptr;
   int64_t* x64 = nullptr;
   int64_t* up_len = nullptr;
-  auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(x64); (void)hipFree(up_len); };
+  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, x64); device_free(ctx, up_len); };
   if ((rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(std::max(nnz, E) + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&x64, size_t(nnz + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&up_len, size_t(E + 1) * 8)) != MOCHY_OK ||
@@ -799,7 +799,7 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
   unsigned long long* ctr = nullptr;  // [0] nkeys | select queue, [1] enum queue
   auto cleanup = [&]() {
     void* bufs[] = {key_i, key_m, sm, keys, pairs, bcnt, boff, tmp, cursor, ctr};
-    for (void* p : bufs) (void)hipFree(p);
+    for (void* p : bufs) device_free(ctx, p);
   };
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&key_i, size_t(C) * 4)) != MOCHY_OK ||

@@ -274,7 +274,7 @@ mochy_status project_incidence(mochy_ctx* ctx, mochy_graph* g) {
   int64_t* cnt = nullptr;
   unsigned int* fill = nullptr;
   mochy_status rc;
-  auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(cnt); (void)hipFree(fill); };
+  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, cnt); device_free(ctx, fill); };
   if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&cnt, size_t(std::max(V, E) + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&fill, size_t(V + 1) * 4)) != MOCHY_OK) {
@@ -318,7 +318,7 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   const size_t tmpn = scan_tmp_elems(E + 1);
   int64_t* tmp = nullptr;
   int64_t* cnt = nullptr;
-  auto cleanup = [&]() { (void)hipFree(tmp); (void)hipFree(cnt); };
+  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, cnt); };
   if ((rc = device_alloc(ctx, (void**)&tmp, tmpn * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&cnt, size_t(E + 1) * 8)) != MOCHY_OK) {
     cleanup();

@@ -1,0 +1,197 @@
+"""Continuous-batching server for characteristic-profile requests.
+
+A request is a hypergraph and its randomized copies (host CSRs); its answer is
+their h-motif and 3h-motif counts, the significance (Eq. 1) and the
+characteristic profile (Eq. 2), computed by one ``mochy_profile`` call.
+
+The server keeps ``slots`` library contexts, each on its own HIP stream and
+driven by its own worker thread (the library calls release the GIL).  A
+waiting request is admitted as soon as a slot is free and its device-memory
+bound fits in what the running requests leave of the budget, so requests that
+arrive while others run start without waiting for them, and their kernels
+overlap on the device.  A request's CSRs are uploaded once at admission and
+stay resident until its answer is read back.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+
+import numpy as np
+
+from . import _lib
+
+
+def request_bytes(graphs) -> int:
+    """Upper bound of the device memory a request holds while it runs.
+
+    Per graph: incidence and transpose, per-row arrays, and the line graph
+    (4-byte column + 16-byte record per row entry, with |wedges| bounded by
+    sum_v C(deg(v), 2)).
+    """
+    total = 0
+    for ptr, nodes, num_nodes in graphs:
+        E = len(ptr) - 1
+        nnz = int(ptr[-1]) if E > 0 else 0
+        deg = np.bincount(np.asarray(nodes), minlength=int(num_nodes)).astype(np.int64)
+        wedges = int((deg * (deg - 1) // 2).sum())
+        total += 16 * (E + 1) + 8 * nnz + 9 * (int(num_nodes) + 1) + 40 * E + 2 * wedges * 20
+    return total
+
+
+class Admission:
+    """Admission policy (host only).
+
+    Waiting requests are kept in arrival order.  ``take`` scans them in order
+    and starts each one whose memory bound fits in the budget left by the
+    running requests, while slots remain.  Later requests may start ahead of
+    an earlier one that does not fit (backfill) until that one has waited
+    ``aging_s`` seconds; from then on nothing passes it.  A request whose bound
+    exceeds the whole budget starts when nothing else runs.
+    """
+
+    def __init__(self, budget: int, aging_s: float = 1.0):
+        self.budget = int(budget)
+        self.aging_s = float(aging_s)
+        self.waiting: deque = deque()  # (rid, nbytes, t_enqueued)
+        self.in_use = 0
+        self.running = 0
+
+    def add(self, rid, nbytes: int, now: float):
+        self.waiting.append((rid, int(nbytes), now))
+
+    def take(self, free_slots: int, now: float) -> list:
+        started = []
+        kept = deque()
+        blocked = False
+        while self.waiting:
+            rid, nb, t0 = self.waiting.popleft()
+            if free_slots == 0 or blocked:
+                kept.append((rid, nb, t0))
+                continue
+            fits = self.in_use + nb <= self.budget or (self.running == 0 and not started)
+            if fits:
+                started.append((rid, nb))
+                self.in_use += nb
+                self.running += 1
+                free_slots -= 1
+            else:
+                kept.append((rid, nb, t0))
+                if now - t0 >= self.aging_s:
+                    blocked = True  # an aged request: no backfill past it
+        self.waiting = kept
+        return started
+
+    def release(self, nbytes: int):
+        self.in_use -= int(nbytes)
+        self.running -= 1
+
+
+class Ticket:
+    """Handle of a submitted request; ``wait()`` returns its result dict."""
+
+    def __init__(self, rid, arrival: float):
+        self.rid = rid
+        self.arrival = arrival
+        self.start = None
+        self.done = None
+        self.result = None
+        self.error = None
+        self._ev = threading.Event()
+
+    def wait(self, timeout=None) -> dict:
+        if not self._ev.wait(timeout):
+            raise TimeoutError(f"request {self.rid} not finished")
+        if self.error is not None:
+            raise self.error
+        return self.result
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class CPServer:
+    """Serves profile requests on one device with ``slots`` concurrent streams."""
+
+    def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int | None = None,
+                 eps: float = 1.0, aging_s: float = 1.0):
+        if budget_bytes is None:
+            import torch
+            free, _ = torch.cuda.mem_get_info(device)
+            budget_bytes = int(0.8 * free)
+        self.eps = float(eps)
+        self._ctxs = [_lib.Context(device) for _ in range(slots)]
+        self._adm = Admission(budget_bytes, aging_s)
+        self._lock = threading.Lock()
+        self._pending = {}            # rid -> (ticket, graphs, nbytes)
+        self._free = list(range(slots))
+        self._work = [None] * slots
+        self._cv = [threading.Condition(self._lock) for _ in range(slots)]
+        self._stop = False
+        self._next = 0
+        self._threads = [threading.Thread(target=self._worker, args=(s,), daemon=True)
+                         for s in range(slots)]
+        for t in self._threads:
+            t.start()
+
+    def submit(self, graphs, arrival: float | None = None) -> Ticket:
+        """graphs: [(edge_ptr, edge_nodes, num_nodes), ...], graphs[0] the hypergraph."""
+        now = time.perf_counter()
+        nbytes = request_bytes(graphs)
+        with self._lock:
+            rid = self._next
+            self._next += 1
+            t = Ticket(rid, now if arrival is None else arrival)
+            self._pending[rid] = (t, list(graphs), nbytes)
+            self._adm.add(rid, nbytes, now)
+            self._dispatch(now)
+        return t
+
+    def _dispatch(self, now):
+        # called with the lock held
+        for rid, nb in self._adm.take(len(self._free), now):
+            s = self._free.pop()
+            self._work[s] = rid
+            self._cv[s].notify()
+
+    def _worker(self, s):
+        ctx = self._ctxs[s]
+        while True:
+            with self._lock:
+                while self._work[s] is None and not self._stop:
+                    self._cv[s].wait()
+                if self._stop and self._work[s] is None:
+                    return
+                rid = self._work[s]
+                ticket, graphs, nbytes = self._pending.pop(rid)
+            ticket.start = time.perf_counter()
+            try:
+                counts, sig26, cp26, sig431, cp431 = _lib.mochy_profile(ctx, graphs, self.eps)
+                ticket.result = dict(counts=counts, sig26=sig26, cp26=cp26, sig431=sig431, cp431=cp431)
+            except Exception as e:  # reported to the waiter
+                ticket.error = e
+            ticket.done = time.perf_counter()
+            with self._lock:
+                self._work[s] = None
+                self._free.append(s)
+                self._adm.release(nbytes)
+                self._dispatch(time.perf_counter())
+            ticket._ev.set()
+
+    def close(self):
+        with self._lock:
+            self._stop = True
+            for cv in self._cv:
+                cv.notify_all()
+        for t in self._threads:
+            t.join()
+        for c in self._ctxs:
+            c.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -18,4 +18,6 @@ from .generators import (  # noqa: F401
     CONFIGS,
     make_config,
     serving_request,
+    serving_copies,
+    poisson_arrivals,
 )

@@ -202,3 +202,14 @@ def serving_request(n: int, lo: int = 1_000, hi: int = 200_000) -> Hypergraph:
     num_edges = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
     num_nodes = max(25, int(round(0.4 * num_edges)))
     return powerlaw_hypergraph(num_nodes, num_edges, 2, 25, 2.5, 1.0, seed=1000 + n)
+
+
+def serving_copies(n: int, h: Hypergraph, copies: int = 8) -> list:
+    """The randomized copies of request ``n``: stub matching with seeds (1000 + n) * 64 + c."""
+    return [stub_matching_copy(h, (1000 + n) * 64 + c) for c in range(copies)]
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 4) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson stream of ``rate`` requests/s."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
