@@ -34,6 +34,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "exact.hip")
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_main_medium_counters.md")
+FREE_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "free.hip")
+ENUM_SUMMARY = os.path.join(ROOT, "profiles", "k_enum_large_aplus.md")
 WORKLOAD = ("medium exact MoCHy-E: 20000 nodes, 100000 drawn hyperedges (duplicates removed), "
             "sizes 2..25 P(s)~s^-2.5, Zipf(1.0) node popularity, seed 1")
 
@@ -48,18 +50,21 @@ def source_digest(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter
-    summary, or None if there is none or the kernel source changed since."""
-    if not os.path.exists(COUNTERS_SUMMARY):
+def measured_traffic(summary=None, source=None):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (default: the pair kernel's), or None if there is none or the
+    kernel source changed since the counters were taken."""
+    summary = summary or COUNTERS_SUMMARY
+    source = source or PAIR_KERNEL_SRC
+    if not os.path.exists(summary):
         return None
     vals = {}
-    with open(COUNTERS_SUMMARY) as f:
+    with open(summary) as f:
         for line in f:
             if ":" in line and line.strip().startswith("- "):
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != source_digest(PAIR_KERNEL_SRC):
+    if vals.get("kernel_source_sha256") != source_digest(source):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -194,7 +199,9 @@ def large_aplus(args):
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "k_enum (enumeration of N_i ∪ N_j)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(ENUM_SUMMARY, FREE_KERNEL_SRC),
+                     "traffic_launch": "one chunk of 2^25 samples",
                      "model": "16 + 4*min(|e_i|,|e_j|,|e_k|) >= 24 bytes per (sample, e_k) pair",
                      "kernel_ms": enum_ms, "pairs_per_s": pairs / (enum_ms * 1e-3)},
         "phases_ms": {k: v / K for k, v in phase_sum.items() if v},
