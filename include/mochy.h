@@ -77,6 +77,14 @@ void mochy_ctx_destroy(mochy_ctx* ctx);
 /* Text of the last error on this context ("" if none); owned by the context. */
 const char* mochy_last_error(const mochy_ctx* ctx);
 
+/* Options of a context; they change how results are computed, never the
+ * results.  MOCHY_EINVAL for an unknown option or value. */
+#define MOCHY_OPT_GROUPS 1  /* exact counting pairs groups of neighbours with equal region
+                               records, weighted by their sizes (1, default), or every
+                               pair of neighbours (0); with too little device memory
+                               for the groups it pairs every neighbour */
+mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
+
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
  * builds on the device the transposed incidence E_v (node -> hyperedges),
  * the full line graph rows N_{e_i} (ascending hyperedge ids) with

@@ -20,6 +20,7 @@ STATUS = {0: "MOCHY_OK", -1: "MOCHY_EINVAL", -2: "MOCHY_EDUP", -3: "MOCHY_ERANGE
           -4: "MOCHY_ENOMEM", -5: "MOCHY_EDEVICE", -6: "MOCHY_EUNSUPPORTED"}
 MOCHY_DEDUP = 1
 MOCHY_LG_FREE = 4
+MOCHY_OPT_GROUPS = 1
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 
@@ -27,7 +28,7 @@ MAX_EDGE = 32
 EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_project",
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
-            "mochy_graph_stats", "mochy_phase_ms")
+            "mochy_graph_stats", "mochy_phase_ms", "mochy_ctx_set_option")
 NUM_PHASES = 11
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
           "exact_correct", "sample_draw", "sample_enum", "profile_cp")
@@ -92,6 +93,8 @@ def lib():
     L.mochy_graph_stats.restype = ctypes.c_int
     L.mochy_phase_ms.argtypes = [vp, vp]
     L.mochy_phase_ms.restype = ctypes.c_int
+    L.mochy_ctx_set_option.argtypes = [vp, i32, i64]
+    L.mochy_ctx_set_option.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -141,6 +144,11 @@ class Context:
 
     def __exit__(self, *exc):
         self.close()
+
+    def set_option(self, option: int, value: int):
+        """mochy_ctx_set_option (e.g. MOCHY_OPT_GROUPS, 0 or 1)."""
+        self.check(lib().mochy_ctx_set_option(self.handle, int(option), int(value)),
+                   "mochy_ctx_set_option")
 
     def check(self, st, what):
         if st != MOCHY_OK:

@@ -299,6 +299,16 @@ extern "C" void mochy_ctx_destroy(mochy_ctx* ctx) {
 
 extern "C" const char* mochy_last_error(const mochy_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return MOCHY_EINVAL;
+  if (option == MOCHY_OPT_GROUPS && (value == 0 || value == 1)) {
+    ctx->group_neighbours = value != 0;
+    return MOCHY_OK;
+  }
+  ctx->err = "unknown option or value";
+  return MOCHY_EINVAL;
+}
+
 extern "C" void mochy_graph_free(mochy_graph* g) {
   if (!g) return;
   if (g->ctx) (void)hipSetDevice(g->ctx->device);  // frees are ordered on the context stream

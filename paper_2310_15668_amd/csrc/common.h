@@ -31,6 +31,7 @@ struct mochy_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
+  bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]

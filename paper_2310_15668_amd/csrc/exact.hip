@@ -50,12 +50,13 @@ constexpr int64_t kFlushVisits = int64_t(1) << 26;  // 32 lanes share a copy: co
 // `order` lists rows (-1 in unused slots); rstart = prefix sums of the rows'
 // block counts, so item q is block (nb - 1 - (q - rstart[k])) of row order[k].
 
-__global__ void k_sched_count(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
-                              const int32_t* __restrict__ row_graph, unsigned long long* nbhist) {
+__global__ void k_sched_count(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ row_ptr,
+                              int64_t min_len, const int32_t* __restrict__ row_graph,
+                              unsigned long long* nbhist) {
   const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= c1) return;
-  const int64_t d = lg_ptr[i + 1] - lg_ptr[i];
-  if (d < 2) return;
+  const int64_t d = row_ptr[i + 1] - row_ptr[i];
+  if (d < min_len) return;
   atomicAdd(&nbhist[int64_t(row_graph[i]) * NB + (d + kWave - 1) / kWave], 1ull);
 }
 
@@ -146,25 +147,25 @@ __global__ __launch_bounds__(1024) void k_sched_graphs(int32_t ng, int64_t c0, i
 
 // Blocks per slot of `order` (0 for unused slots), the input of rstart.
 __global__ void k_item_counts(int64_t n, const int32_t* __restrict__ order,
-                              const int64_t* __restrict__ lg_ptr, int64_t* nbk) {
+                              const int64_t* __restrict__ row_ptr, int64_t* nbk) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k > n) return;
   int64_t v = 0;
   if (k < n && order[k] >= 0) {
     const int32_t i = order[k];
-    v = (lg_ptr[i + 1] - lg_ptr[i] + kWave - 1) / kWave;
+    v = (row_ptr[i + 1] - row_ptr[i] + kWave - 1) / kWave;
   }
   nbk[k] = v;
 }
 
-__global__ void k_sched_scatter(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ lg_ptr,
-                                const int32_t* __restrict__ row_graph,
+__global__ void k_sched_scatter(int64_t c0, int64_t c1, int32_t NB, const int64_t* __restrict__ row_ptr,
+                                int64_t min_len, const int32_t* __restrict__ row_graph,
                                 const int64_t* __restrict__ cnt, const int64_t* __restrict__ seg,
                                 unsigned long long* fill, int32_t* order) {
   const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= c1) return;
-  const int64_t d = lg_ptr[i + 1] - lg_ptr[i];
-  if (d < 2) return;
+  const int64_t d = row_ptr[i + 1] - row_ptr[i];
+  if (d < min_len) return;
   const int64_t g = row_graph[i];
   const int64_t nb = (d + kWave - 1) / kWave;
   const unsigned long long slot = atomicAdd(&fill[g * NB + nb], 1ull);
@@ -296,7 +297,376 @@ __global__ __launch_bounds__(256) void k_exact_main(
   if (dirty_g >= 0) flush_wave(whist, lane, dirty_g, hist_out);
 }
 
+// ---------------------------------------------------------------------------
+// Neighbour groups.  The main kernel's class of a pair (j, k) of a centre,
+// and whether Algorithm 2 counts it, depend only on the two records: the
+// masks m (nodes of e_i held) and h (heavy nodes outside e_i) and the outside
+// counts o, where only min(o - R5, 2) is ever used and R5 <= popcount(h), so o
+// may be clamped to popcount(h) + 2.  Neighbours with equal (m, clamped o, h)
+// form a group; a group keeps N (members) and A (members above the centre).
+// Between two groups x != y the main kernel's count is N_x N_y if they are
+// disjoint (every pair counts) and A_x A_y otherwise (only pairs above the
+// centre count); inside a group it is C(A, 2) (members share their nodes of
+// e_i, so never disjoint).  Pairs sharing a light node are corrected from the
+// ungrouped records afterwards, as before.
+//
+// One 512-thread block per row groups the row's records in an LDS hash table
+// keyed by a 64-bit hash of the signature.  A row longer than the table is
+// cut into parts by the hash (records of one part per pass); a pass whose
+// table fills is redone with twice the parts.  After each pass every record
+// checks its signature against its slot's first member: two signatures with
+// one hash restart the row with another hash seed, so groups are exact.
+constexpr int kGroupThreads = 512;
+constexpr int kGroupSlots = 2048;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  // SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA'14)
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ull;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebull;
+  x ^= x >> 31;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t clamp_outside(const uint4& r) {
+  const uint32_t o = r.y & 0xffu;
+  const uint32_t cap = uint32_t(__popc(r.z) + __popc(r.w)) + 2u;
+  return o < cap ? o : cap;
+}
+
+__device__ __forceinline__ uint64_t sig_hash(const uint4& r, uint32_t o, uint64_t seed) {
+  uint64_t x = mix64(seed ^ (uint64_t(r.x) | (uint64_t(o) << 32)));
+  x = mix64(x ^ (uint64_t(r.z) | (uint64_t(r.w) << 32)));
+  return x | 1ull;  // 0 marks a free slot
+}
+
+constexpr int kGroupTries = 40;  // restarts before a row gives up (flags bit 0)
+
+template <bool kWrite>
+__global__ __launch_bounds__(kGroupThreads) void k_group(
+    int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
+    const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ goff, uint4* grec,
+    uint2* gcnt, int32_t* flags) {
+  __shared__ unsigned long long key[kGroupSlots];
+  __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
+  __shared__ uint32_t s_out, s_bad;
+  const int tid = threadIdx.x;
+  const int64_t i = c0 + blockIdx.x;
+  const int64_t base = lg_ptr[i];
+  const int64_t d = lg_ptr[i + 1] - base;
+  const int64_t u = up_first[i];
+  const uint4* row = rec + base;
+  int64_t parts = (d + kGroupSlots / 2 - 1) / (kGroupSlots / 2);
+  if (parts < 1) parts = 1;
+  uint64_t seed = 0;
+  const int64_t obase = kWrite ? goff[i] : 0;
+  for (int tries = 0;; ++tries) {  // until a grouping without overflow or hash collision
+    if (tries == kGroupTries) {  // cannot happen with a sound hash; the host pairs records
+      if (tid == 0) atomicOr(flags, 1);
+      if (!kWrite && tid == 0) gcount[i] = 0;
+      return;
+    }
+    __syncthreads();
+    if (tid == 0) s_out = 0u;
+    bool redo = false;
+    for (int64_t part = 0; part < parts && !redo; ++part) {
+      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
+        key[t] = 0ull;
+        nall[t] = 0u;
+        nabove[t] = 0u;
+      }
+      if (tid == 0) s_bad = 0u;
+      __syncthreads();
+      for (int64_t r = tid; r < d; r += kGroupThreads) {
+        const uint4 rr = row[r];
+        const uint64_t kk = sig_hash(rr, clamp_outside(rr), seed);
+        if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
+        uint32_t slot = uint32_t(kk) & (kGroupSlots - 1);
+        int n = 0;
+        for (; n < kGroupSlots; ++n) {
+          const unsigned long long old = atomicCAS(&key[slot], 0ull, kk);
+          if (old == 0ull) { first[slot] = uint32_t(r); break; }
+          if (old == kk) break;
+          slot = (slot + 1) & (kGroupSlots - 1);
+        }
+        if (n == kGroupSlots) { atomicOr(&s_bad, 1u); continue; }
+        atomicAdd(&nall[slot], 1u);
+        if (r >= u) atomicAdd(&nabove[slot], 1u);
+      }
+      __syncthreads();
+      const uint32_t full = s_bad;
+      __syncthreads();  // every thread has read the flag before it is written again
+      if (full) {  // table full: twice the parts
+        parts *= 2;
+        redo = true;
+        break;
+      }
+      // every record against its slot's first member
+      for (int64_t r = tid; r < d; r += kGroupThreads) {
+        const uint4 rr = row[r];
+        const uint32_t o = clamp_outside(rr);
+        const uint64_t kk = sig_hash(rr, o, seed);
+        if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
+        uint32_t slot = uint32_t(kk) & (kGroupSlots - 1);
+        while (key[slot] != kk) slot = (slot + 1) & (kGroupSlots - 1);
+        const uint4 f = row[first[slot]];
+        if (f.x != rr.x || f.z != rr.z || f.w != rr.w || clamp_outside(f) != o) atomicOr(&s_bad, 2u);
+      }
+      __syncthreads();
+      const uint32_t clash = s_bad;
+      __syncthreads();
+      if (clash) {  // two signatures with one hash: another seed
+        seed += 0x9E3779B97F4A7C15ull;
+        redo = true;
+        break;
+      }
+      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
+        if (key[t] == 0ull) continue;
+        const uint32_t pos = atomicAdd(&s_out, 1u);
+        if (kWrite) {
+          const uint4 f = row[first[t]];
+          grec[obase + pos] = make_uint4(f.x, clamp_outside(f), f.z, f.w);
+          gcnt[obase + pos] = make_uint2(nall[t], nabove[t]);
+        }
+      }
+      __syncthreads();
+    }
+    if (!redo) break;
+  }
+  if (!kWrite && tid == 0) gcount[i] = int64_t(s_out);
+}
+
+// Pairs of groups (x < y) and each group with itself, weighted as above.
+constexpr int kGCopies = 2;
+constexpr int kGStride = kHistSlots + 1;
+
+template <bool kDiag>
+__device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t a,
+                                           const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
+                                           uint32_t ka, int kp, bool valid,
+                                           const uint16_t* __restrict__ lut,
+                                           unsigned long long* hist) {
+  const uint32_t mj = rj.x;
+  const bool disjoint = ((mj & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u;
+  const uint64_t w = disjoint ? uint64_t(cj.x) * kn : uint64_t(cj.y) * ka;
+  bool act = valid && w != 0ull;
+  if (kDiag) act = act && (j < kp);
+  if (act) {
+    const uint32_t t = uint32_t(__popc(mj & k.m));
+    const uint32_t r5 = uint32_t(__popc(rj.z & khl) + __popc(rj.w & khh));
+    const uint32_t code = pair_code(a, __popc(mj), rj.y & 0xffu, k, t, r5);
+    atomicAdd(&hist[lut[code]], w);
+  }
+}
+
+template <bool kDiag>
+__device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
+                                      int j0, int j1, uint32_t a, const Side& k, uint32_t kn,
+                                      uint32_t ka, int kp, bool valid,
+                                      const uint16_t* __restrict__ lut, unsigned long long* hist) {
+  const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
+    const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
+    gpair_step<kDiag>(r0, c0, j, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+    gpair_step<kDiag>(r1, c1, j + 1, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+    gpair_step<kDiag>(r2, c2, j + 2, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+    gpair_step<kDiag>(r3, c3, j + 3, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+  }
+  for (; j < j1; ++j) gpair_step<kDiag>(grow[j], gc[j], j, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+}
+
+__device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane, int64_t g,
+                                            unsigned long long* hist_out) {
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < kHistSlots; t += kWave) {
+    unsigned long long s = 0;
+    for (int c = 0; c < kGCopies; ++c) {
+      s += whist[c * kGStride + t];
+      whist[c * kGStride + t] = 0ull;
+    }
+    if (s) atomicAdd(&hist_out[g * kHistSlots + t], s);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(256) void k_exact_grouped(
+    const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
+    const uint4* __restrict__ grec, const uint2* __restrict__ gcnt,
+    const int32_t* __restrict__ order, const int64_t* __restrict__ rstart, int64_t nslots,
+    const int32_t* __restrict__ row_graph, unsigned long long* queue,
+    const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
+  __shared__ uint16_t lut[kNumCodes];
+  __shared__ unsigned long long hist[kWavesPerGroup * kGCopies * kGStride];
+  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
+  for (int t = threadIdx.x; t < kWavesPerGroup * kGCopies * kGStride; t += blockDim.x) hist[t] = 0ull;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  unsigned long long* whist = hist + wave * (kGCopies * kGStride);
+  unsigned long long* myhist = whist + (lane & (kGCopies - 1)) * kGStride;
+  const int64_t total = rstart[nslots];
+  int dirty_g = -1;
+  for (;;) {
+    unsigned long long qq = 0;
+    if (lane == 0) qq = atomicAdd(queue, 1ull);
+    const int64_t q = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(int(qq >> 32)) << 32) |
+                                (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(int(qq)));
+    if (q >= total) break;
+    int64_t lo = 0, hi = nslots;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (rstart[mid] <= q) lo = mid; else hi = mid;
+    }
+    const int32_t i = order[lo];
+    const int g = row_graph[i];
+    if (dirty_g >= 0 && dirty_g != g) gflush_wave(whist, lane, dirty_g, hist_out);
+    dirty_g = g;
+    const int nbi = int(rstart[lo + 1] - rstart[lo]);
+    const int b = nbi - 1 - int(q - rstart[lo]);
+    const int64_t gb = goff[i];
+    const int ng = int(goff[i + 1] - gb);
+    const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
+    const uint4* __restrict__ grow = grec + gb;
+    const uint2* __restrict__ gc = gcnt + gb;
+    const int kp = b * kWave + lane;
+    const bool valid = kp < ng;
+    Side k;
+    uint32_t kn = 0, ka = 0;
+    {
+      const uint4 rk = valid ? grow[kp] : make_uint4(0, 0, 0, 0);
+      const uint2 ck = valid ? gc[kp] : make_uint2(0, 0);
+      k.m = rk.x;
+      k.o = rk.y & 0xffu;
+      k.s = __popc(rk.x);
+      k.h = (unsigned long long)rk.z | ((unsigned long long)rk.w << 32);
+      kn = ck.x;
+      ka = ck.y;
+    }
+    const int blo = b * kWave;
+    const int kmax = min(blo + kWave, ng);
+    gwalk<false>(grow, gc, 0, blo, a, k, kn, ka, kp, valid, lut, myhist);
+    gwalk<true>(grow, gc, blo, kmax, a, k, kn, ka, kp, valid, lut, myhist);
+    if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
+      const uint32_t r5 = uint32_t(__popcll(k.h));
+      const uint32_t code = pair_code(a, k.s, k.o, k, k.s, r5);
+      atomicAdd(&myhist[lut[code]], uint64_t(ka) * (ka - 1u) / 2u);
+    }
+  }
+  if (dirty_g >= 0) gflush_wave(whist, lane, dirty_g, hist_out);
+}
+
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
+
+}  // namespace
+
+namespace {
+
+// Work list of (row, 64-block) items over rows [c0, c1) of row_ptr (rows
+// shorter than min_len have no pairs); see the scheduling kernels above.
+struct Schedule {
+  char* scratch = nullptr;
+  int32_t* order = nullptr;
+  int64_t* rstart = nullptr;
+  unsigned long long* queue = nullptr;
+  int64_t rows = 0;
+};
+
+mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                            const int64_t* row_ptr, int64_t min_len, Schedule& S) {
+  hipStream_t st = ctx->stream;
+  const int ng = g->ng;
+  const int32_t maxnb = (g->max_deg + kWave - 1) / kWave;
+  const int64_t NB = maxnb + 1;
+  const int64_t rows = c1 - c0;
+  // scratch (8-byte slots): nbhist, cnt, item_start, fill [ng*NB each], total [ng],
+  // gq [ng+1], seg [ng], queue [1], nbk [rows+1], rstart [rows+1], tmp; then order [rows] int32
+  const size_t tmpn = scan_tmp_elems(rows + 1);
+  const size_t n8 = size_t(ng) * NB * 4 + size_t(ng) * 3 + 2 + size_t(rows + 1) * 2 + tmpn;
+  mochy_status rc = device_alloc(ctx, (void**)&S.scratch, n8 * 8 + size_t(rows) * 4);
+  if (rc != MOCHY_OK) return rc;
+  unsigned long long* nbhist = (unsigned long long*)S.scratch;
+  int64_t* cnt = (int64_t*)(nbhist + ng * NB);
+  int64_t* item_start = cnt + ng * NB;
+  unsigned long long* fill = (unsigned long long*)(item_start + ng * NB);
+  int64_t* total = (int64_t*)(fill + ng * NB);
+  int64_t* gq = total + ng;
+  int64_t* seg = gq + (ng + 1);
+  S.queue = (unsigned long long*)(seg + ng);
+  int64_t* nbk = (int64_t*)(S.queue + 1);
+  S.rstart = nbk + (rows + 1);
+  int64_t* tmp = S.rstart + (rows + 1);
+  S.order = (int32_t*)(S.scratch + n8 * 8);
+  S.rows = rows;
+  MOCHY_HIP(hipMemsetAsync(S.scratch, 0, (size_t(ng) * NB * 4 + size_t(ng) * 3 + 2) * 8, st));
+  MOCHY_HIP(hipMemsetAsync(S.order, 0xff, size_t(rows) * 4, st));
+  k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), row_ptr, min_len, g->row_graph,
+                                                   nbhist);
+  k_sched_scan<<<unsigned(ng), 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
+  k_sched_graphs<<<1, 1024, 0, st>>>(ng, c0, c1, g->geoff, total, gq, seg);
+  k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), row_ptr, min_len,
+                                                     g->row_graph, cnt, seg, fill, S.order);
+  k_item_counts<<<blocks(rows + 1, 256), 256, 0, st>>>(rows, S.order, row_ptr, nbk);
+  launch_exclusive_scan_i64(nbk, S.rstart, rows + 1, tmp, st);
+  return MOCHY_OK;
+}
+
+// Groups of rows [c0, c1): goff[E+1] (absolute row index), grec, gcnt.
+// Returns MOCHY_ENOMEM (nothing held) if the group arrays do not fit or a
+// row could not be grouped; the caller then pairs every record.
+mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                          int64_t** goff, uint4** grec, uint2** gcnt) {
+  hipStream_t st = ctx->stream;
+  const int64_t E = g->E;
+  int64_t* cntarr = nullptr;
+  int64_t* tmp = nullptr;
+  *goff = nullptr;
+  *grec = nullptr;
+  *gcnt = nullptr;
+  auto fail = [&](mochy_status rc) {
+    device_free(ctx, cntarr);
+    device_free(ctx, tmp);
+    device_free(ctx, *goff);
+    device_free(ctx, *grec);
+    device_free(ctx, *gcnt);
+    *goff = nullptr;
+    *grec = nullptr;
+    *gcnt = nullptr;
+    return rc;
+  };
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK)
+    return fail(rc);
+  MOCHY_HIP(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st));
+  MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st));
+  if (c1 > c0)
+    k_group<false><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
+                                                               cntarr, nullptr, nullptr, nullptr,
+                                                               ctx->d_flags + 3);
+  launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int64_t ngroups = ctx->h_small[0];
+  if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
+  device_free(ctx, cntarr);
+  cntarr = nullptr;
+  device_free(ctx, tmp);
+  tmp = nullptr;
+  if ((rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(ngroups, 1)) * 16)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(ngroups, 1)) * 8)) != MOCHY_OK)
+    return fail(rc);
+  if (c1 > c0)
+    k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
+                                                              nullptr, *goff, *grec, *gcnt,
+                                                              ctx->d_flags + 3);
+  MOCHY_HIP(hipGetLastError());
+  return MOCHY_OK;
+}
 
 }  // namespace
 
@@ -306,52 +676,49 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int ng = g->ng;
   MOCHY_HIP(hipMemsetAsync(d_hist, 0, size_t(ng) * kHistSlots * 8, st));
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
-  const int32_t maxnb = (g->max_deg + kWave - 1) / kWave;
-  const int64_t NB = maxnb + 1;
-  const int64_t rows = c1 - c0;
-  // scratch (8-byte slots): nbhist, cnt, item_start, fill [ng*NB each], total [ng],
-  // gq [ng+1], seg [ng], queue [1], rstart [rows+1], tmp; then order [rows] int32
-  const size_t tmpn = scan_tmp_elems(rows + 1);
-  const size_t n8 = size_t(ng) * NB * 4 + size_t(ng) * 3 + 2 + size_t(rows + 1) * 2 + tmpn;
-  char* scratch = nullptr;
-  mochy_status rc = device_alloc(ctx, (void**)&scratch, n8 * 8 + size_t(rows) * 4);
-  if (rc != MOCHY_OK) return rc;
-  unsigned long long* nbhist = (unsigned long long*)scratch;
-  int64_t* cnt = (int64_t*)(nbhist + ng * NB);
-  int64_t* item_start = cnt + ng * NB;
-  unsigned long long* fill = (unsigned long long*)(item_start + ng * NB);
-  int64_t* total = (int64_t*)(fill + ng * NB);
-  int64_t* gq = total + ng;
-  int64_t* seg = gq + (ng + 1);
-  unsigned long long* queue = (unsigned long long*)(seg + ng);
-  int64_t* nbk = (int64_t*)(queue + 1);
-  int64_t* rstart = nbk + (rows + 1);
-  int64_t* tmp = rstart + (rows + 1);
-  int32_t* order = (int32_t*)(scratch + n8 * 8);
-  phase_begin(ctx, kPhSched);
-  MOCHY_HIP(hipMemsetAsync(scratch, 0, (size_t(ng) * NB * 4 + size_t(ng) * 3 + 2) * 8, st));
-  MOCHY_HIP(hipMemsetAsync(order, 0xff, size_t(rows) * 4, st));
-  k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, nbhist);
-  k_sched_scan<<<unsigned(ng), 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
-  k_sched_graphs<<<1, 1024, 0, st>>>(ng, c0, c1, g->geoff, total, gq, seg);
-  k_sched_scatter<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), g->lg_ptr, g->row_graph, cnt,
-                                                     seg, fill, order);
-  k_item_counts<<<blocks(rows + 1, 256), 256, 0, st>>>(rows, order, g->lg_ptr, nbk);
-  launch_exclusive_scan_i64(nbk, rstart, rows + 1, tmp, st);
-  phase_end(ctx, kPhSched);
   const unsigned grid = unsigned(ctx->num_cus) * 8u;
+  int64_t* goff = nullptr;
+  uint4* grec = nullptr;
+  uint2* gcnt = nullptr;
+  mochy_status rc;
+  phase_begin(ctx, kPhSched);
+  bool grouped = ctx->group_neighbours;
+  if (grouped) {
+    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt);
+    if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
+      grouped = false;
+      ctx->err.clear();
+    } else if (rc != MOCHY_OK) {
+      return rc;
+    }
+  }
+  Schedule S;
+  rc = build_schedule(ctx, g, c0, c1, grouped ? goff : g->lg_ptr, grouped ? 1 : 2, S);
+  auto release = [&]() {
+    device_free(ctx, S.scratch);
+    device_free(ctx, goff);
+    device_free(ctx, grec);
+    device_free(ctx, gcnt);
+  };
+  if (rc != MOCHY_OK) { release(); return rc; }
+  phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
-  k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, order, rstart, rows,
-                                     g->row_graph, queue, ctx->d_code_to_id3,
-                                     (unsigned long long*)d_hist);
+  if (grouped)
+    k_exact_grouped<<<grid, 256, 0, st>>>(g->edge_ptr, goff, grec, gcnt, S.order, S.rstart, S.rows,
+                                          g->row_graph, S.queue, ctx->d_code_to_id3,
+                                          (unsigned long long*)d_hist);
+  else
+    k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, S.order, S.rstart,
+                                       S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
+                                       (unsigned long long*)d_hist);
   phase_end(ctx, kPhPairs);
   phase_begin(ctx, kPhCorrect);
   rc = correct_device(ctx, g, c0, c1, d_hist);
-  if (rc != MOCHY_OK) { device_free(ctx, scratch); return rc; }
+  if (rc != MOCHY_OK) { release(); return rc; }
   phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
   phases_collect(ctx);
-  device_free(ctx, scratch);
+  release();
   return MOCHY_OK;
 }

@@ -204,3 +204,32 @@ def test_medium_full_size_identity(ctx, medium, medium_graph):
     sc = int(c26.sum()) - so
     assert so + 3 * sc == int((deg * (deg - 1) // 2).sum())
     assert (native.fold26(np.concatenate([[0], c431])) == c26).all()
+
+
+def test_grouped_equals_every_pair(ctx):
+    # neighbour groups (default) and pairing every record give the same counts
+    import paper_2310_15668_amd as M
+    star = [[0, a] for a in range(1, 3000)] + [[a, a + 1] for a in range(1, 2999, 2)]
+    cases = [make_config("tiny"), make_config("medium", scale=0.03),
+             powerlaw_hypergraph(60, 3000, 2, 6, 2.5, 1.0, seed=9),  # long rows, few distinct records
+             from_edge_lists(star, 3000)]                               # one hub row of 2999 neighbours
+    for h in cases:
+        print(f"[gpu] grouped vs every pair |E|={h.num_edges}", flush=True)
+        g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+        try:
+            ctx.set_option(M.MOCHY_OPT_GROUPS, 0)
+            a26, a431 = M.mochy_count_exact(ctx, g)
+            ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+            b26, b431 = M.mochy_count_exact(ctx, g)
+            cuts = [0, h.num_edges // 3, h.num_edges]
+            parts = [M.mochy_count_exact_range(ctx, g, x, y)[1] for x, y in zip(cuts[:-1], cuts[1:])]
+        finally:
+            ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+            g.close()
+        assert (a431 == b431).all() and (a26 == b26).all()
+        assert (sum(parts) == b431).all()
+        r26, r431, _ = native.mochy_e(h, nthreads=8)
+        assert (b431 == r431).all()
+    with pytest.raises(M.MochyError) as e:
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 2)
+    assert e.value.status == -1
