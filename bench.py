@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "exact.hip")
-COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_main_medium_counters.md")
+COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_grouped_medium_counters.md")
 FREE_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "free.hip")
 ENUM_SUMMARY = os.path.join(ROOT, "profiles", "k_enum_large_aplus.md")
 WORKLOAD = ("medium exact MoCHy-E: 20000 nodes, 100000 drawn hyperedges (duplicates removed), "
@@ -52,8 +52,8 @@ def source_digest(path):
 
 def measured_traffic(summary=None, source=None):
     """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary (default: the pair kernel's), or None if there is none or the
-    kernel source changed since the counters were taken."""
+    summary (default: the exact pair kernel's), or None if there is none or
+    the kernel source changed since the counters were taken."""
     summary = summary or COUNTERS_SUMMARY
     source = source or PAIR_KERNEL_SRC
     if not os.path.exists(summary):
@@ -448,7 +448,7 @@ def main():
                    "incidences": st["nnz"], "hyperwedges": st["hyperwedges"],
                    "max_line_degree": st["max_line_degree"], "candidates": st["candidates"],
                    "connected_triples": triples, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_exact_main (MoCHy-E pair enumeration)",
+        "roofline": {"bound": "hbm", "kernel": "k_exact_grouped (MoCHy-E pairs of neighbour groups)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "model": "8 + 4*min(|e_i|,|e_j|,|e_k|) bytes per MoCHy-E candidate",
