@@ -115,3 +115,15 @@ def test_small_batched_config_against_oracle(ctx):
     for k, h in enumerate(graphs):
         r26, r431, _ = native.mochy_e(h, nthreads=16)
         assert (counts[k, 26:] == r431).all(), k
+
+
+def test_chung_lu_copies_match_oracle(ctx):
+    # the paper's own null model (Chung-Lu on the incidence graph) as the copies
+    from workloads import chung_lu_copy
+    base = powerlaw_hypergraph(200, 600, 2, 10, 2.5, 1.0, seed=31)
+    graphs = [base] + [chung_lu_copy(base, s) for s in range(5)]
+    counts, sig26, cp26, sig431, cp431 = run_profile(ctx, graphs)
+    for k, h in enumerate(graphs):
+        r26, r431, _ = native.mochy_e(h, nthreads=8)
+        assert (counts[k, :26] == r26).all() and (counts[k, 26:] == r431).all(), k
+    check_cp(counts, sig26, cp26, sig431, cp431)

@@ -49,3 +49,38 @@ def test_stub_matching_preserves_degrees_before_collapse():
     g3 = stub_matching_copy(h, seed=100)
     assert not (g.edge_nodes.size == g2.edge_nodes.size and (g.edge_nodes == g2.edge_nodes).all())
     assert (g.edge_nodes == g3.edge_nodes).all()
+
+
+def test_chung_lu_preserves_degrees_in_expectation():
+    # E[degree of v in the incidence multiset] = d_v and E[size of e] = |e|
+    from workloads import chung_lu_incidences
+    h = make_config("tiny")
+    deg = np.bincount(h.edge_nodes, minlength=h.num_nodes).astype(float)
+    size = h.sizes().astype(float)
+    R = 400
+    dsum = np.zeros_like(deg)
+    ssum = np.zeros_like(size)
+    for seed in range(R):
+        e, v = chung_lu_incidences(h, seed)
+        assert e.size == v.size == h.nnz
+        dsum += np.bincount(v, minlength=h.num_nodes)
+        ssum += np.bincount(e, minlength=h.num_edges)
+    # binomial counts: the mean over R copies has sd sqrt(d (1 - d/L) / R)
+    L = h.nnz
+    zd = (dsum / R - deg) / np.sqrt(np.maximum(deg * (1 - deg / L), 1e-9) / R)
+    zs = (ssum / R - size) / np.sqrt(size * (1 - size / L) / R)
+    assert np.abs(zd).max() < 5 and np.abs(zs).max() < 5
+    assert abs(zd.mean()) < 0.3 and abs(zs.mean()) < 0.3
+
+
+def test_chung_lu_copy_is_a_hypergraph():
+    from workloads import chung_lu_copy
+    h = make_config("tiny")
+    for seed in range(5):
+        g = chung_lu_copy(h, seed)
+        sz = g.sizes()
+        assert (sz >= 1).all() and g.num_nodes == h.num_nodes
+        assert g.nnz <= h.nnz and g.num_edges <= h.num_edges
+        rows = [tuple(g.edge_nodes[g.edge_ptr[x]:g.edge_ptr[x + 1]]) for x in range(g.num_edges)]
+        assert all(all(a < b for a, b in zip(r, r[1:])) for r in rows)
+        assert len(set(rows)) == len(rows)

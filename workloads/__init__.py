@@ -13,6 +13,8 @@ from .generators import (  # noqa: F401
     Hypergraph,
     powerlaw_hypergraph,
     stub_matching_copy,
+    chung_lu_copy,
+    chung_lu_incidences,
     from_edge_lists,
     induced_prefix,
     CONFIGS,

@@ -164,6 +164,37 @@ def stub_matching_copy(h: Hypergraph, seed: int) -> Hypergraph:
     return dedup_hypergraph(g)
 
 
+def chung_lu_incidences(h: Hypergraph, seed: int):
+    """The random incidence multiset of the Chung-Lu model on the incidence
+    graph (Appendix, randomized hypergraphs): |incidences| draws, each a node
+    picked with probability proportional to its degree and, independently, a
+    hyperedge picked with probability proportional to its size.  A uniformly
+    drawn incidence's node (hyperedge) has exactly that distribution.
+    Returns (hyperedge ids, node ids), int64 arrays of length nnz."""
+    rng = np.random.default_rng(seed)
+    L = h.nnz
+    owner = np.repeat(np.arange(h.num_edges, dtype=np.int64), h.sizes())
+    nodes = h.edge_nodes.astype(np.int64)[rng.integers(0, L, size=L)]
+    edges = owner[rng.integers(0, L, size=L)]
+    return edges, nodes
+
+
+def chung_lu_copy(h: Hypergraph, seed: int) -> Hypergraph:
+    """Randomized copy by the Chung-Lu model: the incidence multiset of
+    :func:`chung_lu_incidences` turned into a hypergraph whose hyperedges are
+    sets (repeated members collapse); hyperedges that drew no member are
+    dropped and repeated hyperedges removed, keeping the first."""
+    edges, nodes = chung_lu_incidences(h, seed)
+    key = np.unique(edges * np.int64(max(h.num_nodes, 1)) + nodes)
+    e_of = key // max(h.num_nodes, 1)
+    v_of = (key % max(h.num_nodes, 1)).astype(np.int32)
+    sizes = np.bincount(e_of, minlength=h.num_edges).astype(np.int64)
+    sizes = sizes[sizes > 0]
+    ptr = np.zeros(sizes.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=ptr[1:])
+    return dedup_hypergraph(Hypergraph(ptr, v_of, h.num_nodes))
+
+
 def induced_prefix(h: Hypergraph, n_edges: int) -> Hypergraph:
     """First ``n_edges`` hyperedges; nodes are renumbered compactly in order."""
     n_edges = min(n_edges, h.num_edges)
