@@ -57,3 +57,8 @@ def aplus_estimate3(raw431, num_wedges, r):
         w = 2.0 if int(parent[t + 1]) in opened else 3.0
         out.append((float(int(raw431[t])) * float(num_wedges)) / (w * float(r)))
     return out
+
+
+def mochy_a_estimate(raw, num_edges, s):
+    """Algorithm 4's rescaling: every count by |E| / (3 s)."""
+    return [(float(int(x)) * float(num_edges)) / (3.0 * float(s)) for x in raw]

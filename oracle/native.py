@@ -58,6 +58,10 @@ def lib():
     L.orc_aplus_raw.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64,
                                 ctypes.c_int64, ctypes.c_uint64, _i64p, _i64p, ctypes.c_int, _i32p,
                                 _i64p, ctypes.c_int]
+    L.orc_mochy_a_raw.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_uint64, _i64p, ctypes.c_int, _i32p, _i64p,
+                                  ctypes.c_int]
+    L.orc_mochy_a_raw.restype = ctypes.c_int64
     L.orc_wedge_prefix.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, ctypes.c_int]
     L.orc_wedge_prefix.restype = ctypes.c_int64
     L.orc_aplus_raw.restype = ctypes.c_int64
@@ -190,3 +194,22 @@ def aplus_raw(h, r=None, seed=0, n0=0, indices=None, theta=1, nthreads=None, up_
                             _p(up, _i64p) if up is not None else None, int(theta),
                             _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
     return fold26(out), out[1:].copy(), int(out[0]), int(w)
+
+
+def mochy_a_raw(h, s=None, seed=0, n0=0, indices=None, theta=1, nthreads=None):
+    """(raw26, raw431, invalid, |E|) of MoCHy-A samples n in [n0, n0 + s).
+
+    With ``indices`` the samples are those hyperedges instead of Philox draws.
+    """
+    ptr, nodes = _csr(h)
+    out = np.zeros(432, dtype=np.int64)
+    t = _table()
+    if indices is not None:
+        idx = np.ascontiguousarray(indices, dtype=np.int64)
+        n0, n1, ip = 0, idx.size, _p(idx, _i64p)
+    else:
+        n1, ip = n0 + int(s), None
+    e = lib().orc_mochy_a_raw(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), int(n0),
+                              int(n1), ctypes.c_uint64(seed & (2 ** 64 - 1)), ip, int(theta),
+                              _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
+    return fold26(out), out[1:].copy(), int(out[0]), int(e)
