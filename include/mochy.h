@@ -132,6 +132,21 @@ mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r
                                  int64_t* raw26, double* est26,
                                  int64_t* raw431, double* est431);
 
+/* MoCHy-A (Algorithm 4): samples n = sample_begin .. sample_begin+s-1 each
+ * draw one hyperedge uniformly with replacement, using Philox4x32-10 with
+ * counter (lo32 n, hi32 n, 1, 0), key (lo32 seed, hi32 seed),
+ * u = (x1 << 32) | x0 and hyperedge index floor(u * |E| / 2^64).  Every
+ * instance that contains the sampled hyperedge adds one hit to its motif
+ * (found from its 1-hop and 2-hop neighbourhoods).  raw26/raw431 (host int64)
+ * receive the hits; est26/est431 (host double) the unbiased estimates
+ * raw * |E| / (3 s).  Any output pointer may be NULL; s must be > 0.
+ * Needs the stored line graph: MOCHY_EUNSUPPORTED for a graph projected
+ * line-graph-free. */
+mochy_status mochy_count_sampled_edges(mochy_ctx* ctx, const mochy_graph* g, int64_t s,
+                                       uint64_t seed, int64_t sample_begin,
+                                       int64_t* raw26, double* est26,
+                                       int64_t* raw431, double* est431);
+
 /* Significance and characteristic profile against randomized copies
  * (section 3.1).  graphs[0] is the hypergraph, graphs[1..num_graphs-1] its
  * randomized copies (host or device CSRs; the caller draws them).  All graphs

@@ -28,7 +28,8 @@ MAX_EDGE = 32
 EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_project",
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
-            "mochy_graph_stats", "mochy_phase_ms", "mochy_ctx_set_option")
+            "mochy_graph_stats", "mochy_phase_ms", "mochy_ctx_set_option",
+            "mochy_count_sampled_edges")
 NUM_PHASES = 11
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
           "exact_correct", "sample_draw", "sample_enum", "profile_cp")
@@ -93,6 +94,8 @@ def lib():
     L.mochy_graph_stats.restype = ctypes.c_int
     L.mochy_phase_ms.argtypes = [vp, vp]
     L.mochy_phase_ms.restype = ctypes.c_int
+    L.mochy_count_sampled_edges.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
+    L.mochy_count_sampled_edges.restype = ctypes.c_int
     L.mochy_ctx_set_option.argtypes = [vp, i32, i64]
     L.mochy_ctx_set_option.restype = ctypes.c_int
     _lib = L
@@ -228,6 +231,18 @@ def mochy_count_sampled(ctx: Context, g: Graph, r: int, seed: int, sample_begin:
     ctx.check(lib().mochy_count_sampled(ctx.handle, g.handle, int(r), ctypes.c_uint64(seed & (2 ** 64 - 1)),
                                         int(sample_begin), _ptr(raw26), _ptr(est26), _ptr(raw431),
                                         _ptr(est431)), "mochy_count_sampled")
+    return raw26, est26, raw431, est431
+
+
+def mochy_count_sampled_edges(ctx: Context, g: Graph, s: int, seed: int, sample_begin: int = 0):
+    """MoCHy-A: (raw26, est26, raw431, est431) of s hyperedge samples."""
+    raw26 = np.zeros(NUM_H, dtype=np.int64)
+    est26 = np.zeros(NUM_H, dtype=np.float64)
+    raw431 = np.zeros(NUM_3H, dtype=np.int64)
+    est431 = np.zeros(NUM_3H, dtype=np.float64)
+    ctx.check(lib().mochy_count_sampled_edges(ctx.handle, g.handle, int(s), ctypes.c_uint64(seed & (2 ** 64 - 1)),
+                                              int(sample_begin), _ptr(raw26), _ptr(est26), _ptr(raw431),
+                                              _ptr(est431)), "mochy_count_sampled_edges")
     return raw26, est26, raw431, est431
 
 

@@ -41,6 +41,20 @@ __global__ void k_aplus_est(const int64_t* __restrict__ hist, const int32_t* __r
   }
 }
 
+// Algorithm 4's rescaling in float64: est = raw * |E| / (3 s).
+__global__ void k_hsample_est(const int64_t* __restrict__ hist, const int32_t* __restrict__ parent,
+                              int64_t E, int64_t s, int64_t* raw26, double* est26, double* est431) {
+  const int t = threadIdx.x;
+  if (t >= 1 && t < kHistSlots) est431[t - 1] = (double(hist[t]) * double(E)) / (3.0 * double(s));
+  if (t < MOCHY_NUM_H) {
+    int64_t sum = 0;
+    for (int id3 = 1; id3 < kHistSlots; ++id3)
+      if (parent[id3] == t + 1) sum += hist[id3];
+    raw26[t] = sum;
+    est26[t] = (double(sum) * double(E)) / (3.0 * double(s));
+  }
+}
+
 // Significance and characteristic profile (Eq. 1, Eq. 2) of graph 0 against
 // graphs 1..ng-1, in float64.  counts[g][t] for the 26 h-motifs (folded from
 // the 3h-motifs) and the 431 3h-motifs; Mr = (sum over copies, exact in
@@ -494,6 +508,45 @@ extern "C" mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, 
   out[5] = ctx->h_small[500];
   out[6] = g->lg_free ? -1 : ctx->h_small[501];
   out[7] = ctx->h_small[502];
+  return MOCHY_OK;
+}
+
+extern "C" mochy_status mochy_count_sampled_edges(mochy_ctx* ctx, const mochy_graph* g, int64_t s,
+                                                  uint64_t seed, int64_t sample_begin, int64_t* raw26,
+                                                  double* est26, int64_t* raw431, double* est431) {
+  if (!ctx) return MOCHY_EINVAL;
+  ctx->err.clear();
+  phases_reset(ctx);
+  if (!g || g->ctx != ctx || s <= 0 || sample_begin < 0 || s > INT64_MAX - sample_begin) {
+    ctx->err = "bad graph, sample count or sample range";
+    return MOCHY_EINVAL;
+  }
+  if (g->lg_free) {
+    ctx->err = "hyperedge sampling walks stored line-graph rows; this graph was projected without "
+               "them: use mochy_count_sampled";
+    return MOCHY_EUNSUPPORTED;
+  }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  int64_t* d_hist = ctx->d_small + 64;
+  mochy_status rc = sampled_edges_device(ctx, g, s, seed, sample_begin, d_hist);
+  if (rc != MOCHY_OK) return rc;
+  int64_t* d_raw26 = ctx->d_small;
+  k_hsample_est<<<1, 512, 0, st>>>(d_hist, ctx->d_id3_to_id26, g->E, s, d_raw26, ctx->d_dbl,
+                                   ctx->d_dbl + 32);
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, d_hist, kHistSlots * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + kHistSlots, d_raw26, MOCHY_NUM_H * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_dbl, ctx->d_dbl, (32 + MOCHY_NUM_3H) * 8, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  phases_collect(ctx);
+  if (ctx->h_small[0] != 0) {
+    ctx->err = "internal error: sampled triples with an invalid pattern";
+    return MOCHY_EDEVICE;
+  }
+  if (raw431) std::memcpy(raw431, ctx->h_small + 1, MOCHY_NUM_3H * 8);
+  if (raw26) std::memcpy(raw26, ctx->h_small + kHistSlots, MOCHY_NUM_H * 8);
+  if (est26) std::memcpy(est26, ctx->h_dbl, MOCHY_NUM_H * 8);
+  if (est431) std::memcpy(est431, ctx->h_dbl + 32, MOCHY_NUM_3H * 8);
   return MOCHY_OK;
 }
 

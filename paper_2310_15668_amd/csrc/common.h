@@ -140,9 +140,11 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
 mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                             int64_t* d_hist);
 
-// sampled.hip
+// sampled.hip: MoCHy-A+ (hyperwedges) and MoCHy-A (hyperedges)
 mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
                             int64_t n0, int64_t* d_hist);
+mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t s, uint64_t seed,
+                                  int64_t n0, int64_t* d_hist);
 
 // api.hip helpers: allocation and release ordered on the context stream
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);

@@ -16,6 +16,8 @@
 #include "common.h"
 #include "rng.h"
 
+#include <algorithm>
+
 namespace {
 
 __global__ __launch_bounds__(256) void k_aplus(
@@ -99,7 +101,214 @@ __global__ __launch_bounds__(256) void k_aplus(
     if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
 }
 
+// MoCHy-A (Algorithm 4): hyperedge sampling.  Sample n draws Philox4x32-10
+// with counter (lo32 n, hi32 n, 1, 0) and key (lo32 seed, hi32 seed);
+// u = (x1 << 32) | x0 picks hyperedge floor(u * |E| / 2^64).  Every instance
+// containing the sampled e_i gets one hit: the pairs of N_i and the paths
+// e_i - e_j - e_k (e_k in N_j outside N_i and e_i).
+//
+// One 256-thread block per sample.  N_i is an LDS bitmap over its graph's
+// hyperedges with per-word ranks (the rank is e_k's position in row i, whose
+// record gives omega(i, k)).  All pairs of N_i are first counted as if
+// disjoint from each other (class fixed by |e_j|, omega(i, j), |e_k|,
+// omega(i, k)) with a histogram of N_i by (size, omega) and products of its
+// bins.  Then the rows of e_i's neighbours are scanned (64-bit records of
+// row j: e_j's nodes held by e_k, so omega(j, k) and t = |e_i ∩ e_j ∩ e_k|
+// with the record of e_i in row j): a hit e_k in N_i with j < k is an
+// adjacent pair, its disjoint class is taken back and its exact class
+// added; a hit outside N_i is a path.
+constexpr int kHsThreads = 256;
+constexpr int kBins = (MOCHY_MAX_EDGE + 1) * (MOCHY_MAX_EDGE + 1);
+
+__device__ __forceinline__ uint32_t bin_of(uint32_t size, uint32_t omega) {
+  return size * (MOCHY_MAX_EDGE + 1) + omega;
+}
+
+__global__ __launch_bounds__(kHsThreads) void k_hsample(
+    int64_t n0, int64_t s, uint64_t seed, int64_t E, const int32_t* __restrict__ row_graph,
+    const int64_t* __restrict__ geoff, const int64_t* __restrict__ edge_ptr,
+    const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ lg_col,
+    const uint4* __restrict__ rec, const uint16_t* __restrict__ code_to_id3,
+    unsigned long long* queue, unsigned long long* hist_out) {
+  extern __shared__ uint32_t sm[];
+  __shared__ uint16_t lut[kNumCodes];
+  __shared__ unsigned long long hist[kHistSlots];
+  __shared__ uint32_t bins[kBins];
+  __shared__ uint32_t blist[kBins];
+  __shared__ int32_t c_j[kHsThreads];
+  __shared__ int64_t c_base[kHsThreads];
+  __shared__ uint32_t c_mji[kHsThreads], c_b[kHsThreads];
+  __shared__ int64_t c_pre[kHsThreads + 1];
+  __shared__ int32_t part[kHsThreads];
+  __shared__ int64_t s_i;
+  __shared__ uint32_t s_nb;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < kNumCodes; t += kHsThreads) lut[t] = code_to_id3[t];
+  for (int t = tid; t < kHistSlots; t += kHsThreads) hist[t] = 0ull;
+  for (int t = tid; t < kBins; t += kHsThreads) bins[t] = 0u;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) {
+      const unsigned long long q = atomicAdd(queue, 1ull);
+      int64_t i = -1;
+      if (int64_t(q) < s) {
+        const uint64_t n = uint64_t(n0) + q;
+        const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 1u, 0u),
+                                       uint32_t(seed), uint32_t(seed >> 32));
+        i = int64_t(__umul64hi((uint64_t(x.y) << 32) | x.x, uint64_t(E)));
+      }
+      s_i = i;
+      s_nb = 0u;
+    }
+    __syncthreads();
+    const int64_t i = s_i;
+    if (i < 0) break;
+    const int gi = row_graph[i];
+    const int64_t e0 = geoff[gi];
+    const int nw = int((geoff[gi + 1] - e0 + 31) / 32);
+    uint32_t* bm = sm;
+    uint32_t* rank = sm + nw;
+    const int64_t ib = lg_ptr[i];
+    const int di = int(lg_ptr[i + 1] - ib);
+    const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
+    for (int w = tid; w < nw; w += kHsThreads) bm[w] = 0u;
+    __syncthreads();
+    for (int p = tid; p < di; p += kHsThreads) {
+      const int64_t x = lg_col[ib + p] - e0;
+      atomicOr(&bm[x >> 5], 1u << (x & 31));
+      const uint4 r = rec[ib + p];
+      const uint32_t om = __popc(r.x);
+      if (atomicAdd(&bins[bin_of(om + (r.y & 0xffu), om)], 1u) == 0u)
+        blist[atomicAdd(&s_nb, 1u)] = bin_of(om + (r.y & 0xffu), om);
+    }
+    __syncthreads();
+    {  // ranks: set bits before each word
+      const int chunk = (nw + kHsThreads - 1) / kHsThreads;
+      const int w0 = min(nw, tid * chunk), w1 = min(nw, w0 + chunk);
+      int32_t c = 0;
+      for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
+      part[tid] = c;
+      __syncthreads();
+      for (int off = 1; off < kHsThreads; off <<= 1) {
+        const int32_t add = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+      }
+      int32_t run = part[tid] - c;
+      for (int w = w0; w < w1; ++w) {
+        rank[w] = uint32_t(run);
+        run += __popc(bm[w]);
+      }
+    }
+    // every pair of N_i as if e_j and e_k were disjoint: products of bins
+    const uint32_t nb = s_nb;
+    for (uint32_t q = tid; q < nb * nb; q += kHsThreads) {
+      const uint32_t x = q / nb, y = q % nb;
+      if (y < x) continue;
+      const uint32_t bx = blist[x], by = blist[y];
+      const uint64_t nx = bins[bx], ny = bins[by];
+      const uint64_t w = x == y ? nx * (nx - 1) / 2 : nx * ny;
+      if (w == 0) continue;
+      const uint32_t b = bx / (MOCHY_MAX_EDGE + 1), p = bx % (MOCHY_MAX_EDGE + 1);
+      const uint32_t c = by / (MOCHY_MAX_EDGE + 1), sk = by % (MOCHY_MAX_EDGE + 1);
+      atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, sk, 0u)]], w);
+    }
+    __syncthreads();
+    // the rows of e_i's neighbours, 256 neighbours at a time
+    for (int jc = 0; jc < di; jc += kHsThreads) {
+      const int nj = min(kHsThreads, di - jc);
+      int64_t dj = 0;
+      if (tid < nj) {
+        const int32_t j = lg_col[ib + jc + tid];
+        const int64_t jb = lg_ptr[j];
+        dj = lg_ptr[j + 1] - jb;
+        int lo = 0, hi = int(dj);  // e_i's position in row j
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (lg_col[jb + mid] < int32_t(i)) lo = mid + 1; else hi = mid;
+        }
+        c_j[tid] = j;
+        c_base[tid] = jb;
+        c_mji[tid] = rec[jb + lo].x;
+        c_b[tid] = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
+      }
+      // prefix of the row lengths
+      part[tid] = 0;
+      __syncthreads();
+      {
+        __shared__ int64_t pre64[kHsThreads];
+        pre64[tid] = dj;
+        __syncthreads();
+        for (int off = 1; off < kHsThreads; off <<= 1) {
+          const int64_t add = tid >= off ? pre64[tid - off] : 0;
+          __syncthreads();
+          pre64[tid] += add;
+          __syncthreads();
+        }
+        c_pre[tid + 1] = pre64[tid];
+        if (tid == 0) c_pre[0] = 0;
+      }
+      __syncthreads();
+      const int64_t total = c_pre[nj];
+      for (int64_t q = tid; q < total; q += kHsThreads) {
+        int lo = 0, hi = nj;  // last x with c_pre[x] <= q
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (c_pre[mid] <= q) lo = mid; else hi = mid;
+        }
+        const int32_t j = c_j[lo];
+        const int64_t pos = c_base[lo] + (q - c_pre[lo]);
+        const int32_t k = lg_col[pos];
+        if (k == int32_t(i)) continue;
+        const uint4 rjk = rec[pos];
+        const uint32_t mji = c_mji[lo], b = c_b[lo];
+        const uint32_t p = __popc(mji);
+        const uint32_t wjk = __popc(rjk.x);
+        const uint32_t c = wjk + (rjk.y & 0xffu);
+        const int64_t kl = int64_t(k) - e0;
+        const uint32_t kw = bm[kl >> 5], kbit = 1u << (kl & 31);
+        if (kw & kbit) {
+          if (!(j < k)) continue;  // an adjacent pair of N_i, once
+          const uint32_t wik = __popc(rec[ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u)))].x);
+          const uint32_t t = __popc(mji & rjk.x);
+          atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
+          atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
+        } else {
+          atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, 0u, 0u)]], 1ull);  // a path
+        }
+      }
+      __syncthreads();
+    }
+    for (uint32_t q = tid; q < nb; q += kHsThreads) bins[blist[q]] = 0u;
+  }
+  __syncthreads();
+  for (int t = tid; t < kHistSlots; t += kHsThreads)
+    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
+}
+
 }  // namespace
+
+mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t s, uint64_t seed,
+                                  int64_t n0, int64_t* d_hist) {
+  hipStream_t st = ctx->stream;
+  MOCHY_HIP(hipMemsetAsync(d_hist, 0, kHistSlots * 8, st));
+  if (g->E == 0 || s == 0) return MOCHY_OK;
+  unsigned long long* queue = (unsigned long long*)(ctx->d_small + 496);
+  MOCHY_HIP(hipMemsetAsync(queue, 0, 8, st));
+  const int nw = int((g->max_graph_edges + 31) / 32);
+  const size_t dyn = size_t(std::max(nw, 1)) * 8;
+  if (dyn > 60 * 1024)
+    MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(dyn)));
+  phase_begin(ctx, kPhSample);
+  k_hsample<<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
+      n0, s, seed, g->E, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
+      ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
+  phase_end(ctx, kPhSample);
+  MOCHY_HIP(hipGetLastError());
+  return MOCHY_OK;
+}
 
 mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
                             int64_t n0, int64_t* d_hist) {
