@@ -338,6 +338,45 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def tradeoff(args):
+    """MoCHy-A (hyperedge samples) against MoCHy-A+ (hyperwedge samples) on
+    the medium hypergraph: relative error of the estimates against the exact
+    counts, and time, over a range of sample counts."""
+    import numpy as np
+    import torch
+    import paper_2310_15668_amd as M
+    from workloads import make_config
+
+    h = make_config("medium")
+    dp, dn, V = device_csr(h)
+    torch.cuda.synchronize()
+    ctx = M.Context(0, torch.cuda.current_stream().cuda_stream)
+    g = M.mochy_project(ctx, dp, dn, V)
+    exact, _ = M.mochy_count_exact(ctx, g)
+    big = exact > 1e-3 * exact.sum()
+    rows = []
+    for name, fn, counts in (("A+", M.mochy_count_sampled, (10 ** 5, 10 ** 6, 10 ** 7, 10 ** 8)),
+                             ("A", M.mochy_count_sampled_edges, (10, 100, 1000))):
+        for n in counts:
+            fn(ctx, g, min(n, 1000), 99)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, est26, _, _ = fn(ctx, g, n, args.seed)
+            dt = time.perf_counter() - t0
+            rel = np.abs(est26[big] - exact[big]) / exact[big]
+            rows.append({"method": name, "samples": n, "seconds": dt, "max_rel_error": float(rel.max()),
+                         "mean_rel_error": float(rel.mean())})
+            log(rows[-1])
+    g.close()
+    ctx.close()
+    out = {"metric": "relative error of motif-count estimates vs time (MoCHy-A and MoCHy-A+)",
+           "value": None, "unit": "", "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+           "config": {"workload": "medium hypergraph (see medium-exact); h-motifs with at least 0.1 % "
+                                  "of the connected triples", "seed": args.seed},
+           "points": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,7 +384,7 @@ def main():
                     help="timed steps (default 3; 1 for large-aplus)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium-exact",
-                    choices=["medium-exact", "large-aplus", "batched-cp", "serving"])
+                    choices=["medium-exact", "large-aplus", "batched-cp", "serving", "tradeoff"])
     ap.add_argument("--samples", type=int, default=0,
                     help="large-aplus: samples per step (default 5%% of the hyperwedges)")
     ap.add_argument("--seed", type=int, default=2, help="large-aplus: Philox key")
@@ -380,6 +419,9 @@ def main():
         return
     if args.workload == "serving":
         serving(args)
+        return
+    if args.workload == "tradeoff":
+        tradeoff(args)
         return
 
     import numpy as np

@@ -83,6 +83,9 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                records, weighted by their sizes (1, default), or every
                                pair of neighbours (0); with too little device memory
                                for the groups it pairs every neighbour */
+#define MOCHY_OPT_APLUS_ROWS 2  /* MoCHy-A+ on a graph with a stored line graph: enumerate
+                                   N_i ∪ N_j on the fly from the node lists (0, default) or
+                                   by merging the two stored rows (1); same hits */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

@@ -21,6 +21,7 @@ STATUS = {0: "MOCHY_OK", -1: "MOCHY_EINVAL", -2: "MOCHY_EDUP", -3: "MOCHY_ERANGE
 MOCHY_DEDUP = 1
 MOCHY_LG_FREE = 4
 MOCHY_OPT_GROUPS = 1
+MOCHY_OPT_APLUS_ROWS = 2
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 

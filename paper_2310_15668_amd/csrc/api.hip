@@ -319,6 +319,10 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     ctx->group_neighbours = value != 0;
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_APLUS_ROWS && (value == 0 || value == 1)) {
+    ctx->aplus_rows = value != 0;
+    return MOCHY_OK;
+  }
   ctx->err = "unknown option or value";
   return MOCHY_EINVAL;
 }
@@ -563,8 +567,9 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   int64_t* d_hist = ctx->d_small + 64;
-  mochy_status rc = g->lg_free ? sampled_free_device(ctx, g, r, seed, sample_begin, d_hist)
-                               : sampled_device(ctx, g, r, seed, sample_begin, d_hist);
+  const bool walk = g->xnodes != nullptr && (g->lg_free || !ctx->aplus_rows);
+  mochy_status rc = walk ? sampled_free_device(ctx, g, r, seed, sample_begin, d_hist)
+                         : sampled_device(ctx, g, r, seed, sample_begin, d_hist);
   if (rc != MOCHY_OK) return rc;
   int64_t* d_raw26 = ctx->d_small;
   k_aplus_est<<<1, 512, 0, st>>>(d_hist, ctx->d_id3_to_id26, ctx->d_open26, g->W, r, d_raw26,

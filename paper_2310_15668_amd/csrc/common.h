@@ -32,6 +32,7 @@ struct mochy_ctx {
   bool own_stream = false;
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
+  bool aplus_rows = false;            // A+ by merging stored rows (MOCHY_OPT_APLUS_ROWS)
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
@@ -127,6 +128,8 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g);
 
 // free.hip: line-graph-free projection and MoCHy-A+ (single graphs)
 mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g);
+// per-slot node lists and heavy tables for the on-the-fly sampler (single graphs)
+mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g);
 mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
                                  int64_t n0, int64_t* d_hist);
 // adds sum_i C(d_i, 2) to d_out[0] and sum_i d_i^2 to d_out[2]

@@ -694,29 +694,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 
 }  // namespace
 
-mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
+// Per-slot node lists and heavy-node tables (what the sampler walks), for a
+// single graph whose incidence and transpose are built.
+mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g) {
   hipStream_t st = ctx->stream;
-  if (g->ng != 1) {
-    ctx->err = "the line-graph-free mode takes single graphs";
+  if (g->ng != 1 || g->V >= (int64_t(1) << 28)) {
+    ctx->err = "on-the-fly sampling takes single graphs of fewer than 2^28 nodes";
     return MOCHY_EUNSUPPORTED;
   }
-  if (g->V >= (int64_t(1) << 28)) {
-    ctx->err = "the line-graph-free mode takes fewer than 2^28 nodes";
-    return MOCHY_ERANGE;
-  }
-  mochy_status rc = project_incidence(ctx, g);
-  if (rc != MOCHY_OK) return rc;
   const int64_t E = g->E, nnz = g->nnz;
-  g->lg_free = true;
   int64_t* tmp = nullptr;
   int64_t* x64 = nullptr;
-  int64_t* up_len = nullptr;
-  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, x64); device_free(ctx, up_len); };
-  if ((rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(std::max(nnz, E) + 1) * 8)) != MOCHY_OK ||
+  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, x64); };
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(nnz + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&x64, size_t(nnz + 1) * 8)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)&up_len, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->xoff, size_t(nnz + 1) * 4)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)&g->deg, size_t(std::max<int64_t>(E, 1)) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->hsize, size_t(kHeavyBits) * kSizeSlots * 4)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->hpair,
                          size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4)) != MOCHY_OK ||
@@ -724,10 +717,7 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
     cleanup();
     return rc;
   }
-  g->bytes += size_t(nnz + 1) * 4 + size_t(E) * 8 +
-              size_t(kHeavyBits * (kHeavyBits + 1) + kHeavyTriples) * kSizeSlots * 4;
-
-  // expanded lists
+  g->bytes += size_t(nnz + 1) * 4 + size_t(kHeavyBits * (kHeavyBits + 1) + kHeavyTriples) * kSizeSlots * 4;
   phase_begin(ctx, kPhRows);
   k_xsize<<<blocks(nnz + 1, 256), 256, 0, st>>>(nnz, g->edge_ptr, g->node_edges, x64);
   launch_exclusive_scan_i64(x64, x64, nnz + 1, tmp, st);
@@ -736,7 +726,7 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
   const int64_t xtotal = ctx->h_small[0];
   if (xtotal >= (int64_t(1) << 32)) {
     cleanup();
-    ctx->err = "line-graph-free mode: the per-slot node lists would exceed 2^32 entries";
+    ctx->err = "on-the-fly sampling: the per-slot node lists would exceed 2^32 entries";
     return MOCHY_ERANGE;
   }
   if ((rc = device_alloc(ctx, (void**)&g->xnodes, size_t(std::max<int64_t>(xtotal, 1)) * 4)) != MOCHY_OK) {
@@ -754,6 +744,36 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
     k_heavy_tables<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit,
                                                    g->hsize, g->hpair, g->htriple);
   phase_end(ctx, kPhRows);
+  MOCHY_HIP(hipStreamSynchronize(st));
+  cleanup();
+  return MOCHY_OK;
+}
+
+mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g) {
+  hipStream_t st = ctx->stream;
+  if (g->ng != 1) {
+    ctx->err = "the line-graph-free mode takes single graphs";
+    return MOCHY_EUNSUPPORTED;
+  }
+  if (g->V >= (int64_t(1) << 28)) {
+    ctx->err = "the line-graph-free mode takes fewer than 2^28 nodes";
+    return MOCHY_ERANGE;
+  }
+  mochy_status rc = project_incidence(ctx, g);
+  if (rc != MOCHY_OK) return rc;
+  const int64_t E = g->E;
+  g->lg_free = true;
+  if ((rc = build_walk_tables(ctx, g)) != MOCHY_OK) return rc;
+  int64_t* tmp = nullptr;
+  int64_t* up_len = nullptr;
+  auto cleanup = [&]() { device_free(ctx, tmp); device_free(ctx, up_len); };
+  if ((rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&up_len, size_t(E + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&g->deg, size_t(std::max<int64_t>(E, 1)) * 8)) != MOCHY_OK) {
+    cleanup();
+    return rc;
+  }
+  g->bytes += size_t(E) * 8;
 
   // degrees and the hyperwedge order
   phase_begin(ctx, kPhDegree);

@@ -82,11 +82,17 @@ def test_powerlaw_graphs(ctx, seed, V, E, smax, alpha):
 
 
 def test_matches_line_graph_path(ctx):
-    # the same samples through the stored line graph and without it
+    # the same samples through the stored rows (merged) and without them
+    import paper_2310_15668_amd as M
     h = make_config("medium", scale=0.03)
-    a26, a431, _, wa = gpu_sampled(ctx, h, 300000, 5, flags=0)
+    ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 1)
+    try:
+        a26, a431, _, wa = gpu_sampled(ctx, h, 300000, 5, flags=0)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 0)
     b26, b431, _, wb = gpu_sampled(ctx, h, 300000, 5)
-    assert wa == wb and (a431 == b431).all()
+    c26, c431, _, wc = gpu_sampled(ctx, h, 300000, 5, flags=0)  # rows stored, walked on the fly
+    assert wa == wb == wc and (a431 == b431).all() and (c431 == b431).all()
     check(ctx, h, 4000, 5)
 
 
@@ -94,8 +100,13 @@ def test_chunks_and_offsets_add_up(ctx):
     # more samples than one chunk (2^25), and split ranges summing to the whole
     h = make_config("tiny")
     r = (1 << 25) + 12345
+    import paper_2310_15668_amd as M
     _, full, _, _ = gpu_sampled(ctx, h, r, 9)
-    _, ref, _, _ = gpu_sampled(ctx, h, r, 9, flags=0)
+    ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 1)
+    try:
+        _, ref, _, _ = gpu_sampled(ctx, h, r, 9, flags=0)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 0)
     assert (full == ref).all()
     _, p1, _, _ = gpu_sampled(ctx, h, 1000, 9)
     _, p2, _, _ = gpu_sampled(ctx, h, r - 1000, 9, n0=1000)

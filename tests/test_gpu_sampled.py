@@ -2,6 +2,8 @@
 
 Raw hit counts must be bit-exact (int64); the float64 estimates are compared
 against the oracle's rescaling of the oracle's hits within 1e-12 relative.
+Both enumerations of N_i ∪ N_j are checked: on the fly from the node lists
+(default) and by merging the stored rows (MOCHY_OPT_APLUS_ROWS).
 """
 import numpy as np
 import pytest
@@ -20,18 +22,22 @@ def ctx():
     c.close()
 
 
-def gpu_sampled(ctx, h, r, seed, n0=0):
+def gpu_sampled(ctx, h, r, seed, n0=0, rows=False):
     import paper_2310_15668_amd as M
-    print(f"[gpu] A+ |E|={h.num_edges} r={r} seed={seed} n0={n0}", flush=True)
+    print(f"[gpu] A+ |E|={h.num_edges} r={r} seed={seed} n0={n0} rows={rows}", flush=True)
     g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
-    out = M.mochy_count_sampled(ctx, g, r, seed, n0)
+    ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, int(rows))
+    try:
+        out = M.mochy_count_sampled(ctx, g, r, seed, n0)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 0)
     w = g.num_hyperwedges
     g.close()
     return out, w
 
 
-def check(ctx, h, r, seed, n0=0, nthreads=8):
-    (raw26, est26, raw431, est431), w = gpu_sampled(ctx, h, r, seed, n0)
+def check(ctx, h, r, seed, n0=0, nthreads=8, rows=False):
+    (raw26, est26, raw431, est431), w = gpu_sampled(ctx, h, r, seed, n0, rows)
     o26, o431, inv, ow = native.aplus_raw(h, r=r, seed=seed, n0=n0, nthreads=nthreads)
     assert inv == 0 and ow == w
     assert (raw431 == o431).all(), np.nonzero(raw431 != o431)
@@ -47,6 +53,7 @@ def test_tiny_same_seed(ctx):
     h = make_config("tiny")
     for seed in (0, 7, 2 ** 40 + 123):
         check(ctx, h, 5000, seed)
+        check(ctx, h, 5000, seed, rows=True)
 
 
 def test_prefix_offsets_add_up(ctx):
