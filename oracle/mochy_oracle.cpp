@@ -132,7 +132,7 @@ inline void add_hist(std::vector<int64_t>& local, int id3) { local[id3] += 1; }
 
 extern "C" {
 
-int orc_abi_version() { return 5; }
+int orc_abi_version() { return 6; }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy
 // as 1, 2, 3", SC'11): ten rounds of the 4x32 S-box; each round multiplies
@@ -451,14 +451,35 @@ int64_t orc_aplus_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* n
   return (int64_t)W;
 }
 
+// Every instance (connected triple) that contains e_i, counted into local:
+// each pair {e_j, e_k} of N_i (adjacent to each other or not), and each path
+// e_i - e_j - e_k with e_j in N_i and e_k in N_j outside N_i and e_i (the
+// 1-hop and 2-hop neighbourhoods explored by Algorithm 4).
+static void instances_of(const Graph& g, int64_t i, int theta, const int32_t* canon_to_id3,
+                         std::vector<int64_t>& mark, int64_t& stamp, std::vector<int32_t>& ni,
+                         std::vector<int32_t>& nj, std::vector<int64_t>& local) {
+  neighbor_list(g, i, mark, stamp, ni);
+  int64_t card[7];
+  for (size_t a = 0; a < ni.size(); ++a)
+    for (size_t b = a + 1; b < ni.size(); ++b) {
+      orc_region_cards(g.ptr, g.nodes, i, ni[a], ni[b], card);
+      add_hist(local, classify(card, theta, canon_to_id3));
+    }
+  for (int32_t j : ni) {
+    neighbor_list(g, j, mark, stamp, nj);
+    for (int32_t k : nj) {
+      if (k == i || std::binary_search(ni.begin(), ni.end(), k)) continue;
+      orc_region_cards(g.ptr, g.nodes, i, j, k, card);
+      add_hist(local, classify(card, theta, canon_to_id3));
+    }
+  }
+}
+
 // MoCHy-A (Algorithm 4), hit counts before rescaling, for sample numbers
 // n in [n0, n1): sample n draws Philox4x32-10 with counter (lo32 n, hi32 n,
 // 1, 0) and key (lo32 seed, hi32 seed); u = (x1 << 32) | x0; the sampled
-// hyperedge is floor(u * |E| / 2^64).  Every instance that contains the
-// sampled e_i adds one to raw[h(instance)]: every pair {e_j, e_k} of N_i
-// (adjacent to each other or not), and the paths e_i - e_j - e_k with e_j in
-// N_i and e_k in N_j outside N_i and e_i (its 1-hop and 2-hop
-// neighbourhoods).  With `indices`, sample n is
+// hyperedge is floor(u * |E| / 2^64), and every instance that contains it
+// adds one to raw[h(instance)] (instances_of).  With `indices`, sample n is
 // hyperedge indices[n].  Returns |E|.
 int64_t orc_mochy_a_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes, int64_t n0,
                         int64_t n1, uint64_t seed, const int64_t* indices, int theta,
@@ -485,29 +506,34 @@ int64_t orc_mochy_a_raw(int64_t E, int64_t V, const int64_t* ptr, const int32_t*
         const uint64_t u = ((uint64_t)x[1] << 32) | x[0];
         i = (int64_t)(((unsigned __int128)u * (uint64_t)E) >> 64);
       }
-      neighbor_list(g, i, mark, stamp, ni);
-      int64_t card[7];
-      // e_i adjacent to both: every pair of N_i
-      for (size_t a = 0; a < ni.size(); ++a)
-        for (size_t b = a + 1; b < ni.size(); ++b) {
-          orc_region_cards(ptr, nodes, i, ni[a], ni[b], card);
-          add_hist(local, classify(card, theta, canon_to_id3));
-        }
-      // e_i adjacent to one: e_j in N_i, e_k in N_j outside N_i and e_i
-      for (int32_t j : ni) {
-        neighbor_list(g, j, mark, stamp, nj);
-        for (int32_t k : nj) {
-          if (k == i || std::binary_search(ni.begin(), ni.end(), k)) continue;
-          orc_region_cards(ptr, nodes, i, j, k, card);
-          add_hist(local, classify(card, theta, canon_to_id3));
-        }
-      }
+      instances_of(g, i, theta, canon_to_id3, mark, stamp, ni, nj, local);
     }
 #pragma omp critical
     for (int t = 0; t < 432; ++t) total[t] += local[t];
   }
   memcpy(raw3, total.data(), 432 * sizeof(int64_t));
   return E;
+}
+
+// Hyperedge profiles (section 3.2): for each e_i with c0 <= i < c1, the
+// number of instances of each motif that contain e_i; out[(i - c0) * 432 + id3].
+void orc_hyperedge_profiles(int64_t E, int64_t V, const int64_t* ptr, const int32_t* nodes,
+                            int64_t c0, int64_t c1, int theta, const int32_t* canon_to_id3,
+                            int64_t* out, int nthreads) {
+  Graph g(E, V, ptr, nodes);
+#pragma omp parallel num_threads(nthreads)
+  {
+    std::vector<int64_t> local(432, 0);
+    std::vector<int64_t> mark(E, -1);
+    std::vector<int32_t> ni, nj;
+    int64_t stamp = -1;
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t i = c0; i < c1; ++i) {
+      std::fill(local.begin(), local.end(), 0);
+      instances_of(g, i, theta, canon_to_id3, mark, stamp, ni, nj, local);
+      memcpy(out + (i - c0) * 432, local.data(), 432 * sizeof(int64_t));
+    }
+  }
 }
 
 }  // extern "C"

@@ -62,6 +62,8 @@ def lib():
                                   ctypes.c_int64, ctypes.c_uint64, _i64p, ctypes.c_int, _i32p, _i64p,
                                   ctypes.c_int]
     L.orc_mochy_a_raw.restype = ctypes.c_int64
+    L.orc_hyperedge_profiles.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, ctypes.c_int64,
+                                         ctypes.c_int64, ctypes.c_int, _i32p, _i64p, ctypes.c_int]
     L.orc_wedge_prefix.argtypes = [ctypes.c_int64, ctypes.c_int64, _i64p, _i32p, _i64p, ctypes.c_int]
     L.orc_wedge_prefix.restype = ctypes.c_int64
     L.orc_aplus_raw.restype = ctypes.c_int64
@@ -213,3 +215,17 @@ def mochy_a_raw(h, s=None, seed=0, n0=0, indices=None, theta=1, nthreads=None):
                               int(n1), ctypes.c_uint64(seed & (2 ** 64 - 1)), ip, int(theta),
                               _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
     return fold26(out), out[1:].copy(), int(out[0]), int(e)
+
+
+def hyperedge_profiles(h, c0=0, c1=None, theta=1, nthreads=None):
+    """(hp26 [n, 26], hp431 [n, 431], invalid [n]) for hyperedges [c0, c1): the
+    instances of each motif containing each hyperedge."""
+    ptr, nodes = _csr(h)
+    c1 = h.num_edges if c1 is None else c1
+    n = max(0, c1 - c0)
+    out = np.zeros((n, 432), dtype=np.int64)
+    t = _table()
+    lib().orc_hyperedge_profiles(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), int(c0),
+                                 int(c1), int(theta), _p(t, _i32p), _p(out, _i64p), _threads(nthreads))
+    hp26 = np.array([fold26(row) for row in out]) if n else np.zeros((0, 26), dtype=np.int64)
+    return hp26, out[:, 1:].copy(), out[:, 0].copy()

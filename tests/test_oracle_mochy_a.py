@@ -43,3 +43,24 @@ def test_estimates_are_unbiased():
     big = m26 > 0.01 * m26.sum()
     rel = np.abs(est[big] - m26[big]) / m26[big]
     assert rel.max() < 0.15, rel
+
+
+def test_hyperedge_profiles_sum_to_three_times_the_counts():
+    # every instance is in the profile of each of its three hyperedges
+    for h in (make_config("tiny"), powerlaw_hypergraph(60, 250, 1, 6, 2.5, 1.2, seed=8)):
+        hp26, hp431, inv = native.hyperedge_profiles(h, nthreads=4)
+        assert (inv == 0).all() and hp26.shape == (h.num_edges, 26)
+        b26, b431, _ = native.bruteforce(h, nthreads=4)
+        assert (hp26.sum(axis=0) == 3 * b26).all() and (hp431.sum(axis=0) == 3 * b431).all()
+
+
+def test_hyperedge_profile_by_hand():
+    # e0={0,1} e1={1,2} e2={2,3}: the path e0-e1-e2 is the only connected
+    # triple (an open motif: e1 holds e0 ∩ e1 and e1 ∩ e2, disjoint)
+    h = from_edge_lists([[0, 1], [1, 2], [2, 3]], 4)
+    hp26, _, _ = native.hyperedge_profiles(h, nthreads=1)
+    assert (hp26.sum(axis=1) == 1).all()
+    t = int(np.argmax(hp26[0]))
+    assert (hp26[:, t] == 1).all() and t + 1 in range(17, 23)
+    b26, _, _ = native.bruteforce(h, nthreads=1)
+    assert b26[t] == 1
