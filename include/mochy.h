@@ -150,6 +150,17 @@ mochy_status mochy_count_sampled_edges(mochy_ctx* ctx, const mochy_graph* g, int
                                        int64_t* raw26, double* est26,
                                        int64_t* raw431, double* est431);
 
+/* Hyperedge profiles (section 3.2): for each hyperedge e with
+ * e_begin <= e < e_end, the number of instances of every h-motif (hp26, host,
+ * (e_end-e_begin) x 26 int64, row-major) and 3h-motif (hp431, host,
+ * (e_end-e_begin) x 431 int64) that contain e; either may be NULL.  Summed
+ * over all hyperedges, each motif's profile column is 3 times its count.
+ * Work per hyperedge: its 1-hop and 2-hop neighbourhoods (sum over its
+ * neighbours e_j of |N_j|), as one MoCHy-A sample.  Needs the stored line
+ * graph (MOCHY_EUNSUPPORTED otherwise). */
+mochy_status mochy_hyperedge_profiles(mochy_ctx* ctx, const mochy_graph* g, int64_t e_begin,
+                                      int64_t e_end, int64_t* hp26, int64_t* hp431);
+
 /* Significance and characteristic profile against randomized copies
  * (section 3.1).  graphs[0] is the hypergraph, graphs[1..num_graphs-1] its
  * randomized copies (host or device CSRs; the caller draws them).  All graphs

@@ -222,7 +222,9 @@ def hyperedge_profiles(h, c0=0, c1=None, theta=1, nthreads=None):
     instances of each motif containing each hyperedge."""
     ptr, nodes = _csr(h)
     c1 = h.num_edges if c1 is None else c1
-    n = max(0, c1 - c0)
+    if not 0 <= c0 <= c1 <= h.num_edges:
+        raise ValueError(f"hyperedge range [{c0}, {c1}) outside [0, {h.num_edges}]")
+    n = c1 - c0
     out = np.zeros((n, 432), dtype=np.int64)
     t = _table()
     lib().orc_hyperedge_profiles(h.num_edges, h.num_nodes, _p(ptr, _i64p), _p(nodes, _i32p), int(c0),

@@ -30,7 +30,7 @@ EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
             "mochy_graph_stats", "mochy_phase_ms", "mochy_ctx_set_option",
-            "mochy_count_sampled_edges")
+            "mochy_count_sampled_edges", "mochy_hyperedge_profiles")
 NUM_PHASES = 11
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
           "exact_correct", "sample_draw", "sample_enum", "profile_cp")
@@ -97,6 +97,8 @@ def lib():
     L.mochy_phase_ms.restype = ctypes.c_int
     L.mochy_count_sampled_edges.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
     L.mochy_count_sampled_edges.restype = ctypes.c_int
+    L.mochy_hyperedge_profiles.argtypes = [vp, vp, i64, i64, vp, vp]
+    L.mochy_hyperedge_profiles.restype = ctypes.c_int
     L.mochy_ctx_set_option.argtypes = [vp, i32, i64]
     L.mochy_ctx_set_option.restype = ctypes.c_int
     _lib = L
@@ -245,6 +247,19 @@ def mochy_count_sampled_edges(ctx: Context, g: Graph, s: int, seed: int, sample_
                                               int(sample_begin), _ptr(raw26), _ptr(est26), _ptr(raw431),
                                               _ptr(est431)), "mochy_count_sampled_edges")
     return raw26, est26, raw431, est431
+
+
+def mochy_hyperedge_profiles(ctx: Context, g: Graph, e_begin: int = 0, e_end: int | None = None,
+                             with_431: bool = True):
+    """(hp26 [n, 26], hp431 [n, 431] or None) for hyperedges [e_begin, e_end)."""
+    e_end = g.num_edges if e_end is None else int(e_end)
+    n = max(0, e_end - int(e_begin))
+    hp26 = np.zeros((n, NUM_H), dtype=np.int64)
+    hp431 = np.zeros((n, NUM_3H), dtype=np.int64) if with_431 else None
+    ctx.check(lib().mochy_hyperedge_profiles(ctx.handle, g.handle, int(e_begin), int(e_end), _ptr(hp26),
+                                             _ptr(hp431) if hp431 is not None else None),
+              "mochy_hyperedge_profiles")
+    return hp26, hp431
 
 
 def mochy_profile(ctx: Context, graphs, eps: float = 1.0):

@@ -4,6 +4,7 @@
 #include <new>
 #include <string>
 #include <unordered_set>
+#include <vector>
 
 #include "common.h"
 
@@ -552,6 +553,60 @@ extern "C" mochy_status mochy_count_sampled_edges(mochy_ctx* ctx, const mochy_gr
   if (est26) std::memcpy(est26, ctx->h_dbl, MOCHY_NUM_H * 8);
   if (est431) std::memcpy(est431, ctx->h_dbl + 32, MOCHY_NUM_3H * 8);
   return MOCHY_OK;
+}
+
+extern "C" mochy_status mochy_hyperedge_profiles(mochy_ctx* ctx, const mochy_graph* g, int64_t e_begin,
+                                                 int64_t e_end, int64_t* hp26, int64_t* hp431) {
+  if (!ctx) return MOCHY_EINVAL;
+  ctx->err.clear();
+  phases_reset(ctx);
+  if (!g || g->ctx != ctx || e_begin < 0 || e_end < e_begin || e_end > g->E) {
+    ctx->err = "bad graph or hyperedge range";
+    return MOCHY_EINVAL;
+  }
+  if (g->lg_free) {
+    ctx->err = "hyperedge profiles walk stored line-graph rows; this graph was projected without them";
+    return MOCHY_EUNSUPPORTED;
+  }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  constexpr int64_t kChunkRows = int64_t(1) << 16;
+  const int64_t rows = std::min(kChunkRows, std::max<int64_t>(e_end - e_begin, 1));
+  int64_t* d_prof = nullptr;
+  int64_t* d_prof26 = nullptr;
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&d_prof, size_t(rows) * kHistSlots * 8)) != MOCHY_OK) return rc;
+  if ((rc = device_alloc(ctx, (void**)&d_prof26, size_t(rows) * MOCHY_NUM_H * 8)) != MOCHY_OK) {
+    device_free(ctx, d_prof);
+    return rc;
+  }
+  std::vector<int64_t> h_prof(size_t(rows) * kHistSlots);
+  for (int64_t c0 = e_begin; c0 < e_end && rc == MOCHY_OK; c0 += rows) {
+    const int64_t c1 = std::min(e_end, c0 + rows), n = c1 - c0;
+    rc = profiles_device(ctx, g, c0, c1, d_prof, d_prof26);
+    if (rc != MOCHY_OK) break;
+    if (hipMemcpyAsync(h_prof.data(), d_prof, size_t(n) * kHistSlots * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        (hp26 && hipMemcpyAsync(hp26 + (c0 - e_begin) * MOCHY_NUM_H, d_prof26, size_t(n) * MOCHY_NUM_H * 8,
+                                hipMemcpyDeviceToHost, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      ctx->err = "copying the profiles back failed";
+      rc = MOCHY_EDEVICE;
+      break;
+    }
+    for (int64_t x = 0; x < n; ++x) {
+      const int64_t* row = h_prof.data() + x * kHistSlots;
+      if (row[0] != 0) {
+        ctx->err = "internal error: instances with an invalid pattern";
+        rc = MOCHY_EDEVICE;
+        break;
+      }
+      if (hp431) std::memcpy(hp431 + (c0 - e_begin + x) * MOCHY_NUM_3H, row + 1, MOCHY_NUM_3H * 8);
+    }
+  }
+  phases_collect(ctx);
+  device_free(ctx, d_prof);
+  device_free(ctx, d_prof26);
+  return rc;
 }
 
 extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r,

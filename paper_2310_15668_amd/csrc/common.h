@@ -148,6 +148,9 @@ mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uin
                             int64_t n0, int64_t* d_hist);
 mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t s, uint64_t seed,
                                   int64_t n0, int64_t* d_hist);
+// hyperedge profiles of [c0, c1): d_prof[(c1-c0) x kHistSlots], d_prof26[(c1-c0) x 26]
+mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                             int64_t* d_prof, int64_t* d_prof26);
 
 // api.hip helpers: allocation and release ordered on the context stream
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);

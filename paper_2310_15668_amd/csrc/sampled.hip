@@ -124,6 +124,10 @@ __device__ __forceinline__ uint32_t bin_of(uint32_t size, uint32_t omega) {
   return size * (MOCHY_MAX_EDGE + 1) + omega;
 }
 
+// kProfile: the "samples" are the hyperedges n0 .. n0+s-1 in order, and each
+// one's counts are written to hist_out[(i - n0) * kHistSlots + id] (its
+// hyperedge profile) instead of being summed.
+template <bool kProfile>
 __global__ __launch_bounds__(kHsThreads) void k_hsample(
     int64_t n0, int64_t s, uint64_t seed, int64_t E, const int32_t* __restrict__ row_graph,
     const int64_t* __restrict__ geoff, const int64_t* __restrict__ edge_ptr,
@@ -153,9 +157,13 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       int64_t i = -1;
       if (int64_t(q) < s) {
         const uint64_t n = uint64_t(n0) + q;
-        const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 1u, 0u),
-                                       uint32_t(seed), uint32_t(seed >> 32));
-        i = int64_t(__umul64hi((uint64_t(x.y) << 32) | x.x, uint64_t(E)));
+        if (kProfile) {
+          i = int64_t(n);
+        } else {
+          const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 1u, 0u),
+                                         uint32_t(seed), uint32_t(seed >> 32));
+          i = int64_t(__umul64hi((uint64_t(x.y) << 32) | x.x, uint64_t(E)));
+        }
       }
       s_i = i;
       s_nb = 0u;
@@ -281,10 +289,33 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       __syncthreads();
     }
     for (uint32_t q = tid; q < nb; q += kHsThreads) bins[blist[q]] = 0u;
+    if (kProfile) {  // this hyperedge's profile
+      __syncthreads();
+      unsigned long long* out = hist_out + (i - n0) * kHistSlots;
+      for (int t = tid; t < kHistSlots; t += kHsThreads) {
+        out[t] = hist[t];
+        hist[t] = 0ull;
+      }
+    }
   }
-  __syncthreads();
-  for (int t = tid; t < kHistSlots; t += kHsThreads)
-    if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
+  if (!kProfile) {
+    __syncthreads();
+    for (int t = tid; t < kHistSlots; t += kHsThreads)
+      if (hist[t]) atomicAdd(&hist_out[t], hist[t]);
+  }
+}
+
+// 26 h-motif counts of each profile row from its 431 3h-motif counts.
+__global__ void k_fold_rows(int64_t n, const int64_t* __restrict__ prof,
+                            const int32_t* __restrict__ parent, int64_t* out26) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x >= n * MOCHY_NUM_H) return;
+  const int64_t row = x / MOCHY_NUM_H;
+  const int h = int(x % MOCHY_NUM_H);
+  int64_t sum = 0;
+  for (int id3 = 1; id3 < kHistSlots; ++id3)
+    if (parent[id3] == h + 1) sum += prof[row * kHistSlots + id3];
+  out26[x] = sum;
 }
 
 }  // namespace
@@ -299,12 +330,35 @@ mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t 
   const int nw = int((g->max_graph_edges + 31) / 32);
   const size_t dyn = size_t(std::max(nw, 1)) * 8;
   if (dyn > 60 * 1024)
-    MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  int(dyn)));
+    MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
   phase_begin(ctx, kPhSample);
-  k_hsample<<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
+  k_hsample<false><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
       n0, s, seed, g->E, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
       ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
+  phase_end(ctx, kPhSample);
+  MOCHY_HIP(hipGetLastError());
+  return MOCHY_OK;
+}
+
+mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
+                             int64_t* d_prof, int64_t* d_prof26) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = c1 - c0;
+  if (n <= 0) return MOCHY_OK;
+  unsigned long long* queue = (unsigned long long*)(ctx->d_small + 496);
+  MOCHY_HIP(hipMemsetAsync(queue, 0, 8, st));
+  const int nw = int((g->max_graph_edges + 31) / 32);
+  const size_t dyn = size_t(std::max(nw, 1)) * 8;
+  if (dyn > 60 * 1024)
+    MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  phase_begin(ctx, kPhSample);
+  k_hsample<true><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
+      c0, n, 0ull, g->E, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
+      ctx->d_code_to_id3, queue, (unsigned long long*)d_prof);
+  k_fold_rows<<<unsigned((n * MOCHY_NUM_H + 255) / 256), 256, 0, st>>>(n, d_prof, ctx->d_id3_to_id26,
+                                                                        d_prof26);
   phase_end(ctx, kPhSample);
   MOCHY_HIP(hipGetLastError());
   return MOCHY_OK;
