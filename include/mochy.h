@@ -86,6 +86,15 @@ const char* mochy_last_error(const mochy_ctx* ctx);
 #define MOCHY_OPT_APLUS_ROWS 2  /* MoCHy-A+ on a graph with a stored line graph: enumerate
                                    N_i ∪ N_j on the fly from the node lists (0, default) or
                                    by merging the two stored rows (1); same hits */
+#define MOCHY_OPT_MEMO_BUDGET 3  /* on-the-fly MoCHy-A+ groups its samples by key hyperedge
+                                    (the endpoint of larger line-graph degree, Algorithm 9)
+                                    and memoizes the neighbourhood counts of keys, in
+                                    descending degree order, in a device arena of this many
+                                    bytes per call (default 1 GiB; 0 = no memoization, every
+                                    sample enumerated on its own); same hits */
+#define MOCHY_OPT_MEMO_ALL 4  /* 1: memoize every key that fits the budget; 0 (default):
+                                 only keys whose samples repay one walk of their whole
+                                 neighbourhood; same hits */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

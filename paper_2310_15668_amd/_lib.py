@@ -22,6 +22,8 @@ MOCHY_DEDUP = 1
 MOCHY_LG_FREE = 4
 MOCHY_OPT_GROUPS = 1
 MOCHY_OPT_APLUS_ROWS = 2
+MOCHY_OPT_MEMO_BUDGET = 3
+MOCHY_OPT_MEMO_ALL = 4
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 

@@ -324,6 +324,14 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     ctx->aplus_rows = value != 0;
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_MEMO_BUDGET && value >= 0) {
+    ctx->memo_budget = value;
+    return MOCHY_OK;
+  }
+  if (option == MOCHY_OPT_MEMO_ALL && (value == 0 || value == 1)) {
+    ctx->memo_all = value != 0;
+    return MOCHY_OK;
+  }
   ctx->err = "unknown option or value";
   return MOCHY_EINVAL;
 }
@@ -334,7 +342,7 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
-                  g->hpair,    g->htriple};
+                  g->hpair,    g->htriple,    g->hmask};
   for (void* b : bufs) {
     if (g->ctx) device_free(g->ctx, b);
     else (void)hipFree(b);

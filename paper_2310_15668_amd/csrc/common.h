@@ -33,6 +33,8 @@ struct mochy_ctx {
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
   bool aplus_rows = false;            // A+ by merging stored rows (MOCHY_OPT_APLUS_ROWS)
+  int64_t memo_budget = int64_t(1) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
+  bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
@@ -91,6 +93,7 @@ struct mochy_graph {
   uint32_t* xoff = nullptr;              // [nnz+1]: slot p of E_v -> start of e_k's nodes in xnodes
   int32_t* xnodes = nullptr;             // [xoff[nnz]]: node list of the hyperedge at each slot
   int64_t* deg = nullptr;                // [E]: line-graph degrees
+  uint64_t* hmask = nullptr;             // [E]: heavy nodes held by each hyperedge (bit = heavy index)
   uint32_t* hsize = nullptr;             // [64][kSizeSlots]: hyperedges holding heavy node b, by size
   uint32_t* hpair = nullptr;             // [64][64][kSizeSlots]: holding heavy nodes b1 and b2, by size
   uint32_t* htriple = nullptr;           // [C(64,3)][kSizeSlots]: holding three heavy nodes, by size
@@ -132,6 +135,15 @@ mochy_status project_free_device(mochy_ctx* ctx, mochy_graph* g);
 mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g);
 mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,
                                  int64_t n0, int64_t* d_hist);
+// memo.hip: key-grouped, memoized enumeration of sampled pairs (per call:
+// begin, one chunk at a time, end); a chunk's samples of keys left without a
+// memo are returned for the plain enumeration
+struct memo_bufs;
+mochy_status memo_begin(mochy_ctx* ctx, const mochy_graph* g, int64_t chunk, memo_bufs** out);
+mochy_status memo_chunk(mochy_ctx* ctx, const mochy_graph* g, memo_bufs* m, int64_t cnt,
+                        const int2* pairs, const int64_t* deg, int64_t* d_hist, int32_t* flags,
+                        const int2** left, int64_t* n_left);
+void memo_end(mochy_ctx* ctx, memo_bufs* m);
 // adds sum_i C(d_i, 2) to d_out[0] and sum_i d_i^2 to d_out[2]
 mochy_status free_graph_stats(mochy_ctx* ctx, const mochy_graph* g, unsigned long long* d_out);
 

@@ -26,52 +26,11 @@
 #include "classify.h"
 #include "common.h"
 #include "rng.h"
+#include "walk.h"
 
 namespace {
 
-inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const int lo = __shfl_xor(int(uint32_t(v)), off);
-    const int hi = __shfl_xor(int(uint32_t(uint64_t(v) >> 32)), off);
-    v += int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
-  }
-  return v;
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned lo = unsigned(__shfl_xor(int(uint32_t(v)), off));
-    const unsigned hi = unsigned(__shfl_xor(int(uint32_t(v >> 32)), off));
-    const uint64_t o = (uint64_t(hi) << 32) | lo;
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
-// inclusive prefix sum over the 64 lanes
-__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v, int lane) {
-  for (int off = 1; off < 64; off <<= 1) {
-    const int lo = __shfl_up(int(uint32_t(v)), off);
-    const int hi = __shfl_up(int(uint32_t(uint64_t(v) >> 32)), off);
-    const int64_t o = int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
-    if (lane >= off) v += o;
-  }
-  return v;
-}
-
 // ---------------------------------------------------------------- projection
-
-// Expanded lists are padded with -1 to a multiple of 4 nodes, so each is read
-// as independent 16-byte loads.
-constexpr int kXPad = 4;
 
 // padded size of the hyperedge at every slot of E_v (slot nnz holds 0)
 __global__ void k_xsize(int64_t nnz, const int64_t* __restrict__ edge_ptr,
@@ -97,20 +56,6 @@ __global__ void k_xfill(int64_t nnz, const int64_t* __restrict__ edge_ptr,
   xoff[p] = uint32_t(o);
   for (int64_t t = 0; t < o1 - o; ++t) xnodes[o + t] = t < c ? edge_nodes[s + t] : -1;
 }
-
-// The first 8 entries of a padded list (entries past its end read as -1).
-__device__ __forceinline__ void load8(const int32_t* __restrict__ xnodes, uint32_t xs, uint32_t xe,
-                                      int4& q0, int4& q1) {
-  const int4* src = reinterpret_cast<const int4*>(xnodes + xs);
-  q0 = src[0];
-  q1 = xe - xs > uint32_t(kXPad) ? src[1] : make_int4(-1, -1, -1, -1);
-}
-
-// position of the heavy-index triple x0 < x1 < x2 among all such triples
-__device__ __forceinline__ int triple_index(int x0, int x1, int x2) {
-  return x2 * (x2 - 1) * (x2 - 2) / 6 + x1 * (x1 - 1) / 2 + x0;
-}
-constexpr int kHeavyTriples = kHeavyBits * (kHeavyBits - 1) * (kHeavyBits - 2) / 6;
 
 // per hyperedge of size c: +1 to hsize[b][c] for each heavy node b it holds,
 // to hpair[b1][b2][c] (both orders) for each pair and to htriple[{b1,b2,b3}][c]
@@ -141,6 +86,26 @@ __global__ void k_heavy_tables(int64_t E, const int64_t* __restrict__ edge_ptr,
       }
     }
   }
+}
+
+// heavy nodes held by each hyperedge, as a 64-bit mask of heavy indices
+__global__ void k_hmask(int64_t E, const int64_t* __restrict__ edge_ptr,
+                        const int32_t* __restrict__ edge_nodes, const int8_t* __restrict__ heavy_bit,
+                        uint64_t* hmask) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  uint64_t m = 0;
+  for (int64_t q = edge_ptr[e]; q < edge_ptr[e + 1]; ++q) {
+    const int hb = heavy_bit[edge_nodes[q]];
+    if (hb >= 0) m |= 1ull << hb;
+  }
+  hmask[e] = m;
+}
+
+// line-graph degrees from stored rows
+__global__ void k_row_deg(int64_t E, const int64_t* __restrict__ lg_ptr, int64_t* deg) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < E) deg[i] = lg_ptr[i + 1] - lg_ptr[i];
 }
 
 // One wave per row i: d_i = |N_i| and the upper degree |{j > i in N_i}|.
@@ -381,81 +346,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select(
   }
 }
 
-// Enumeration: one wave per sampled pair (i, j).
-//
-// u = e_i ∪ e_j lives in a per-wave hash table of 64 buckets of 4 slots;
-// slot = ((node + 1) << 4) | flags, 0 = free, flags = in e_i (bit 0), in e_j
-// (bit 1), and the rank 1..3 of a skipped node (bits 2-3, 0 if walked).  A
-// lookup reads one bucket (16 bytes) and compares its four slots without
-// branching; a member whose bucket is full goes to a short overflow list.
-constexpr int kEnumWaves = 4;
-constexpr int kBuckets = 64;
-constexpr int kSkip = 3;                   // heavy lists counted in bulk
-constexpr int kPatterns = (1 << kSkip) - 1;
-constexpr uint32_t kFI = 1, kFJ = 2;
-constexpr int kBatch = 4;                  // samples taken from the queue at a time
-constexpr int kMaxChunks = kWave * (MOCHY_MAX_EDGE / kXPad);  // chunks of one window
-
-struct EnumLds {
-  uint4 tab[kBuckets];
-  uint32_t ovf[2 * MOCHY_MAX_EDGE];
-  int32_t ei[MOCHY_MAX_EDGE], ej[MOCHY_MAX_EDGE];
-  int32_t wn[2 * MOCHY_MAX_EDGE];          // walked nodes
-  int64_t wb[2 * MOCHY_MAX_EDGE];          // node_ptr of each walked node
-  int64_t pre[2 * MOCHY_MAX_EDGE + 1];     // prefix of walked list lengths
-  uint32_t tally[kPatterns * kSizeSlots];  // walked e_k by skipped nodes held and size
-  // one window of 64 visits, split into 4-node chunks
-  uint32_t vx[kWave];                      // start of the visit's node list in xnodes
-  uint32_t vc[kWave];                      // its first chunk in the window
-  int32_t vv[kWave];                       // the walked node it was reached through
-  unsigned long long acc[kWave];           // packed sums of its chunks
-  uint8_t cmap[kMaxChunks];                // chunk -> visit (lane)
-  uint32_t novf;
-};
-
-__device__ __forceinline__ uint32_t bucket_of(int32_t z) {
-  return (uint32_t(z) * 2654435761u) >> 26;  // 6 bits
-}
-
-// flags of node z (0 if z is not in u, or z = -1 padding); the overflow list
-// is scanned only for the (rare) samples that have one
-template <bool kOvf>
-__device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t novf) {
-  const uint32_t key = uint32_t(z + 1) << 4;
-  const uint4 q = L.tab[bucket_of(z)];
-  uint32_t f = (q.x & ~15u) == key ? q.x : 0u;
-  f |= (q.y & ~15u) == key ? q.y : 0u;
-  f |= (q.z & ~15u) == key ? q.z : 0u;
-  f |= (q.w & ~15u) == key ? q.w : 0u;
-  if (kOvf)
-    for (uint32_t t = 0; t < novf; ++t) f |= (L.ovf[t] & ~15u) == key ? L.ovf[t] : 0u;
-  return f & 15u;
-}
-
-// Packed per-visit sums (6 bits each): |e_k|, |e_k ∩ e_i|, |e_k ∩ e_j|,
-// |e_k ∩ e_i ∩ e_j|, walked members of u in e_k below the visit's node, and
-// (2 bits each) the three skipped nodes held.
-constexpr int kSc = 0, kSi = 6, kSj = 12, kSt = 18, kSb = 24, kSp = 30;
-
-template <bool kOvf>
-__device__ __forceinline__ unsigned long long chunk_sums(const EnumLds& L, int4 z4, int32_t v,
-                                                         uint32_t novf) {
-  unsigned long long s = 0;
-  auto one = [&](int32_t z) {
-    const uint32_t ff = lookup<kOvf>(L, z, novf);
-    const uint32_t rk = ff >> 2;
-    uint32_t w = z >= 0 ? 1u : 0u;
-    w += (ff & 1u) << kSi;
-    w += ((ff >> 1) & 1u) << kSj;
-    w += ((ff & 3u) == 3u ? 1u : 0u) << kSt;
-    w += (ff && !rk && z < v) ? 1u << kSb : 0u;
-    s += w;
-    s += rk ? 1ull << (kSp + 2 * (rk - 1u)) : 0ull;
-  };
-  one(z4.x); one(z4.y); one(z4.z); one(z4.w);
-  return s;
-}
-
 // Walks the lists of the non-skipped members of u for one sample, 64 visits
 // (flattened over the lists) at a time.  The node lists of a window's visits
 // are consecutive in xnodes within a list, so the window is cut into 4-node
@@ -531,23 +421,6 @@ __device__ __forceinline__ void walk_lists(EnumLds& L, int lane, int64_t T, uint
     wave_sync();
   }
   if (run_n) atomicAdd(&hist[run_id], (unsigned long long)run_n);
-}
-
-// hyperedges of size c holding every heavy node of `mask` (bits index hb[])
-__device__ __forceinline__ int64_t superset_count(uint32_t mask, const int* hb, int c,
-                                                  const uint32_t* __restrict__ hsize,
-                                                  const uint32_t* __restrict__ hpair,
-                                                  const uint32_t* __restrict__ htriple) {
-  int h[kSkip], n = 0;
-  for (int x = 0; x < kSkip; ++x)
-    if (mask & (1u << x)) h[n++] = hb[x];
-  if (n == 1) return hsize[h[0] * kSizeSlots + c];
-  if (n == 2) return hpair[(h[0] * kHeavyBits + h[1]) * kSizeSlots + c];
-  int x0 = h[0], x1 = h[1], x2 = h[2];  // sort the three heavy indices
-  if (x0 > x1) { const int t = x0; x0 = x1; x1 = t; }
-  if (x1 > x2) { const int t = x1; x1 = x2; x2 = t; }
-  if (x0 > x1) { const int t = x0; x0 = x1; x1 = t; }
-  return htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots + c];
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_enum(
@@ -713,11 +586,21 @@ mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g) {
       (rc = device_alloc(ctx, (void**)&g->hsize, size_t(kHeavyBits) * kSizeSlots * 4)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&g->hpair,
                          size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)&g->htriple, size_t(kHeavyTriples) * kSizeSlots * 4)) != MOCHY_OK) {
+      (rc = device_alloc(ctx, (void**)&g->htriple, size_t(kHeavyTriples) * kSizeSlots * 4)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&g->hmask, size_t(std::max<int64_t>(E, 1)) * 8)) != MOCHY_OK) {
     cleanup();
     return rc;
   }
-  g->bytes += size_t(nnz + 1) * 4 + size_t(kHeavyBits * (kHeavyBits + 1) + kHeavyTriples) * kSizeSlots * 4;
+  g->bytes += size_t(nnz + 1) * 4 + size_t(kHeavyBits * (kHeavyBits + 1) + kHeavyTriples) * kSizeSlots * 4 +
+              size_t(E) * 8;
+  if (g->lg_ptr && !g->deg) {  // stored rows: degrees for the key order of the memoized sampler
+    if ((rc = device_alloc(ctx, (void**)&g->deg, size_t(std::max<int64_t>(E, 1)) * 8)) != MOCHY_OK) {
+      cleanup();
+      return rc;
+    }
+    g->bytes += size_t(E) * 8;
+    if (E > 0) k_row_deg<<<blocks(E, 256), 256, 0, st>>>(E, g->lg_ptr, g->deg);
+  }
   phase_begin(ctx, kPhRows);
   k_xsize<<<blocks(nnz + 1, 256), 256, 0, st>>>(nnz, g->edge_ptr, g->node_edges, x64);
   launch_exclusive_scan_i64(x64, x64, nnz + 1, tmp, st);
@@ -740,9 +623,11 @@ mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g) {
   MOCHY_HIP(hipMemsetAsync(g->hsize, 0, size_t(kHeavyBits) * kSizeSlots * 4, st));
   MOCHY_HIP(hipMemsetAsync(g->hpair, 0, size_t(kHeavyBits) * kHeavyBits * kSizeSlots * 4, st));
   MOCHY_HIP(hipMemsetAsync(g->htriple, 0, size_t(kHeavyTriples) * kSizeSlots * 4, st));
-  if (E > 0)
+  if (E > 0) {
     k_heavy_tables<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit,
                                                    g->hsize, g->hpair, g->htriple);
+    k_hmask<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->hmask);
+  }
   phase_end(ctx, kPhRows);
   MOCHY_HIP(hipStreamSynchronize(st));
   cleanup();
@@ -817,9 +702,12 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
   int64_t *boff = nullptr, *tmp = nullptr;
   unsigned int* cursor = nullptr;
   unsigned long long* ctr = nullptr;  // [0] nkeys | select queue, [1] enum queue
+  memo_bufs* memo = nullptr;
   auto cleanup = [&]() {
     void* bufs[] = {key_i, key_m, sm, keys, pairs, bcnt, boff, tmp, cursor, ctr};
     for (void* p : bufs) device_free(ctx, p);
+    memo_end(ctx, memo);
+    memo = nullptr;
   };
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&key_i, size_t(C) * 4)) != MOCHY_OK ||
@@ -840,6 +728,12 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
   unsigned long long* enum_queue = ctr + 1;
   int32_t* flags = ctx->d_flags + 2;
   MOCHY_HIP(hipMemsetAsync(flags, 0, 4, st));
+  if (ctx->memo_budget > 0 && g->deg && g->hmask) {
+    if ((rc = memo_begin(ctx, g, C, &memo)) != MOCHY_OK) {
+      cleanup();
+      return rc;
+    }
+  }
   for (int64_t off = 0; off < r; off += C) {
     const int64_t cnt = std::min(C, r - off);
     if (hipMemsetAsync(bcnt, 0, size_t(E + 1) * 8, st) != hipSuccess ||
@@ -860,10 +754,18 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
                                                              flags);
     phase_end(ctx, kPhDraw);
     phase_begin(ctx, kPhSample);
-    k_enum<<<unsigned(ctx->num_cus) * 8u, kEnumWaves * kWave, 0, st>>>(
-        cnt, E, pairs, g->edge_ptr, g->edge_nodes, g->node_ptr, g->heavy_bit, g->xoff, g->xnodes,
-        g->hsize, g->hpair, g->htriple, ctx->d_code_to_id3, enum_queue,
-        (unsigned long long*)d_hist, flags);
+    const int2* enum_pairs = pairs;
+    int64_t n_enum = cnt;
+    if (memo && (rc = memo_chunk(ctx, g, memo, cnt, pairs, g->deg, d_hist, flags, &enum_pairs,
+                                 &n_enum)) != MOCHY_OK) {
+      cleanup();
+      return rc;
+    }
+    if (n_enum > 0)
+      k_enum<<<unsigned(ctx->num_cus) * 8u, kEnumWaves * kWave, 0, st>>>(
+          n_enum, E, enum_pairs, g->edge_ptr, g->edge_nodes, g->node_ptr, g->heavy_bit, g->xoff,
+          g->xnodes, g->hsize, g->hpair, g->htriple, ctx->d_code_to_id3, enum_queue,
+          (unsigned long long*)d_hist, flags);
     phase_end(ctx, kPhSample);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {

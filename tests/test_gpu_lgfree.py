@@ -137,6 +137,43 @@ def test_degenerate_and_errors(ctx):
     assert e.value.status == -2
 
 
+MEMO_MODES = {  # (arena bytes, memoize every key that fits)
+    "none": (0, 0),        # every sample enumerated on its own
+    "all": (1 << 30, 1),   # every key memoized
+    "tight": (2048, 1),    # the first few keys (by degree) memoized, the rest enumerated
+    "auto": (1 << 30, 0),  # the default: keys whose samples repay the memo
+}
+
+
+def set_memo(ctx, mode):
+    import paper_2310_15668_amd as M
+    budget, every = MEMO_MODES[mode]
+    ctx.set_option(M.MOCHY_OPT_MEMO_BUDGET, budget)
+    ctx.set_option(M.MOCHY_OPT_MEMO_ALL, every)
+
+
+@pytest.mark.parametrize("mode", list(MEMO_MODES))
+def test_memo_modes(ctx, mode):
+    # key-grouped samples with memoized key counts give the same hits as the
+    # oracle's per-sample enumeration, whichever keys are memoized
+    set_memo(ctx, mode)
+    try:
+        print(f"[gpu] memo mode {mode}", flush=True)
+        check(ctx, make_config("tiny"), 30000, 3)
+        rng = np.random.default_rng(5)
+        for trial in range(12):
+            h = random_graph(rng, int(rng.integers(3, 14)), int(rng.integers(2, 30)), 6)
+            check(ctx, h, 800, seed=100 + trial, nthreads=2)
+        check(ctx, powerlaw_hypergraph(40, 600, 2, 8, 2.5, 1.2, seed=11), 20000, seed=4)
+        check(ctx, powerlaw_hypergraph(400, 2500, 2, 12, 2.5, 1.0, seed=12), 20000, seed=5)
+        check(ctx, powerlaw_hypergraph(150, 1200, 2, 25, 2.5, 0.9, seed=13), 20000, seed=6)
+        h = make_config("medium", scale=0.03)
+        _, via_rows, _, _ = gpu_sampled(ctx, h, 60000, 7, flags=0)  # rows stored, walked on the fly
+        assert (via_rows == check(ctx, h, 60000, 7)).all()
+    finally:
+        set_memo(ctx, "auto")
+
+
 def test_medium_full_size_prefix(ctx):
     h = make_config("medium")
     up, _ = native.wedge_prefix(h, 16)
