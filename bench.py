@@ -377,6 +377,57 @@ def tradeoff(args):
     print(json.dumps(out), flush=True)
 
 
+def budget_sweep(args):
+    """On-the-fly MoCHy-A+ with key memos (Algorithm 9) under memo budgets
+    given as fractions of a stored line graph ((e_k, omega) entries of 8 bytes
+    over both rows of every hyperwedge), the large hypergraph without a stored
+    line graph: time per sample, the share of samples counted through a memo,
+    and the same hits at every budget."""
+    import numpy as np
+    import torch
+    import paper_2310_15668_amd as M
+    from workloads import make_config
+
+    name = args.sweep_graph
+    h = make_config(name)
+    dp, dn, V = device_csr(h)
+    torch.cuda.synchronize()
+    ctx = M.Context(0, torch.cuda.current_stream().cuda_stream)
+    g = M.mochy_project(ctx, dp, dn, V, M.MOCHY_LG_FREE)
+    W = g.num_hyperwedges
+    lg_bytes = 2 * W * 8
+    r = args.samples if args.samples else 1 << 25
+    log(f"{name}: |E|={h.num_edges} |wedges|={W} r={r}; line graph as (e_k, omega) lists: {lg_bytes / 2**30:.1f} GiB")
+    M.mochy_count_sampled(ctx, g, min(r, 1 << 20), 99)  # warm-up
+    rows, ref = [], None
+    for frac in (0.0, 1e-5, 1e-4, 1e-3, 1e-2):
+        budget = min(int(frac * lg_bytes), 16 << 30)
+        ctx.set_option(M.MOCHY_OPT_MEMO_BUDGET, budget)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        raw26, _, raw431, _ = M.mochy_count_sampled(ctx, g, r, args.seed)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ph = M.mochy_phase_ms(ctx)
+        ms = M.mochy_memo_stats(ctx)
+        if ref is None:
+            ref = raw431
+        rows.append({"budget_fraction_of_line_graph": frac, "budget_bytes": budget, "seconds": dt,
+                     "samples_per_s": r / dt, "enum_ms": ph["sample_enum"], "draw_ms": ph["sample_draw"],
+                     "memo_sample_share": ms["memo_samples"] / max(ms["samples"], 1),
+                     "memo_keys": ms["memo_keys"], "arena_bytes_used": ms["arena_bytes"],
+                     "same_hits": bool((raw431 == ref).all())})
+        log(rows[-1])
+    g.close()
+    ctx.close()
+    out = {"metric": "MoCHy-A+ samples/s vs key-memo budget (on-the-fly, Algorithm 9)",
+           "value": None, "unit": "samples/s", "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+           "config": {"workload": f"{name} hypergraph, no stored line graph; one call of {r} samples",
+                      "hyperwedges": W, "line_graph_list_bytes": lg_bytes, "seed": args.seed},
+           "points": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,7 +435,9 @@ def main():
                     help="timed steps (default 3; 1 for large-aplus)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="medium-exact",
-                    choices=["medium-exact", "large-aplus", "batched-cp", "serving", "tradeoff"])
+                    choices=["medium-exact", "large-aplus", "batched-cp", "serving", "tradeoff", "budget"])
+    ap.add_argument("--sweep-graph", default="large", choices=["medium", "large"],
+                    help="budget: hypergraph of the memo-budget sweep")
     ap.add_argument("--samples", type=int, default=0,
                     help="large-aplus: samples per step (default 5%% of the hyperwedges)")
     ap.add_argument("--seed", type=int, default=2, help="large-aplus: Philox key")
@@ -420,6 +473,8 @@ def main():
     if args.workload == "serving":
         serving(args)
         return
+    if args.workload == "budget":
+        return budget_sweep(args)
     if args.workload == "tradeoff":
         tradeoff(args)
         return

@@ -90,11 +90,14 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                     (the endpoint of larger line-graph degree, Algorithm 9)
                                     and memoizes the neighbourhood counts of keys, in
                                     descending degree order, in a device arena of this many
-                                    bytes per call (default 1 GiB; 0 = no memoization, every
+                                    bytes per call (default 4 GiB; 0 = no memoization, every
                                     sample enumerated on its own); same hits */
 #define MOCHY_OPT_MEMO_ALL 4  /* 1: memoize every key that fits the budget; 0 (default):
-                                 only keys whose samples repay one walk of their whole
-                                 neighbourhood; same hits */
+                                 only keys with at least 4 samples in a chunk; same hits */
+#define MOCHY_OPT_MEMO_POOL 5  /* heavy nodes a key's samples skip on their other side:
+                                  any (0, default; the 16 with the most list entries
+                                  if the key would need too many node sets) or always
+                                  those 16 (1); same hits */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
@@ -213,6 +216,14 @@ mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* ou
  * ms: host, MOCHY_NUM_PHASES doubles. */
 #define MOCHY_NUM_PHASES 11
 mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);
+
+/* What the key memos of the most recent on-the-fly MoCHy-A+ call did
+ * (Algorithm 9 with a memo budget, MOCHY_OPT_MEMO_BUDGET): out[0] samples,
+ * out[1] samples counted through a key memo (the rest were enumerated on
+ * their own), out[2] keys memoized (summed over chunks), out[3] most arena
+ * bytes used by one chunk, out[4] list entries E_v walked to build the memos.
+ * Zeros after calls that sampled nothing on the fly.  out: host, 5 int64. */
+mochy_status mochy_memo_stats(const mochy_ctx* ctx, int64_t* out);
 
 #ifdef __cplusplus
 }

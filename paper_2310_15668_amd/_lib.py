@@ -24,6 +24,7 @@ MOCHY_OPT_GROUPS = 1
 MOCHY_OPT_APLUS_ROWS = 2
 MOCHY_OPT_MEMO_BUDGET = 3
 MOCHY_OPT_MEMO_ALL = 4
+MOCHY_OPT_MEMO_POOL = 5
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 
@@ -31,7 +32,7 @@ MAX_EDGE = 32
 EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_project",
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
-            "mochy_graph_stats", "mochy_phase_ms", "mochy_ctx_set_option",
+            "mochy_graph_stats", "mochy_phase_ms", "mochy_memo_stats", "mochy_ctx_set_option",
             "mochy_count_sampled_edges", "mochy_hyperedge_profiles")
 NUM_PHASES = 11
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
@@ -97,6 +98,8 @@ def lib():
     L.mochy_graph_stats.restype = ctypes.c_int
     L.mochy_phase_ms.argtypes = [vp, vp]
     L.mochy_phase_ms.restype = ctypes.c_int
+    L.mochy_memo_stats.argtypes = [vp, vp]
+    L.mochy_memo_stats.restype = ctypes.c_int
     L.mochy_count_sampled_edges.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
     L.mochy_count_sampled_edges.restype = ctypes.c_int
     L.mochy_hyperedge_profiles.argtypes = [vp, vp, i64, i64, vp, vp]
@@ -282,6 +285,14 @@ def mochy_graph_stats(ctx: Context, g: Graph) -> dict:
     keys = ("num_edges", "num_nodes", "nnz", "hyperwedges", "max_line_degree", "candidates",
             "candidate_min_size_sum", "sum_deg_sq")
     return {k: int(v) for k, v in zip(keys, out)}
+
+
+def mochy_memo_stats(ctx: Context) -> dict:
+    """Key memos of the last on-the-fly MoCHy-A+ call."""
+    out = np.zeros(5, dtype=np.int64)
+    ctx.check(lib().mochy_memo_stats(ctx.handle, _ptr(out)), "mochy_memo_stats")
+    return {"samples": int(out[0]), "memo_samples": int(out[1]), "memo_keys": int(out[2]),
+            "arena_bytes": int(out[3]), "memo_walk": int(out[4])}
 
 
 def mochy_phase_ms(ctx: Context) -> dict:

@@ -202,11 +202,18 @@ static void phases_reset(mochy_ctx* c) {
   c->phases_run = 0;
   c->phases_begun = 0;
   for (double& m : c->phase_ms) m = 0.0;
+  for (int64_t& m : c->memo_stats) m = 0;
 }
 
 extern "C" mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms) {
   if (!ctx || !ms) return MOCHY_EINVAL;
   std::memcpy(ms, ctx->phase_ms, sizeof(ctx->phase_ms));
+  return MOCHY_OK;
+}
+
+extern "C" mochy_status mochy_memo_stats(const mochy_ctx* ctx, int64_t* out) {
+  if (!ctx || !out) return MOCHY_EINVAL;
+  std::memcpy(out, ctx->memo_stats, sizeof(ctx->memo_stats));
   return MOCHY_OK;
 }
 
@@ -332,6 +339,10 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     ctx->memo_all = value != 0;
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_MEMO_POOL && (value == 0 || value == 1)) {
+    ctx->memo_pool = value != 0;
+    return MOCHY_OK;
+  }
   ctx->err = "unknown option or value";
   return MOCHY_EINVAL;
 }
@@ -342,7 +353,7 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
-                  g->hpair,    g->htriple,    g->hmask};
+                  g->hpair,    g->htriple,    g->hmask,      g->hbig_key,   g->hbig_val};
   for (void* b : bufs) {
     if (g->ctx) device_free(g->ctx, b);
     else (void)hipFree(b);

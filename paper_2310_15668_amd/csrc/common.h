@@ -33,8 +33,9 @@ struct mochy_ctx {
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
   bool aplus_rows = false;            // A+ by merging stored rows (MOCHY_OPT_APLUS_ROWS)
-  int64_t memo_budget = int64_t(1) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
+  int64_t memo_budget = int64_t(4) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
   bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
+  bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
@@ -49,6 +50,10 @@ struct mochy_ctx {
   uint32_t phases_begun = 0;          // phases whose start event was recorded
   uint32_t phases_run = 0;            // phases recorded since the last reset
   double phase_ms[MOCHY_NUM_PHASES] = {};
+  // last on-the-fly sampling call: samples, samples counted through key
+  // memos, keys memoized, most arena bytes one chunk used, list entries the
+  // memo builds walked
+  int64_t memo_stats[5] = {};
 };
 
 // Phase timing: bracket device work on the context stream.
@@ -94,12 +99,24 @@ struct mochy_graph {
   int32_t* xnodes = nullptr;             // [xoff[nnz]]: node list of the hyperedge at each slot
   int64_t* deg = nullptr;                // [E]: line-graph degrees
   uint64_t* hmask = nullptr;             // [E]: heavy nodes held by each hyperedge (bit = heavy index)
+  // sets of 4 to 6 heavy nodes: open-addressed table (key = set as a mask of
+  // heavy indices, 0 = free) of the hyperedges holding the set, by size
+  unsigned long long* hbig_key = nullptr;  // [1 << hbig_log2]
+  uint32_t* hbig_val = nullptr;            // [1 << hbig_log2][kSizeSlots]
+  int hbig_log2 = 0;
+  bool memo_ok = false;                  // heavy-set tables complete: key memos allowed
   uint32_t* hsize = nullptr;             // [64][kSizeSlots]: hyperedges holding heavy node b, by size
+                                         // (slot 0: sizes above kSizeTail)
   uint32_t* hpair = nullptr;             // [64][64][kSizeSlots]: holding heavy nodes b1 and b2, by size
   uint32_t* htriple = nullptr;           // [C(64,3)][kSizeSlots]: holding three heavy nodes, by size
   size_t bytes = 0;                      // device bytes held
 };
+// Heavy-node tables count hyperedges by size c = 1..32 in slot c; slot 0
+// (no hyperedge is empty) holds those of size above kSizeTail, whose classes
+// never depend on the exact size where the tables are read with at most three
+// nodes taken off (the region keeps at least 6 nodes).
 constexpr int kSizeSlots = MOCHY_MAX_EDGE + 1;
+constexpr int kSizeTail = 8;
 
 // Per (centre i, neighbour x) record, 16 bytes:
 //   x: bit p set iff the p-th node of e_i (ascending) is in e_x

@@ -76,13 +76,19 @@ __global__ void k_heavy_tables(int64_t E, const int64_t* __restrict__ edge_ptr,
   for (unsigned long long m0 = held; m0; m0 &= m0 - 1) {
     const int x0 = __ffsll((long long)m0) - 1;
     atomicAdd(&hsize[x0 * kSizeSlots + c], 1u);
+    if (c > kSizeTail) atomicAdd(&hsize[x0 * kSizeSlots], 1u);
     for (unsigned long long m1 = m0 & (m0 - 1); m1; m1 &= m1 - 1) {
       const int x1 = __ffsll((long long)m1) - 1;
       atomicAdd(&hpair[(x0 * kHeavyBits + x1) * kSizeSlots + c], 1u);
       atomicAdd(&hpair[(x1 * kHeavyBits + x0) * kSizeSlots + c], 1u);
+      if (c > kSizeTail) {
+        atomicAdd(&hpair[(x0 * kHeavyBits + x1) * kSizeSlots], 1u);
+        atomicAdd(&hpair[(x1 * kHeavyBits + x0) * kSizeSlots], 1u);
+      }
       for (unsigned long long m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) {
         const int x2 = __ffsll((long long)m2) - 1;
         atomicAdd(&htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots + c], 1u);
+        if (c > kSizeTail) atomicAdd(&htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots], 1u);
       }
     }
   }
@@ -100,6 +106,55 @@ __global__ void k_hmask(int64_t E, const int64_t* __restrict__ edge_ptr,
     if (hb >= 0) m |= 1ull << hb;
   }
   hmask[e] = m;
+}
+
+// Sets of 4 to 6 heavy nodes held together by some hyperedge: their number
+// (upper bound of the table's entries); a hyperedge with more than
+// kBigHeavy heavy nodes makes the table too large (flag).
+constexpr int kBigHeavy = 16;
+
+__host__ __device__ constexpr int64_t choose(int n, int k) {
+  return k < 0 || k > n ? 0 : (k == 0 ? 1 : choose(n - 1, k - 1) * n / k);
+}
+
+__global__ void k_bigcount(int64_t E, const uint64_t* __restrict__ hmask, unsigned long long* total,
+                           int32_t* too_many) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int m = __popcll(hmask[e]);
+  if (m > kBigHeavy) { atomicOr(too_many, 1); return; }
+  const int64_t n = choose(m, 4) + choose(m, 5) + choose(m, 6);
+  if (n) atomicAdd(total, (unsigned long long)n);
+}
+
+__global__ void k_bigfill(int64_t E, const int64_t* __restrict__ edge_ptr,
+                          const uint64_t* __restrict__ hmask, unsigned long long* key, uint32_t* val,
+                          int log2cap) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const uint64_t hm = hmask[e];
+  const int m = __popcll(hm);
+  if (m < 4 || m > kBigHeavy) return;
+  const int c = int(edge_ptr[e + 1] - edge_ptr[e]);
+  int h[kBigHeavy];
+  int n = 0;
+  for (uint64_t r = hm; r; r &= r - 1) h[n++] = __ffsll((long long)r) - 1;
+  const uint32_t cap_mask = (1u << log2cap) - 1u;
+  for (uint32_t sub = 0; sub < (1u << m); ++sub) {
+    const int k = __popc(sub);
+    if (k < 4 || k > 6) continue;
+    uint64_t xm = 0;
+    for (int t = 0; t < m; ++t)
+      if (sub & (1u << t)) xm |= 1ull << h[t];
+    for (uint32_t s = big_slot(xm, log2cap);; s = (s + 1u) & cap_mask) {
+      const unsigned long long prev = atomicCAS(&key[s], 0ull, (unsigned long long)xm);
+      if (prev == 0ull || prev == xm) {
+        atomicAdd(&val[uint64_t(s) * kSizeSlots + c], 1u);
+        if (c > kSizeTail) atomicAdd(&val[uint64_t(s) * kSizeSlots], 1u);
+        break;
+      }
+    }
+  }
 }
 
 // line-graph degrees from stored rows
@@ -202,7 +257,8 @@ __global__ void k_deg_stats(int64_t E, const int64_t* __restrict__ deg, unsigned
 
 // ------------------------------------------------------------------ sampling
 
-constexpr int64_t kChunk = int64_t(1) << 25;  // samples per chunk
+constexpr int64_t kChunk = int64_t(1) << 25;      // samples per chunk
+constexpr int64_t kChunkMemo = int64_t(1) << 27;  // with key memos: more samples per key and build
 
 // Hyperwedge index of each sample -> (row i, rank m of j among i's upper
 // neighbours); counts samples per row and lists each row drawn once.
@@ -628,6 +684,32 @@ mochy_status build_walk_tables(mochy_ctx* ctx, mochy_graph* g) {
                                                    g->hsize, g->hpair, g->htriple);
     k_hmask<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->hmask);
   }
+  // table of the sets of 4 to 6 heavy nodes (for the key memos)
+  MOCHY_HIP(hipMemsetAsync(ctx->d_small, 0, 16, st));
+  if (E > 0)
+    k_bigcount<<<blocks(E, 256), 256, 0, st>>>(E, g->hmask, (unsigned long long*)ctx->d_small,
+                                                reinterpret_cast<int32_t*>(ctx->d_small + 1));
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, ctx->d_small, 16, hipMemcpyDeviceToHost, st));
+  MOCHY_HIP(hipStreamSynchronize(st));
+  const int64_t big_sets = ctx->h_small[0];
+  const bool too_many = (*reinterpret_cast<const int32_t*>(ctx->h_small + 1)) != 0;
+  g->memo_ok = !too_many && big_sets <= (int64_t(1) << 22);
+  if (g->memo_ok) {
+    int lg = 6;
+    while ((int64_t(1) << lg) < 2 * big_sets) ++lg;
+    const size_t cap = size_t(1) << lg;
+    if ((rc = device_alloc(ctx, (void**)&g->hbig_key, cap * 8)) != MOCHY_OK ||
+        (rc = device_alloc(ctx, (void**)&g->hbig_val, cap * kSizeSlots * 4)) != MOCHY_OK) {
+      cleanup();
+      return rc;
+    }
+    g->hbig_log2 = lg;
+    g->bytes += cap * (8 + kSizeSlots * 4);
+    MOCHY_HIP(hipMemsetAsync(g->hbig_key, 0, cap * 8, st));
+    MOCHY_HIP(hipMemsetAsync(g->hbig_val, 0, cap * kSizeSlots * 4, st));
+    if (big_sets > 0)
+      k_bigfill<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->hmask, g->hbig_key, g->hbig_val, lg);
+  }
   phase_end(ctx, kPhRows);
   MOCHY_HIP(hipStreamSynchronize(st));
   cleanup();
@@ -695,7 +777,8 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
   MOCHY_HIP(hipMemsetAsync(d_hist, 0, kHistSlots * 8, st));
   if (g->W == 0 || r == 0) return MOCHY_OK;
   const int64_t E = g->E;
-  const int64_t C = std::min(r, kChunk);
+  const bool use_memo = ctx->memo_budget > 0 && g->deg && g->memo_ok;
+  const int64_t C = std::min(r, use_memo ? kChunkMemo : kChunk);
   int32_t *key_i = nullptr, *key_m = nullptr, *sm = nullptr, *keys = nullptr;
   int2* pairs = nullptr;
   unsigned long long* bcnt = nullptr;
@@ -728,7 +811,7 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
   unsigned long long* enum_queue = ctr + 1;
   int32_t* flags = ctx->d_flags + 2;
   MOCHY_HIP(hipMemsetAsync(flags, 0, 4, st));
-  if (ctx->memo_budget > 0 && g->deg && g->hmask) {
+  if (use_memo) {
     if ((rc = memo_begin(ctx, g, C, &memo)) != MOCHY_OK) {
       cleanup();
       return rc;
@@ -756,6 +839,7 @@ mochy_status sampled_free_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r
     phase_begin(ctx, kPhSample);
     const int2* enum_pairs = pairs;
     int64_t n_enum = cnt;
+    ctx->memo_stats[0] += cnt;
     if (memo && (rc = memo_chunk(ctx, g, memo, cnt, pairs, g->deg, d_hist, flags, &enum_pairs,
                                  &n_enum)) != MOCHY_OK) {
       cleanup();

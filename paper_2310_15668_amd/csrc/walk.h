@@ -102,8 +102,8 @@ __device__ __forceinline__ uint32_t bucket_of(int32_t z) {
 
 // flags of node z (0 if z is not in u, or z = -1 padding); the overflow list
 // is scanned only for the (rare) samples that have one
-template <bool kOvf>
-__device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t novf) {
+template <bool kOvf, class Tab>
+__device__ __forceinline__ uint32_t lookup(const Tab& L, int32_t z, uint32_t novf) {
   const uint32_t key = uint32_t(z + 1) << 4;
   const uint4 q = L.tab[bucket_of(z)];
   uint32_t f = (q.x & ~15u) == key ? q.x : 0u;
@@ -122,8 +122,8 @@ __device__ __forceinline__ uint32_t lookup(const EnumLds& L, int32_t z, uint32_t
 // are not walked).
 constexpr int kSc = 0, kSi = 6, kSj = 12, kSt = 18, kSb = 24, kSp = 30;
 
-template <bool kOvf, bool kJOnly = false>
-__device__ __forceinline__ unsigned long long chunk_sums(const EnumLds& L, int4 z4, int32_t v,
+template <bool kOvf, bool kJOnly = false, class Tab>
+__device__ __forceinline__ unsigned long long chunk_sums(const Tab& L, int4 z4, int32_t v,
                                                          uint32_t novf) {
   unsigned long long s = 0;
   auto one = [&](int32_t z) {
@@ -140,6 +140,37 @@ __device__ __forceinline__ unsigned long long chunk_sums(const EnumLds& L, int4 
   };
   one(z4.x); one(z4.y); one(z4.z); one(z4.w);
   return s;
+}
+
+__device__ __forceinline__ uint32_t big_slot(uint64_t mask, int log2cap) {
+  return uint32_t((mask * 0x9E3779B97F4A7C15ull) >> (64 - log2cap));
+}
+
+// hyperedges of size c holding every heavy node of the set `xmask` (bits =
+// heavy indices, 1 to 6 of them)
+__device__ __forceinline__ int64_t heavy_set_count(uint64_t xmask, int c,
+                                                   const uint32_t* __restrict__ hsize,
+                                                   const uint32_t* __restrict__ hpair,
+                                                   const uint32_t* __restrict__ htriple,
+                                                   const unsigned long long* __restrict__ big_key,
+                                                   const uint32_t* __restrict__ big_val,
+                                                   int big_log2) {
+  const int n = __popcll(xmask);
+  const int x0 = __ffsll((long long)xmask) - 1;
+  if (n == 1) return hsize[x0 * kSizeSlots + c];
+  const uint64_t r1 = xmask & (xmask - 1);
+  const int x1 = __ffsll((long long)r1) - 1;
+  if (n == 2) return hpair[(x0 * kHeavyBits + x1) * kSizeSlots + c];
+  if (n == 3) {
+    const int x2 = __ffsll((long long)(r1 & (r1 - 1))) - 1;
+    return htriple[int64_t(triple_index(x0, x1, x2)) * kSizeSlots + c];
+  }
+  const uint32_t cap_mask = (1u << big_log2) - 1u;
+  for (uint32_t s = big_slot(xmask, big_log2);; s = (s + 1u) & cap_mask) {
+    const unsigned long long k = big_key[s];
+    if (k == xmask) return big_val[uint64_t(s) * kSizeSlots + c];
+    if (k == 0ull) return 0;
+  }
 }
 
 // hyperedges of size c holding every heavy node of `mask` (bits index hb[])

@@ -97,9 +97,10 @@ def test_matches_line_graph_path(ctx):
 
 
 def test_chunks_and_offsets_add_up(ctx):
-    # more samples than one chunk (2^25), and split ranges summing to the whole
+    # more samples than one chunk (2^27 with key memos, 2^25 without), and
+    # split ranges summing to the whole
     h = make_config("tiny")
-    r = (1 << 25) + 12345
+    r = (1 << 27) + 12345
     import paper_2310_15668_amd as M
     _, full, _, _ = gpu_sampled(ctx, h, r, 9)
     ctx.set_option(M.MOCHY_OPT_APLUS_ROWS, 1)
@@ -137,19 +138,21 @@ def test_degenerate_and_errors(ctx):
     assert e.value.status == -2
 
 
-MEMO_MODES = {  # (arena bytes, memoize every key that fits)
-    "none": (0, 0),        # every sample enumerated on its own
-    "all": (1 << 30, 1),   # every key memoized
-    "tight": (2048, 1),    # the first few keys (by degree) memoized, the rest enumerated
-    "auto": (1 << 30, 0),  # the default: keys whose samples repay the memo
+MEMO_MODES = {  # (arena bytes, memoize every key that fits, always the skip pool)
+    "none": (0, 0, 0),        # every sample enumerated on its own
+    "all": (1 << 30, 1, 0),   # every key memoized
+    "pool": (1 << 30, 1, 1),  # every key memoized, other sides skipping only the pool
+    "tight": (2048, 1, 0),    # the first few keys (by degree) memoized, the rest enumerated
+    "auto": (4 << 30, 0, 0),  # the default: keys with enough samples
 }
 
 
 def set_memo(ctx, mode):
     import paper_2310_15668_amd as M
-    budget, every = MEMO_MODES[mode]
+    budget, every, pool = MEMO_MODES[mode]
     ctx.set_option(M.MOCHY_OPT_MEMO_BUDGET, budget)
     ctx.set_option(M.MOCHY_OPT_MEMO_ALL, every)
+    ctx.set_option(M.MOCHY_OPT_MEMO_POOL, pool)
 
 
 @pytest.mark.parametrize("mode", list(MEMO_MODES))
