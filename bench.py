@@ -34,8 +34,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "exact.hip")
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_grouped_medium_counters.md")
-FREE_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "free.hip")
-ENUM_SUMMARY = os.path.join(ROOT, "profiles", "k_enum_large_aplus.md")
+# the on-the-fly enumeration phase: k_enum (free.hip), k_memo and k_msample
+# (memo.hip), their shared walk (walk.h)
+ENUM_SRCS = [os.path.join(ROOT, "paper_2310_15668_amd", "csrc", f) for f in ("free.hip", "memo.hip", "walk.h")]
+ENUM_SUMMARY = os.path.join(ROOT, "profiles", "enum_phase_large_aplus.md")
 WORKLOAD = ("medium exact MoCHy-E: 20000 nodes, 100000 drawn hyperedges (duplicates removed), "
             "sizes 2..25 P(s)~s^-2.5, Zipf(1.0) node popularity, seed 1")
 
@@ -44,10 +46,14 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def source_digest(path):
+def source_digest(paths):
+    """sha256 of a source file, or of several files' contents in order."""
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    d = hashlib.sha256()
+    for path in ([paths] if isinstance(paths, str) else paths):
+        with open(path, "rb") as f:
+            d.update(f.read())
+    return d.hexdigest()
 
 
 def measured_traffic(summary=None, source=None):
@@ -132,7 +138,8 @@ def device_csr(h):
 def large_aplus(args):
     """MoCHy-A+ on the large hypergraph without a stored line graph: one step =
     projection (validation, transpose, per-slot node lists, degrees, hyperwedge
-    order) + r samples (draw, group by row, pick e_j, enumerate N_i ∪ N_j)."""
+    order) + r samples (draw, group by row, pick e_j; group by key hyperedge,
+    memoize the keys' neighbourhood counts, enumerate each sample's other side)."""
     import numpy as np
     import torch
     import paper_2310_15668_amd as M
@@ -167,6 +174,7 @@ def large_aplus(args):
         # so the hits add up to one call's); est = hits * |wedges| / (w * r)
         raw26 = np.zeros(26, dtype=np.int64)
         est26 = np.zeros(26)
+        memo = {"samples": 0, "memo_samples": 0, "memo_keys": 0, "memo_walk": 0}
         for n0 in range(0, r, 1 << 28):
             rr = min(1 << 28, r - n0)
             c26, e26, _, _ = M.mochy_count_sampled(ctx, g, rr, args.seed, n0)
@@ -174,6 +182,9 @@ def large_aplus(args):
             est26 += e26 * (rr / r)
             for k, v in M.mochy_phase_ms(ctx).items():
                 phase_sum[k] += v
+            for k, v in M.mochy_memo_stats(ctx).items():
+                if k in memo:
+                    memo[k] += v
             log(f"  samples {n0 + rr}/{r}")
         g.close()
     torch.cuda.synchronize()
@@ -197,14 +208,17 @@ def large_aplus(args):
                    "sample_fraction": r / W, "seed": args.seed, "max_line_degree": st["max_line_degree"],
                    "samples_per_s": r / (dt / K), "estimated_connected_triples": float(est26.sum()),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_enum (enumeration of N_i ∪ N_j)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "enumeration phase: k_memo + k_msample, k_enum for keys left without a memo",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(ENUM_SUMMARY, FREE_KERNEL_SRC),
-                     "traffic_launch": "one chunk of 2^25 samples",
+                     "traffic": measured_traffic(ENUM_SUMMARY, ENUM_SRCS),
+                     "traffic_launch": "one chunk of 2^27 samples",
                      "model": "16 + 4*min(|e_i|,|e_j|,|e_k|) >= 24 bytes per (sample, e_k) pair",
                      "kernel_ms": enum_ms, "pairs_per_s": pairs / (enum_ms * 1e-3)},
         "phases_ms": {k: v / K for k, v in phase_sum.items() if v},
+        "key_memos": {"memo_sample_share": memo["memo_samples"] / max(memo["samples"], 1),
+                      "keys_memoized": memo["memo_keys"], "memo_walk_entries": memo["memo_walk"]},
     }
     print(json.dumps(out), flush=True)
 

@@ -90,7 +90,7 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                     (the endpoint of larger line-graph degree, Algorithm 9)
                                     and memoizes the neighbourhood counts of keys, in
                                     descending degree order, in a device arena of this many
-                                    bytes per call (default 4 GiB; 0 = no memoization, every
+                                    bytes per call (default 16 GiB; 0 = no memoization, every
                                     sample enumerated on its own); same hits */
 #define MOCHY_OPT_MEMO_ALL 4  /* 1: memoize every key that fits the budget; 0 (default):
                                  only keys with at least 4 samples in a chunk; same hits */

@@ -143,7 +143,7 @@ MEMO_MODES = {  # (arena bytes, memoize every key that fits, always the skip poo
     "all": (1 << 30, 1, 0),   # every key memoized
     "pool": (1 << 30, 1, 1),  # every key memoized, other sides skipping only the pool
     "tight": (2048, 1, 0),    # the first few keys (by degree) memoized, the rest enumerated
-    "auto": (4 << 30, 0, 0),  # the default: keys with enough samples
+    "auto": (16 << 30, 0, 0),  # the default: keys with enough samples
 }
 
 
