@@ -353,7 +353,8 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
   void* bufs[] = {g->edge_ptr, g->edge_nodes, g->node_ptr, g->node_edges, g->heavy_bit, g->lg_ptr,
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
-                  g->hpair,    g->htriple,    g->hmask,      g->hbig_key,   g->hbig_val};
+                  g->hpair,    g->htriple,    g->hmask,      g->hbig_key,   g->hbig_val,
+                  g->recm};
   for (void* b : bufs) {
     if (g->ctx) device_free(g->ctx, b);
     else (void)hipFree(b);

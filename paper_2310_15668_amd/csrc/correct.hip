@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) void k_light_fix(
     const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
     const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
-    const int32_t* __restrict__ lg_col, const uint4* __restrict__ rec,
+    const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
@@ -153,31 +153,45 @@ __global__ __launch_bounds__(256) void k_light_fix(
     const int64_t kl = k - e0;
     const uint32_t kw = bm[kl >> 5];
     const int qk = int(rank[kl >> 5] + __popc(kw & ((1u << (kl & 31)) - 1u)));
-    const uint32_t mjk = rec[jb + qk].x;
+    const uint32_t mjk = recm[jb + qk];
     const int64_t kb = lg_ptr[k];
     const int dk = int(lg_ptr[k + 1] - kb);
     const uint32_t sizek = uint32_t(edge_ptr[k + 1] - edge_ptr[k]);
-    for (int r = threadIdx.x; r < dk; r += blockDim.x) {
-      const int32_t i = lg_col[kb + r];
-      if (i < c0 || i >= c1) continue;
-      const int64_t il = i - e0;
-      const uint32_t iw = bm[il >> 5];
-      const uint32_t ibit = 1u << (il & 31);
-      if (!(iw & ibit)) continue;  // not a neighbour of e_j (or i == j)
-      const uint32_t mji = rec[jb + int(rank[il >> 5] + __popc(iw & (ibit - 1u)))].x;
-      const uint32_t ls = __popc(mjk & L & ~mji);
-      if (ls == 0u) continue;  // the pair kernel was exact at this centre
-      const uint32_t wik = __popc(rec[kb + r].x);
-      const uint32_t t = __popc(mji & mjk);
-      const uint32_t r5h = __popc(mjk & H & ~mji);
-      const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
-      const uint32_t pj = __popc(mji);
-      Side K;
-      K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
-      const uint32_t oj = sizej - pj;
-      const bool above = (j > i) && (k > i);
-      if (above || (t | r5h) == 0u) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h)]], ~0ull);
-      if (above) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h + ls)]], 1ull);
+    // row k scanned kUnroll entries per thread at a time, their loads issued
+    // together (the scan is bound by load latency, not bandwidth)
+    constexpr int kUnroll = 8;
+    const int step = int(blockDim.x);
+    for (int r0 = threadIdx.x; r0 < dk; r0 += kUnroll * step) {
+      int32_t iv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int r = r0 + u * step;
+        iv[u] = r < dk ? lg_col[kb + r] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t i = iv[u];
+        const int r = r0 + u * step;
+        if (i < c0 || i >= c1) continue;  // also the -1 past the row's end
+        const int64_t il = i - e0;
+        const uint32_t iw = bm[il >> 5];
+        const uint32_t ibit = 1u << (il & 31);
+        if (!(iw & ibit)) continue;  // not a neighbour of e_j (or i == j)
+        const uint32_t mji = recm[jb + int(rank[il >> 5] + __popc(iw & (ibit - 1u)))];
+        const uint32_t ls = __popc(mjk & L & ~mji);
+        if (ls == 0u) continue;  // the pair kernel was exact at this centre
+        const uint32_t wik = __popc(recm[kb + r]);
+        const uint32_t t = __popc(mji & mjk);
+        const uint32_t r5h = __popc(mjk & H & ~mji);
+        const uint32_t pj = __popc(mji);
+        const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
+        Side K;
+        K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
+        const uint32_t oj = sizej - pj;
+        const bool above = (j > i) && (k > i);
+        if (above || (t | r5h) == 0u) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h)]], ~0ull);
+        if (above) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h + ls)]], 1ull);
+      }
     }
   }
   __syncthreads();
@@ -259,7 +273,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
                                                partners);
   k_light_fix<<<unsigned(nowners), 256, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners, g->edge_ptr,
                                                    g->edge_nodes, g->heavy_bit, g->lg_ptr, g->lg_col,
-                                                   g->rec, ctx->d_code_to_id3,
+                                                   g->recm, ctx->d_code_to_id3,
                                                    (unsigned long long*)d_hist);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
