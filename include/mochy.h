@@ -208,8 +208,9 @@ mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* ou
 /* Milliseconds spent in each device phase by the most recent call on this
  * context, from HIP events recorded on the context stream (0 for phases the
  * call did not run).  Phases: 0 upload+validate, 1 transpose + heavy-node
- * pick, 2 line-graph degrees, 3 line-graph rows (line-graph-free mode: the
- * per-slot node lists and heavy-node tables), 4 region records,
+ * pick, 2 line-graph degrees, 3 line-graph rows (line-graph-free mode, and
+ * a stored-row graph's first on-the-fly sampling call: the per-slot node
+ * lists and heavy-node tables), 4 region records,
  * 5 exact scheduling, 6 exact pair kernel, 7 exact light-node correction,
  * 8 sampling draws (line-graph-free mode: with grouping by row and the pick
  * of e_j), 9 sampled enumeration, 10 profile significance + CP.

@@ -642,6 +642,16 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   int64_t* d_hist = ctx->d_small + 64;
+  if (!g->lg_free && !ctx->aplus_rows && !g->walk_tried && g->ng == 1 && g->V < (int64_t(1) << 28)) {
+    // first on-the-fly sampling of a single graph with stored rows: the
+    // per-slot node lists and heavy tables (a few MB; without them, when the
+    // lists would exceed 2^32 entries, sampling merges the stored rows)
+    mochy_graph* gm = const_cast<mochy_graph*>(g);
+    gm->walk_tried = true;
+    const mochy_status wr = build_walk_tables(ctx, gm);
+    if (wr == MOCHY_ERANGE) ctx->err.clear();
+    else if (wr != MOCHY_OK) return wr;
+  }
   const bool walk = g->xnodes != nullptr && (g->lg_free || !ctx->aplus_rows);
   mochy_status rc = walk ? sampled_free_device(ctx, g, r, seed, sample_begin, d_hist)
                          : sampled_device(ctx, g, r, seed, sample_begin, d_hist);

@@ -106,6 +106,7 @@ struct mochy_graph {
   uint32_t* hbig_val = nullptr;            // [1 << hbig_log2][kSizeSlots]
   int hbig_log2 = 0;
   bool memo_ok = false;                  // heavy-set tables complete: key memos allowed
+  bool walk_tried = false;               // walk tables built (or found too large) for a graph with rows
   uint32_t* hsize = nullptr;             // [64][kSizeSlots]: hyperedges holding heavy node b, by size
                                          // (slot 0: sizes above kSizeTail)
   uint32_t* hpair = nullptr;             // [64][64][kSizeSlots]: holding heavy nodes b1 and b2, by size

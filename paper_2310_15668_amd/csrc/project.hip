@@ -375,12 +375,7 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   cleanup();
   const int32_t f1 = *reinterpret_cast<int32_t*>(ctx->h_small);
   if (f1 & kFlagDup) { ctx->err = "duplicate hyperedges (pass MOCHY_DEDUP for host input)"; return MOCHY_EDUP; }
-  // a single graph also gets what the on-the-fly sampler walks (a few MB);
-  // without it (too many nodes), sampling merges the stored rows
-  if (g->ng == 1 && g->V < (int64_t(1) << 28)) {
-    rc = build_walk_tables(ctx, g);
-    if (rc == MOCHY_ERANGE) ctx->err.clear();
-    else if (rc != MOCHY_OK) return rc;
-  }
+  // what the on-the-fly sampler walks is built on a single graph's first
+  // sampling call (mochy_count_sampled)
   return MOCHY_OK;
 }
