@@ -124,12 +124,38 @@ __device__ __forceinline__ uint32_t bin_of(uint32_t size, uint32_t omega) {
   return size * (MOCHY_MAX_EDGE + 1) + omega;
 }
 
-// kProfile: the "samples" are the hyperedges n0 .. n0+s-1 in order, and each
-// one's counts are written to hist_out[(i - n0) * kHistSlots + id] (its
-// hyperedge profile) instead of being summed.
+// The sampled hyperedge of each sample (kProfile: the hyperedges n0 ..
+// n0+s-1 in order) and its number of work items: one per 256 neighbours
+// (at least one), so that a sample's rows spread over many blocks.
+template <bool kProfile>
+__global__ void k_hs_items(int64_t n0, int64_t s, uint64_t seed, int64_t E,
+                           const int64_t* __restrict__ lg_ptr, int64_t* sample_i, int64_t* nitems) {
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q == s) nitems[s] = 0;
+  if (q >= s) return;
+  const uint64_t n = uint64_t(n0) + uint64_t(q);
+  int64_t i;
+  if (kProfile) {
+    i = int64_t(n);
+  } else {
+    const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 1u, 0u), uint32_t(seed),
+                                   uint32_t(seed >> 32));
+    i = int64_t(__umul64hi((uint64_t(x.y) << 32) | x.x, uint64_t(E)));
+  }
+  sample_i[q] = i;
+  const int64_t d = lg_ptr[i + 1] - lg_ptr[i];
+  nitems[q] = d > 0 ? (d + kHsThreads - 1) / kHsThreads : 1;
+}
+
+// One block per work item (sample, chunk of 256 neighbours of e_i): N_i as an
+// LDS bitmap with ranks, the chunk's neighbours' rows, and for chunk 0 also
+// every pair of N_i counted as disjoint.  kProfile: the item's counts are
+// added to hist_out[(i - n0) * kHistSlots + id] (the hyperedge's profile,
+// zeroed before) instead of being summed.
 template <bool kProfile>
 __global__ __launch_bounds__(kHsThreads) void k_hsample(
-    int64_t n0, int64_t s, uint64_t seed, int64_t E, const int32_t* __restrict__ row_graph,
+    int64_t n0, int64_t s, const int64_t* __restrict__ sample_i, const int64_t* __restrict__ ioff,
+    const int32_t* __restrict__ row_graph,
     const int64_t* __restrict__ geoff, const int64_t* __restrict__ edge_ptr,
     const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ lg_col,
     const uint4* __restrict__ rec, const uint16_t* __restrict__ code_to_id3,
@@ -144,33 +170,35 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
   __shared__ uint32_t c_mji[kHsThreads], c_b[kHsThreads];
   __shared__ int64_t c_pre[kHsThreads + 1];
   __shared__ int32_t part[kHsThreads];
-  __shared__ int64_t s_i;
+  __shared__ int64_t s_i, s_chunk;
   __shared__ uint32_t s_nb;
   const int tid = threadIdx.x;
+  const int64_t total = ioff[s];
   for (int t = tid; t < kNumCodes; t += kHsThreads) lut[t] = code_to_id3[t];
   for (int t = tid; t < kHistSlots; t += kHsThreads) hist[t] = 0ull;
   for (int t = tid; t < kBins; t += kHsThreads) bins[t] = 0u;
   for (;;) {
     __syncthreads();
     if (tid == 0) {
-      const unsigned long long q = atomicAdd(queue, 1ull);
-      int64_t i = -1;
-      if (int64_t(q) < s) {
-        const uint64_t n = uint64_t(n0) + q;
-        if (kProfile) {
-          i = int64_t(n);
-        } else {
-          const uint4 x = philox_4x32_10(make_uint4(uint32_t(n), uint32_t(n >> 32), 1u, 0u),
-                                         uint32_t(seed), uint32_t(seed >> 32));
-          i = int64_t(__umul64hi((uint64_t(x.y) << 32) | x.x, uint64_t(E)));
+      const int64_t item = int64_t(atomicAdd(queue, 1ull));
+      int64_t i = -1, chunk = 0;
+      if (item < total) {
+        int64_t lo = 0, hi = s;  // the sample: last q with ioff[q] <= item
+        while (hi - lo > 1) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (ioff[mid] <= item) lo = mid; else hi = mid;
         }
+        i = sample_i[lo];
+        chunk = item - ioff[lo];
       }
       s_i = i;
+      s_chunk = chunk;
       s_nb = 0u;
     }
     __syncthreads();
     const int64_t i = s_i;
     if (i < 0) break;
+    const int64_t chunk = s_chunk;
     const int gi = row_graph[i];
     const int64_t e0 = geoff[gi];
     const int nw = int((geoff[gi + 1] - e0 + 31) / 32);
@@ -184,10 +212,12 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
     for (int p = tid; p < di; p += kHsThreads) {
       const int64_t x = lg_col[ib + p] - e0;
       atomicOr(&bm[x >> 5], 1u << (x & 31));
-      const uint4 r = rec[ib + p];
-      const uint32_t om = __popc(r.x);
-      if (atomicAdd(&bins[bin_of(om + (r.y & 0xffu), om)], 1u) == 0u)
-        blist[atomicAdd(&s_nb, 1u)] = bin_of(om + (r.y & 0xffu), om);
+      if (chunk == 0) {
+        const uint4 r = rec[ib + p];
+        const uint32_t om = __popc(r.x);
+        if (atomicAdd(&bins[bin_of(om + (r.y & 0xffu), om)], 1u) == 0u)
+          blist[atomicAdd(&s_nb, 1u)] = bin_of(om + (r.y & 0xffu), om);
+      }
     }
     __syncthreads();
     {  // ranks: set bits before each word
@@ -223,8 +253,8 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, sk, 0u)]], w);
     }
     __syncthreads();
-    // the rows of e_i's neighbours, 256 neighbours at a time
-    for (int jc = 0; jc < di; jc += kHsThreads) {
+    // the rows of this item's 256 neighbours of e_i
+    for (int jc = int(chunk) * kHsThreads; jc < di && jc < int(chunk + 1) * kHsThreads; jc += kHsThreads) {
       const int nj = min(kHsThreads, di - jc);
       int64_t dj = 0;
       if (tid < nj) {
@@ -289,11 +319,11 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       __syncthreads();
     }
     for (uint32_t q = tid; q < nb; q += kHsThreads) bins[blist[q]] = 0u;
-    if (kProfile) {  // this hyperedge's profile
+    if (kProfile) {  // this item's part of the hyperedge's profile
       __syncthreads();
       unsigned long long* out = hist_out + (i - n0) * kHistSlots;
       for (int t = tid; t < kHistSlots; t += kHsThreads) {
-        out[t] = hist[t];
+        if (hist[t]) atomicAdd(&out[t], hist[t]);
         hist[t] = 0ull;
       }
     }
@@ -318,6 +348,37 @@ __global__ void k_fold_rows(int64_t n, const int64_t* __restrict__ prof,
   out26[x] = sum;
 }
 
+// Work items of hyperedge sampling: the samples' hyperedges and the prefix of
+// their item counts.
+struct HsItems {
+  int64_t* sample_i = nullptr;
+  int64_t* ioff = nullptr;
+  int64_t* tmp = nullptr;
+  void release(mochy_ctx* ctx) {
+    device_free(ctx, sample_i);
+    device_free(ctx, ioff);
+    device_free(ctx, tmp);
+    sample_i = ioff = tmp = nullptr;
+  }
+};
+
+template <bool kProfile>
+mochy_status hs_items(mochy_ctx* ctx, const mochy_graph* g, int64_t n0, int64_t s, uint64_t seed,
+                      HsItems& it) {
+  mochy_status rc;
+  if ((rc = device_alloc(ctx, (void**)&it.sample_i, size_t(s) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&it.ioff, size_t(s + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&it.tmp, scan_tmp_elems(s + 1) * 8)) != MOCHY_OK) {
+    it.release(ctx);
+    return rc;
+  }
+  // item counts into ioff, scanned in place
+  k_hs_items<kProfile><<<unsigned((s + 1 + 255) / 256), 256, 0, ctx->stream>>>(n0, s, seed, g->E, g->lg_ptr,
+                                                                               it.sample_i, it.ioff);
+  launch_exclusive_scan_i64(it.ioff, it.ioff, s + 1, it.tmp, ctx->stream);
+  return MOCHY_OK;
+}
+
 }  // namespace
 
 mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t s, uint64_t seed,
@@ -332,12 +393,17 @@ mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t 
   if (dyn > 60 * 1024)
     MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample<false>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  HsItems it;
+  mochy_status rc = hs_items<false>(ctx, g, n0, s, seed, it);
+  if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
   k_hsample<false><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
-      n0, s, seed, g->E, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
+      n0, s, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
       ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
   phase_end(ctx, kPhSample);
-  MOCHY_HIP(hipGetLastError());
+  const hipError_t e = hipGetLastError();
+  it.release(ctx);
+  MOCHY_HIP(e);
   return MOCHY_OK;
 }
 
@@ -348,19 +414,25 @@ mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, i
   if (n <= 0) return MOCHY_OK;
   unsigned long long* queue = (unsigned long long*)(ctx->d_small + 496);
   MOCHY_HIP(hipMemsetAsync(queue, 0, 8, st));
+  MOCHY_HIP(hipMemsetAsync(d_prof, 0, size_t(n) * kHistSlots * 8, st));
   const int nw = int((g->max_graph_edges + 31) / 32);
   const size_t dyn = size_t(std::max(nw, 1)) * 8;
   if (dyn > 60 * 1024)
     MOCHY_HIP(hipFuncSetAttribute((const void*)k_hsample<true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(dyn)));
+  HsItems it;
+  mochy_status rc = hs_items<true>(ctx, g, c0, n, 0ull, it);
+  if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
   k_hsample<true><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
-      c0, n, 0ull, g->E, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
+      c0, n, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
       ctx->d_code_to_id3, queue, (unsigned long long*)d_prof);
   k_fold_rows<<<unsigned((n * MOCHY_NUM_H + 255) / 256), 256, 0, st>>>(n, d_prof, ctx->d_id3_to_id26,
                                                                         d_prof26);
   phase_end(ctx, kPhSample);
-  MOCHY_HIP(hipGetLastError());
+  const hipError_t e = hipGetLastError();
+  it.release(ctx);
+  MOCHY_HIP(e);
   return MOCHY_OK;
 }
 
