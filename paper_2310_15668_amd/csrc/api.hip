@@ -331,6 +331,10 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     ctx->aplus_rows = value != 0;
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_GROUP_CAPACITY && value >= 0) {
+    ctx->group_cap_bytes = value;
+    return MOCHY_OK;
+  }
   if (option == MOCHY_OPT_MEMO_BUDGET && value >= 0) {
     ctx->memo_budget = value;
     return MOCHY_OK;

@@ -33,6 +33,7 @@ struct mochy_ctx {
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
   bool aplus_rows = false;            // A+ by merging stored rows (MOCHY_OPT_APLUS_ROWS)
+  int64_t group_cap_bytes = int64_t(24) << 30;  // one-pass grouping limit (MOCHY_OPT_GROUP_CAPACITY)
   int64_t memo_budget = int64_t(16) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
   bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)

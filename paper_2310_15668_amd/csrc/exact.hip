@@ -343,13 +343,15 @@ __device__ __forceinline__ uint64_t sig_hash(const uint4& r, uint32_t o, uint64_
 
 constexpr int kGroupTries = 40;  // restarts before a row gives up (flags bit 0)
 
-// Row i's groups go to positions [lg_ptr[i] - cap0, + its group count) of
-// grec / gcnt (a row has at most as many groups as records), the count to
-// gcount[i].
+// kWrite: row i's groups go to positions [base[i] - cap0, + its group count)
+// of grec / gcnt: base = lg_ptr with the row-capacity layout (a row has at
+// most as many groups as records), or the prefix of the counts with cap0 = 0
+// (compact layout, counted by a first pass).  The count goes to gcount[i].
+template <bool kWrite>
 __global__ __launch_bounds__(kGroupThreads) void k_group(
     int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
-    const uint4* __restrict__ rec, int64_t* gcount, int64_t cap0, uint4* grec, uint2* gcnt,
-    int32_t* flags) {
+    const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* flags) {
   __shared__ unsigned long long key[kGroupSlots];
   __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
   __shared__ uint32_t s_out, s_bad;
@@ -362,12 +364,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
   int64_t parts = (d + kGroupSlots / 2 - 1) / (kGroupSlots / 2);
   if (parts < 1) parts = 1;
   uint64_t seed = 0;
-  const int64_t obase = base - cap0;
+  const int64_t obase = kWrite ? obase_of[i] - cap0 : 0;
   for (int tries = 0;; ++tries) {  // until a grouping without overflow or hash collision
     if (tries == kGroupTries) {  // cannot happen with a sound hash; the host pairs records
       if (tid == 0) {
         atomicOr(flags, 1);
-        gcount[i] = 0;
+        if (gcount) gcount[i] = 0;
       }
       return;
     }
@@ -428,15 +430,17 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
       for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
         if (key[t] == 0ull) continue;
         const uint32_t pos = atomicAdd(&s_out, 1u);
-        const uint4 f = row[first[t]];
-        grec[obase + pos] = make_uint4(f.x, clamp_outside(f), f.z, f.w);
-        gcnt[obase + pos] = make_uint2(nall[t], nabove[t]);
+        if (kWrite) {
+          const uint4 f = row[first[t]];
+          grec[obase + pos] = make_uint4(f.x, clamp_outside(f), f.z, f.w);
+          gcnt[obase + pos] = make_uint2(nall[t], nabove[t]);
+        }
       }
       __syncthreads();
     }
     if (!redo) break;
   }
-  if (tid == 0) gcount[i] = int64_t(s_out);
+  if (tid == 0 && gcount) gcount[i] = int64_t(s_out);
 }
 
 // Pairs of groups (x < y) and each group with itself, weighted as above.
@@ -496,7 +500,7 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
 
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
-    const int64_t* __restrict__ lg_ptr, int64_t cap0,
+    const int64_t* __restrict__ gbase, int64_t cap0,
     const uint4* __restrict__ grec, const uint2* __restrict__ gcnt,
     const int32_t* __restrict__ order, const int64_t* __restrict__ rstart, int64_t nslots,
     const int32_t* __restrict__ row_graph, unsigned long long* queue,
@@ -529,7 +533,7 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
     dirty_g = g;
     const int nbi = int(rstart[lo + 1] - rstart[lo]);
     const int b = nbi - 1 - int(q - rstart[lo]);
-    const int64_t gb = lg_ptr[i] - cap0;
+    const int64_t gb = gbase[i] - cap0;
     const int ng = int(goff[i + 1] - goff[i]);
     const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
     const uint4* __restrict__ grow = grec + gb;
@@ -616,12 +620,17 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   return MOCHY_OK;
 }
 
-// Groups of rows [c0, c1), in one pass: row i's groups at grec / gcnt
-// [lg_ptr[i] - cap0, ...), goff[E+1] the prefix of the rows' group counts.
-// Returns MOCHY_ENOMEM (nothing held) if the group arrays do not fit or a
-// row could not be grouped; the caller then pairs every record.
+// Groups of rows [c0, c1): goff[E+1] the prefix of the rows' group counts,
+// row i's groups at grec / gcnt [gbase[i] - cap0, ...).  For a single graph
+// with up to ctx->group_cap_bytes of row capacity, one pass writes each row's
+// groups at its line-graph offset (gbase = lg_ptr); otherwise (batches,
+// larger graphs) the groups are counted first and allocated exactly
+// (gbase = goff, cap0 = 0).  Returns MOCHY_ENOMEM (nothing held) if
+// the group arrays do not fit or a row could not be grouped; the caller then
+// pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
-                          int64_t** goff, uint4** grec, uint2** gcnt, int64_t* cap0) {
+                          int64_t** goff, uint4** grec, uint2** gcnt, const int64_t** gbase,
+                          int64_t* cap0) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E;
   int64_t* cntarr = nullptr;
@@ -640,25 +649,53 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     *gcnt = nullptr;
     return rc;
   };
-  // capacity: the records of rows [c0, c1)
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + c0, 8, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, g->lg_ptr + c1, 8, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
-  *cap0 = ctx->h_small[0];
-  const int64_t cap = ctx->h_small[1] - ctx->h_small[0];
+  const int64_t row0 = ctx->h_small[0];
+  const int64_t cap = ctx->h_small[1] - row0;
+  // one pass into row capacity for a single graph (a batch's transient row
+  // capacity would be far larger than its groups)
+  const bool by_rows = g->ng == 1 && cap * 24 <= ctx->group_cap_bytes;
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8)) != MOCHY_OK)
+      (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK)
     return fail(rc);
   MOCHY_HIP(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st));
-  if (c1 > c0)
-    k_group<<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec, cntarr,
-                                                         *cap0, *grec, *gcnt, ctx->d_flags + 3);
-  launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
+  if (by_rows) {
+    *gbase = g->lg_ptr;
+    *cap0 = row0;
+    if ((rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16)) != MOCHY_OK ||
+        (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8)) != MOCHY_OK)
+      return fail(rc);
+    if (c1 > c0)
+      k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
+                                                                cntarr, g->lg_ptr, row0, *grec, *gcnt,
+                                                                ctx->d_flags + 3);
+    launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
+  } else {
+    *gbase = *goff;
+    *cap0 = 0;
+    if (c1 > c0)
+      k_group<false><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
+                                                                 cntarr, nullptr, 0, nullptr, nullptr,
+                                                                 ctx->d_flags + 3);
+    launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
+    MOCHY_HIP(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st));
+    MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
+    MOCHY_HIP(hipStreamSynchronize(st));
+    if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
+    const int64_t ngroups = ctx->h_small[0];
+    if ((rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(ngroups, 1)) * 16)) != MOCHY_OK ||
+        (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(ngroups, 1)) * 8)) != MOCHY_OK)
+      return fail(rc);
+    if (c1 > c0)
+      k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
+                                                                nullptr, *goff, 0, *grec, *gcnt,
+                                                                ctx->d_flags + 3);
+  }
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
   if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
@@ -678,6 +715,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
   const unsigned grid = unsigned(ctx->num_cus) * 8u;
   int64_t* goff = nullptr;
+  const int64_t* gbase = nullptr;
   int64_t cap0 = 0;
   uint4* grec = nullptr;
   uint2* gcnt = nullptr;
@@ -685,7 +723,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_begin(ctx, kPhSched);
   bool grouped = ctx->group_neighbours;
   if (grouped) {
-    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &cap0);
+    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gbase, &cap0);
     if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
       grouped = false;
       ctx->err.clear();
@@ -705,7 +743,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
   if (grouped)
-    k_exact_grouped<<<grid, 256, 0, st>>>(g->edge_ptr, goff, g->lg_ptr, cap0, grec, gcnt, S.order,
+    k_exact_grouped<<<grid, 256, 0, st>>>(g->edge_ptr, goff, gbase, cap0, grec, gcnt, S.order,
                                           S.rstart, S.rows,
                                           g->row_graph, S.queue, ctx->d_code_to_id3,
                                           (unsigned long long*)d_hist);

@@ -27,7 +27,8 @@ def request_bytes(graphs) -> int:
     """Upper bound of the device memory a request holds while it runs.
 
     Per graph: incidence and transpose, per-row arrays, and the line graph
-    (4-byte column + 16-byte record + 4-byte record mask per row entry, with
+    (4-byte column + 16-byte record + 4-byte record mask per row entry, and
+    the exact counting's neighbour groups, 24 bytes per row entry, with
     |wedges| bounded by sum_v C(deg(v), 2)).
     """
     total = 0
@@ -36,7 +37,7 @@ def request_bytes(graphs) -> int:
         nnz = int(ptr[-1]) if E > 0 else 0
         deg = np.bincount(np.asarray(nodes), minlength=int(num_nodes)).astype(np.int64)
         wedges = int((deg * (deg - 1) // 2).sum())
-        total += 16 * (E + 1) + 8 * nnz + 9 * (int(num_nodes) + 1) + 40 * E + 2 * wedges * 24
+        total += 16 * (E + 1) + 8 * nnz + 9 * (int(num_nodes) + 1) + 40 * E + 2 * wedges * 48
     return total
 
 

@@ -223,11 +223,17 @@ def test_grouped_equals_every_pair(ctx):
             b26, b431 = M.mochy_count_exact(ctx, g)
             cuts = [0, h.num_edges // 3, h.num_edges]
             parts = [M.mochy_count_exact_range(ctx, g, x, y)[1] for x, y in zip(cuts[:-1], cuts[1:])]
+            # groups counted first and allocated exactly (the layout of large batches)
+            ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 0)
+            c26, c431 = M.mochy_count_exact(ctx, g)
+            cparts = [M.mochy_count_exact_range(ctx, g, x, y)[1] for x, y in zip(cuts[:-1], cuts[1:])]
         finally:
             ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+            ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
             g.close()
         assert (a431 == b431).all() and (a26 == b26).all()
-        assert (sum(parts) == b431).all()
+        assert (c431 == b431).all() and (c26 == b26).all()
+        assert (sum(parts) == b431).all() and (sum(cparts) == b431).all()
         r26, r431, _ = native.mochy_e(h, nthreads=8)
         assert (b431 == r431).all()
     with pytest.raises(M.MochyError) as e:

@@ -50,7 +50,7 @@ def test_request_bytes_bounds_the_line_graph():
     h = from_edge_lists([[0, 1], [1, 2], [1, 3]], 4)
     g = (h.edge_ptr, h.edge_nodes, h.num_nodes)
     # node 1 is in 3 hyperedges: at most 3 hyperwedges, 2 row entries each
-    per = 16 * 4 + 8 * 6 + 9 * 5 + 40 * 3 + 2 * 3 * 24
+    per = 16 * 4 + 8 * 6 + 9 * 5 + 40 * 3 + 2 * 3 * 48
     assert request_bytes([g]) == per
     assert request_bytes([g, g]) == 2 * per
     assert isinstance(request_bytes([g]), int) and np.int64(request_bytes([g])) > 0
