@@ -343,18 +343,30 @@ __device__ __forceinline__ uint64_t sig_hash(const uint4& r, uint32_t o, uint64_
 
 constexpr int kGroupTries = 40;  // restarts before a row gives up (flags bit 0)
 
-// kWrite: row i's groups go to positions [base[i] - cap0, + its group count)
+// Open class of a group: (|its overlap with e_i|, min(outside, 2)); the code
+// of an open pair depends on j only through it.  Below kOpenClasses.
+constexpr int kOpenClasses = 128;
+__device__ __forceinline__ uint32_t open_class(uint32_t m, uint32_t o) {
+  return uint32_t(__popc(m)) * 3u + st3(o);
+}
+
+// kWrite: row i's groups go to its region [base[i] - cap0, base[i + 1] - cap0)
 // of grec / gcnt: base = lg_ptr with the row-capacity layout (a row has at
 // most as many groups as records), or the prefix of the counts with cap0 = 0
-// (compact layout, counted by a first pass).  The count goes to gcount[i].
+// (compact layout, counted by a first pass).  Groups with members above the
+// centre fill the region from its start (their count goes to gna[i]), the
+// others from its end, so that the pair kernel can take the pairs that can
+// only be open apart; within each hash part of the row, both kinds are
+// ordered by open class.  The count goes to gcount[i].
 template <bool kWrite>
 __global__ __launch_bounds__(kGroupThreads) void k_group(
     int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
     const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
-    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* flags) {
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags) {
   __shared__ unsigned long long key[kGroupSlots];
   __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
-  __shared__ uint32_t s_out, s_bad;
+  __shared__ uint32_t s_out, s_outb, s_bad;
+  __shared__ uint32_t cfill[2 * kOpenClasses];  // per (above, open class): count, then next slot
   const int tid = threadIdx.x;
   const int64_t i = c0 + blockIdx.x;
   const int64_t base = lg_ptr[i];
@@ -365,6 +377,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
   if (parts < 1) parts = 1;
   uint64_t seed = 0;
   const int64_t obase = kWrite ? obase_of[i] - cap0 : 0;
+  const int64_t oend = kWrite ? obase_of[i + 1] - cap0 : 0;  // one past the row's region
   for (int tries = 0;; ++tries) {  // until a grouping without overflow or hash collision
     if (tries == kGroupTries) {  // cannot happen with a sound hash; the host pairs records
       if (tid == 0) {
@@ -374,7 +387,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
       return;
     }
     __syncthreads();
-    if (tid == 0) s_out = 0u;
+    if (tid == 0) {
+      s_out = 0u;
+      s_outb = 0u;
+    }
     bool redo = false;
     for (int64_t part = 0; part < parts && !redo; ++part) {
       for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
@@ -427,61 +443,169 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         redo = true;
         break;
       }
+      if (!kWrite) {
+        for (int t = tid; t < kGroupSlots; t += kGroupThreads)
+          if (key[t] != 0ull) atomicAdd(&s_out, 1u);
+        __syncthreads();
+        continue;
+      }
+      // counting sort of the part's groups by (above, open class)
+      for (int t = tid; t < 2 * kOpenClasses; t += kGroupThreads) cfill[t] = 0u;
+      __syncthreads();
       for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
         if (key[t] == 0ull) continue;
-        const uint32_t pos = atomicAdd(&s_out, 1u);
-        if (kWrite) {
-          const uint4 f = row[first[t]];
-          grec[obase + pos] = make_uint4(f.x, clamp_outside(f), f.z, f.w);
-          gcnt[obase + pos] = make_uint2(nall[t], nabove[t]);
+        const uint4 f = row[first[t]];
+        atomicAdd(&cfill[(nabove[t] != 0u ? 0 : kOpenClasses) + open_class(f.x, clamp_outside(f))], 1u);
+      }
+      __syncthreads();
+      if (tid < 2 * kWave) {  // exclusive prefix per kind (one wave each), from where its output stands
+        static_assert(kOpenClasses == 2 * kWave, "two classes per lane");
+        const int kind = tid / kWave, ln = tid % kWave;
+        uint32_t* cf = cfill + kind * kOpenClasses + 2 * ln;
+        const uint32_t n0 = cf[0], n1 = cf[1];
+        uint32_t inc = n0 + n1;
+        for (int off = 1; off < kWave; off <<= 1) {
+          const uint32_t up = __shfl_up(inc, off, kWave);
+          if (ln >= off) inc += up;
         }
+        const uint32_t start = (kind == 0 ? s_out : s_outb) + inc - (n0 + n1);
+        cf[0] = start;
+        cf[1] = start + n0;
+      }
+      __syncthreads();
+      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
+        if (key[t] == 0ull) continue;
+        const bool above = nabove[t] != 0u;
+        const uint4 f = row[first[t]];
+        const uint32_t oc = clamp_outside(f);
+        const uint32_t pos = atomicAdd(&cfill[(above ? 0 : kOpenClasses) + open_class(f.x, oc)], 1u);
+        const int64_t o = above ? obase + pos : oend - 1 - pos;
+        grec[o] = make_uint4(f.x, oc, f.z, f.w);
+        gcnt[o] = make_uint2(nall[t], nabove[t]);
+      }
+      __syncthreads();
+      if (tid == 0) {  // both kinds' ends: the last class's next slot
+        s_out = cfill[kOpenClasses - 1];
+        s_outb = cfill[2 * kOpenClasses - 1];
       }
       __syncthreads();
     }
     if (!redo) break;
   }
-  if (tid == 0 && gcount) gcount[i] = int64_t(s_out);
+  if (tid == 0) {
+    if (gcount) gcount[i] = int64_t(s_out) + s_outb;
+    if (kWrite) gna[i] = int32_t(s_out);
+  }
 }
 
 // Pairs of groups (x < y) and each group with itself, weighted as above.
 constexpr int kGCopies = 2;
 constexpr int kGStride = kHistSlots + 1;
 
-template <bool kDiag>
-__device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t a,
+// kNarrow: every row is shorter than 2^24, so a weight is a product of two
+// 24-bit counts (two full-rate multiplies instead of a 64-bit one).
+// A disjoint pair (open at the centre) weighs nall_j * nall_k, an
+// overlapping one nabove_j * nabove_k; ka_m is the lane's nabove with every
+// bit set or clear as row j has members above the centre or not, so the
+// selected lane count is zero exactly when the pair weighs nothing (every
+// group holds at least one neighbour, and kn = 0 on lanes past the row).
+template <bool kDiag, bool kNarrow>
+__device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks,
                                            const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
-                                           uint32_t ka, int kp, bool valid,
-                                           const uint16_t* __restrict__ lut,
+                                           uint32_t ka, int kp, const uint16_t* __restrict__ lut,
                                            unsigned long long* hist) {
   const uint32_t mj = rj.x;
-  const bool disjoint = ((mj & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u;
-  const uint64_t w = disjoint ? uint64_t(cj.x) * kn : uint64_t(cj.y) * ka;
-  bool act = valid && w != 0ull;
+  const uint32_t xm = mj & k.m, xl = rj.z & khl, xh = rj.w & khh;
+  const bool disjoint = (xm | xl | xh) == 0u;
+  // the counts of j are uniform: kept in scalar registers as two 32-bit
+  // values (seen as one 64-bit word, the test below becomes a vector compare)
+  uint32_t cx = cj.x, cy = cj.y;
+  asm("" : "+s"(cx), "+s"(cy));
+  const uint32_t ka_m = ka & (cy != 0u ? ~0u : 0u);
+  const uint32_t y = disjoint ? kn : ka_m;
+  bool act = y != 0u;
   if (kDiag) act = act && (j < kp);
   if (act) {
-    const uint32_t t = uint32_t(__popc(mj & k.m));
-    const uint32_t r5 = uint32_t(__popc(rj.z & khl) + __popc(rj.w & khh));
-    const uint32_t code = pair_code(a, __popc(mj), rj.y & 0xffu, k, t, r5);
+    const uint32_t x = kNarrow ? (disjoint ? cx : cy) & 0xffffffu : (disjoint ? cx : cy);
+    const uint64_t w = uint64_t(x) * y;
+    const uint32_t t = uint32_t(__popc(xm));
+    const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
+    const uint32_t code = pair_code_aks(aks, __popc(mj), rj.y & 0xffu, k, t, r5);
     atomicAdd(&hist[lut[code]], w);
   }
 }
 
-template <bool kDiag>
+template <bool kDiag, bool kNarrow>
 __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
-                                      int j0, int j1, uint32_t a, const Side& k, uint32_t kn,
-                                      uint32_t ka, int kp, bool valid,
-                                      const uint16_t* __restrict__ lut, unsigned long long* hist) {
+                                      int j0, int j1, uint32_t aks, const Side& k, uint32_t kn,
+                                      uint32_t ka, int kp, const uint16_t* __restrict__ lut,
+                                      unsigned long long* hist) {
   const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
   int j = j0;
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag>(r0, c0, j, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
-    gpair_step<kDiag>(r1, c1, j + 1, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
-    gpair_step<kDiag>(r2, c2, j + 2, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
-    gpair_step<kDiag>(r3, c3, j + 3, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+    gpair_step<kDiag, kNarrow>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
   }
-  for (; j < j1; ++j) gpair_step<kDiag>(grow[j], gc[j], j, a, k, khl, khh, kn, ka, kp, valid, lut, hist);
+  for (; j < j1; ++j)
+    gpair_step<kDiag, kNarrow>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+}
+
+// A pair in which one group has no member above the centre counts only when
+// open at the centre (disjoint), with weight nall_j * nall_k and t = r5 = 0:
+// its code is k0 (the lane's digits R6, R3) + j's digits R4, R2 + st3(|e_i|
+// - k.s - pj) (R1), so j enters only through its open class (pj, st3(oj)).
+// The groups are ordered by open class within each hash part, so each lane
+// sums nall_j over a run of one class and adds sum * nall_k to the
+// histogram when the class changes.
+__device__ __forceinline__ void open_flush(uint32_t cls, uint32_t acc, uint32_t aks, uint32_t k0,
+                                           uint32_t kn, const uint16_t* __restrict__ lut,
+                                           unsigned long long* hist) {
+  if (acc != 0u) {
+    const uint32_t pj = cls / 3u, oc = cls - 3u * pj;
+    const uint32_t code = k0 + 27u * st3(pj) + 3u * oc + st3(aks - pj);
+    atomicAdd(&hist[lut[code]], uint64_t(acc) * kn);
+  }
+}
+
+template <bool kDiag>
+__device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int j, const Side& k,
+                                          uint32_t khl, uint32_t khh, uint32_t kn, int kp,
+                                          uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& acc,
+                                          const uint16_t* __restrict__ lut,
+                                          unsigned long long* hist) {
+  const uint32_t cls = open_class(rj.x, rj.y & 0xffu);  // uniform
+  if (cls != cur) {
+    open_flush(cur, acc, aks, k0, kn, lut, hist);
+    cur = cls;
+    acc = 0u;
+  }
+  bool act = ((rj.x & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u && kn != 0u;
+  if (kDiag) act = act && (j < kp);
+  if (act) acc += cj.x;
+}
+
+template <bool kDiag>
+__device__ __forceinline__ void owalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
+                                      int j0, int j1, uint32_t aks, uint32_t k0, const Side& k,
+                                      uint32_t kn, int kp, const uint16_t* __restrict__ lut,
+                                      unsigned long long* hist) {
+  const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
+  uint32_t cur = 0u, acc = 0u;
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
+    const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
+    open_step<kDiag>(r0, c0, j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r1, c1, j + 1, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r2, c2, j + 2, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r3, c3, j + 3, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+  }
+  for (; j < j1; ++j) open_step<kDiag>(grow[j], gc[j], j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+  open_flush(cur, acc, aks, k0, kn, lut, hist);
 }
 
 __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane, int64_t g,
@@ -498,10 +622,11 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
   __builtin_amdgcn_wave_barrier();
 }
 
+template <bool kNarrow>
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
-    const uint4* __restrict__ grec, const uint2* __restrict__ gcnt,
+    const uint4* __restrict__ grec, const uint2* __restrict__ gcnt, const int32_t* __restrict__ gna,
     const int32_t* __restrict__ order, const int64_t* __restrict__ rstart, int64_t nslots,
     const int32_t* __restrict__ row_graph, unsigned long long* queue,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
@@ -535,16 +660,23 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
     const int b = nbi - 1 - int(q - rstart[lo]);
     const int64_t gb = gbase[i] - cap0;
     const int ng = int(goff[i + 1] - goff[i]);
+    // groups with members above the centre at [0, na), the others at
+    // [na, ng) + gap (gap = the row region's unused middle)
+    const int na = gna[i];
+    const int64_t gap = (gbase[i + 1] - gbase[i]) - ng;
     const uint32_t a = uint32_t(edge_ptr[i + 1] - edge_ptr[i]);
     const uint4* __restrict__ grow = grec + gb;
     const uint2* __restrict__ gc = gcnt + gb;
+    const uint4* __restrict__ growb = grow + gap;
+    const uint2* __restrict__ gcb = gc + gap;
     const int kp = b * kWave + lane;
     const bool valid = kp < ng;
     Side k;
     uint32_t kn = 0, ka = 0;
     {
-      const uint4 rk = valid ? grow[kp] : make_uint4(0, 0, 0, 0);
-      const uint2 ck = valid ? gc[kp] : make_uint2(0, 0);
+      const int64_t kpos = kp < na ? int64_t(kp) : kp + gap;
+      const uint4 rk = valid ? grow[kpos] : make_uint4(0, 0, 0, 0);
+      const uint2 ck = valid ? gc[kpos] : make_uint2(0, 0);
       k.m = rk.x;
       k.o = rk.y & 0xffu;
       k.s = __popc(rk.x);
@@ -552,10 +684,24 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       kn = ck.x;
       ka = ck.y;
     }
+    if (kNarrow) {
+      kn &= 0xffffffu;
+      ka &= 0xffffffu;
+    }
     const int blo = b * kWave;
     const int kmax = min(blo + kWave, ng);
-    gwalk<false>(grow, gc, 0, blo, a, k, kn, ka, kp, valid, lut, myhist);
-    gwalk<true>(grow, gc, blo, kmax, a, k, kn, ka, kp, valid, lut, myhist);
+    const uint32_t aks = a - k.s;
+    const uint32_t k0 = 243u * st3(k.s) + 9u * st3(k.o);
+    if (blo >= na) {  // no lane has members above the centre: open pairs only
+      owalk<false>(grow, gc, 0, na, aks, k0, k, kn, kp, lut, myhist);
+      owalk<false>(growb, gcb, na, blo, aks, k0, k, kn, kp, lut, myhist);
+      owalk<true>(growb, gcb, blo, kmax, aks, k0, k, kn, kp, lut, myhist);
+    } else {  // j with members above the centre: every pair; the others: open only
+      const int ka1 = min(kmax, na);
+      gwalk<false, kNarrow>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, kNarrow>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
+      owalk<true>(growb, gcb, ka1, kmax, aks, k0, k, kn, kp, lut, myhist);
+    }
     if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
       const uint32_t r5 = uint32_t(__popcll(k.h));
       const uint32_t code = pair_code(a, k.s, k.o, k, k.s, r5);
@@ -621,7 +767,9 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 }
 
 // Groups of rows [c0, c1): goff[E+1] the prefix of the rows' group counts,
-// row i's groups at grec / gcnt [gbase[i] - cap0, ...).  For a single graph
+// row i's groups in grec / gcnt [gbase[i] - cap0, gbase[i + 1] - cap0): the
+// gna[i] with members above the centre first, the others at the region's
+// end (the region holds exactly the groups in the compact layout).  For a single graph
 // with up to ctx->group_cap_bytes of row capacity, one pass writes each row's
 // groups at its line-graph offset (gbase = lg_ptr); otherwise (batches,
 // larger graphs) the groups are counted first and allocated exactly
@@ -629,8 +777,8 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 // the group arrays do not fit or a row could not be grouped; the caller then
 // pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
-                          int64_t** goff, uint4** grec, uint2** gcnt, const int64_t** gbase,
-                          int64_t* cap0) {
+                          int64_t** goff, uint4** grec, uint2** gcnt, int32_t** gna,
+                          const int64_t** gbase, int64_t* cap0) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E;
   int64_t* cntarr = nullptr;
@@ -638,15 +786,18 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   *goff = nullptr;
   *grec = nullptr;
   *gcnt = nullptr;
+  *gna = nullptr;
   auto fail = [&](mochy_status rc) {
     device_free(ctx, cntarr);
     device_free(ctx, tmp);
     device_free(ctx, *goff);
     device_free(ctx, *grec);
     device_free(ctx, *gcnt);
+    device_free(ctx, *gna);
     *goff = nullptr;
     *grec = nullptr;
     *gcnt = nullptr;
+    *gna = nullptr;
     return rc;
   };
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + c0, 8, hipMemcpyDeviceToHost, st));
@@ -660,7 +811,8 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK)
+      (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)gna, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK)
     return fail(rc);
   MOCHY_HIP(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st));
@@ -673,7 +825,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0)
       k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                 cntarr, g->lg_ptr, row0, *grec, *gcnt,
-                                                                ctx->d_flags + 3);
+                                                                *gna, ctx->d_flags + 3);
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
   } else {
     *gbase = *goff;
@@ -681,7 +833,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0)
       k_group<false><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                  cntarr, nullptr, 0, nullptr, nullptr,
-                                                                 ctx->d_flags + 3);
+                                                                 nullptr, ctx->d_flags + 3);
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
     MOCHY_HIP(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st));
     MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
@@ -694,7 +846,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0)
       k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                 nullptr, *goff, 0, *grec, *gcnt,
-                                                                ctx->d_flags + 3);
+                                                                *gna, ctx->d_flags + 3);
   }
   MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
@@ -719,11 +871,12 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   int64_t cap0 = 0;
   uint4* grec = nullptr;
   uint2* gcnt = nullptr;
+  int32_t* gna = nullptr;
   mochy_status rc;
   phase_begin(ctx, kPhSched);
   bool grouped = ctx->group_neighbours;
   if (grouped) {
-    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gbase, &cap0);
+    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0);
     if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
       grouped = false;
       ctx->err.clear();
@@ -738,15 +891,15 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     device_free(ctx, goff);
     device_free(ctx, grec);
     device_free(ctx, gcnt);
+    device_free(ctx, gna);
   };
   if (rc != MOCHY_OK) { release(); return rc; }
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
   if (grouped)
-    k_exact_grouped<<<grid, 256, 0, st>>>(g->edge_ptr, goff, gbase, cap0, grec, gcnt, S.order,
-                                          S.rstart, S.rows,
-                                          g->row_graph, S.queue, ctx->d_code_to_id3,
-                                          (unsigned long long*)d_hist);
+    (g->max_deg < (1 << 24) ? k_exact_grouped<true> : k_exact_grouped<false>)<<<grid, 256, 0, st>>>(
+        g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, g->row_graph, S.queue,
+        ctx->d_code_to_id3, (unsigned long long*)d_hist);
   else
     k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, S.order, S.rstart,
                                        S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
