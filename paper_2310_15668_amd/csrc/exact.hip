@@ -905,13 +905,14 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
                                        S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
                                        (unsigned long long*)d_hist);
   phase_end(ctx, kPhPairs);
+  MOCHY_HIP(hipGetLastError());
+  release();  // stream-ordered; the correction reads rows and records only
   phase_begin(ctx, kPhCorrect);
   rc = correct_device(ctx, g, c0, c1, d_hist);
-  if (rc != MOCHY_OK) { release(); return rc; }
+  if (rc != MOCHY_OK) return rc;
   phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
   phases_collect(ctx);
-  release();
   return MOCHY_OK;
 }
