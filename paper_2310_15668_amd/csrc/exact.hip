@@ -622,7 +622,13 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
   __builtin_amdgcn_wave_barrier();
 }
 
-template <bool kNarrow>
+// kShared (a single graph): the block's 8 histogram copies are shared by its
+// waves, lane l adding to copy l % 8 (8 lanes per copy instead of 32: fewer
+// same-word adds in one instruction), flushed once at the end; otherwise each
+// wave has 2 copies of its own, flushed whenever its rows change graph.  (16
+// shared copies in 512-thread blocks are no faster: the 60 KB of LDS halves
+// the resident waves.)
+template <bool kNarrow, bool kShared>
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
@@ -631,14 +637,16 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
     const int32_t* __restrict__ row_graph, unsigned long long* queue,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   __shared__ uint16_t lut[kNumCodes];
-  __shared__ unsigned long long hist[kWavesPerGroup * kGCopies * kGStride];
+  constexpr int kAll = kWavesPerGroup * kGCopies;
+  __shared__ unsigned long long hist[kAll * kGStride];
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
-  for (int t = threadIdx.x; t < kWavesPerGroup * kGCopies * kGStride; t += blockDim.x) hist[t] = 0ull;
+  for (int t = threadIdx.x; t < kAll * kGStride; t += blockDim.x) hist[t] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   unsigned long long* whist = hist + wave * (kGCopies * kGStride);
-  unsigned long long* myhist = whist + (lane & (kGCopies - 1)) * kGStride;
+  unsigned long long* myhist = kShared ? hist + (lane & (kAll - 1)) * kGStride
+                                       : whist + (lane & (kGCopies - 1)) * kGStride;
   const int64_t total = rstart[nslots];
   int dirty_g = -1;
   for (;;) {
@@ -653,8 +661,8 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       if (rstart[mid] <= q) lo = mid; else hi = mid;
     }
     const int32_t i = order[lo];
-    const int g = row_graph[i];
-    if (dirty_g >= 0 && dirty_g != g) gflush_wave(whist, lane, dirty_g, hist_out);
+    const int g = kShared ? 0 : row_graph[i];
+    if (!kShared && dirty_g >= 0 && dirty_g != g) gflush_wave(whist, lane, dirty_g, hist_out);
     dirty_g = g;
     const int nbi = int(rstart[lo + 1] - rstart[lo]);
     const int b = nbi - 1 - int(q - rstart[lo]);
@@ -708,7 +716,16 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       atomicAdd(&myhist[lut[code]], uint64_t(ka) * (ka - 1u) / 2u);
     }
   }
-  if (dirty_g >= 0) gflush_wave(whist, lane, dirty_g, hist_out);
+  if (kShared) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) {
+      unsigned long long v = 0;
+      for (int c = 0; c < kAll; ++c) v += hist[c * kGStride + t];
+      if (v) atomicAdd(&hist_out[t], v);
+    }
+  } else if (dirty_g >= 0) {
+    gflush_wave(whist, lane, dirty_g, hist_out);
+  }
 }
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -897,7 +914,9 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
   if (grouped)
-    (g->max_deg < (1 << 24) ? k_exact_grouped<true> : k_exact_grouped<false>)<<<grid, 256, 0, st>>>(
+    (g->max_deg < (1 << 24) ? (g->ng == 1 ? k_exact_grouped<true, true> : k_exact_grouped<true, false>)
+                            : (g->ng == 1 ? k_exact_grouped<false, true> : k_exact_grouped<false, false>))
+        <<<grid, 256, 0, st>>>(
         g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, g->row_graph, S.queue,
         ctx->d_code_to_id3, (unsigned long long*)d_hist);
   else
