@@ -342,6 +342,8 @@ __device__ __forceinline__ uint64_t sig_hash(const uint4& r, uint32_t o, uint64_
 }
 
 constexpr int kGroupTries = 40;  // restarts before a row gives up (flags bit 0)
+constexpr int kPartRecords = 2 * kGroupSlots;        // records per hash part, first guess
+constexpr int kPartGroups = kGroupSlots * 3 / 4;     // groups per part before the parts double
 
 // Open class of a group: (|its overlap with e_i|, min(outside, 2)); the code
 // of an open pair depends on j only through it.  Below kOpenClasses.
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
     int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags) {
   __shared__ unsigned long long key[kGroupSlots];
   __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
-  __shared__ uint32_t s_out, s_outb, s_bad;
+  __shared__ uint32_t s_out, s_outb, s_bad, s_cnt;
   __shared__ uint32_t cfill[2 * kOpenClasses];  // per (above, open class): count, then next slot
   const int tid = threadIdx.x;
   const int64_t i = c0 + blockIdx.x;
@@ -373,7 +375,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
   const int64_t d = lg_ptr[i + 1] - base;
   const int64_t u = up_first[i];
   const uint4* row = rec + base;
-  int64_t parts = (d + kGroupSlots / 2 - 1) / (kGroupSlots / 2);
+  // hash parts of the row, each grouped in the LDS table: a first guess of
+  // kPartRecords records per part, doubled whenever a part has more than
+  // kPartGroups groups (rows have 0.38 groups per record on medium)
+  int64_t parts = (d + kPartRecords - 1) / kPartRecords;
   if (parts < 1) parts = 1;
   uint64_t seed = 0;
   const int64_t obase = kWrite ? obase_of[i] - cap0 : 0;
@@ -398,9 +403,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         nall[t] = 0u;
         nabove[t] = 0u;
       }
-      if (tid == 0) s_bad = 0u;
+      if (tid == 0) {
+        s_bad = 0u;
+        s_cnt = 0u;
+      }
       __syncthreads();
       for (int64_t r = tid; r < d; r += kGroupThreads) {
+        if (*(volatile uint32_t*)&s_bad) break;  // this part overflowed: the row is redone
         const uint4 rr = row[r];
         const uint64_t kk = sig_hash(rr, clamp_outside(rr), seed);
         if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
@@ -408,7 +417,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         int n = 0;
         for (; n < kGroupSlots; ++n) {
           const unsigned long long old = atomicCAS(&key[slot], 0ull, kk);
-          if (old == 0ull) { first[slot] = uint32_t(r); break; }
+          if (old == 0ull) {
+            first[slot] = uint32_t(r);
+            if (atomicAdd(&s_cnt, 1u) >= uint32_t(kPartGroups)) atomicOr(&s_bad, 4u);
+            break;
+          }
           if (old == kk) break;
           slot = (slot + 1) & (kGroupSlots - 1);
         }
@@ -419,7 +432,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
       __syncthreads();
       const uint32_t full = s_bad;
       __syncthreads();  // every thread has read the flag before it is written again
-      if (full) {  // table full: twice the parts
+      if (full) {  // too many groups in the part: twice the parts
         parts *= 2;
         redo = true;
         break;
