@@ -87,7 +87,11 @@ __global__ __launch_bounds__(256) void k_light_pairs(
   }
 }
 
-__global__ __launch_bounds__(256) void k_light_fix(
+// One block per owner; 512 threads, so that the LDS the row bitmap takes
+// still leaves room for 24 resident waves per CU (the scan waits on loads).
+constexpr int kFixThreads = 512;
+
+__global__ __launch_bounds__(kFixThreads) void k_light_fix(
     int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
     const int32_t* __restrict__ owners,
     const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_light_fix(
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
   __shared__ unsigned long long hist[kHistSlots];
-  __shared__ int32_t part[256];
+  __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
   const int32_t j = owners[blockIdx.x];
   const int gj = row_graph[j];
@@ -125,13 +129,13 @@ __global__ __launch_bounds__(256) void k_light_fix(
   }
   __syncthreads();
   {
-    const int chunk = (nwE + 255) / 256;
+    const int chunk = (nwE + kFixThreads - 1) / kFixThreads;
     const int w0 = min(nwE, int(threadIdx.x) * chunk), w1 = min(nwE, w0 + chunk);
     int32_t c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bm[w]);
     part[threadIdx.x] = c;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
+    for (int off = 1; off < kFixThreads; off <<= 1) {
       const int32_t add = threadIdx.x >= unsigned(off) ? part[threadIdx.x - off] : 0;
       __syncthreads();
       part[threadIdx.x] += add;
@@ -290,7 +294,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);
-  k_light_fix<<<unsigned(nowners), 256, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners, g->edge_ptr,
+  k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners, g->edge_ptr,
                                                    g->edge_nodes, g->heavy_bit, g->lg_ptr, g->lg_col,
                                                    g->recm, ctx->d_code_to_id3,
                                                    (unsigned long long*)d_hist);
