@@ -239,3 +239,29 @@ def test_grouped_equals_every_pair(ctx):
     with pytest.raises(M.MochyError) as e:
         ctx.set_option(M.MOCHY_OPT_GROUPS, 2)
     assert e.value.status == -1
+
+
+def test_grouping_parts_double(ctx):
+    # a centre of 25 nodes whose 2300 neighbours (every 3-subset of its nodes)
+    # all have distinct signatures: its row's single hash part passes the
+    # per-part group limit, so the row is regrouped with twice the parts, in
+    # the one-pass layout and in the counted-first one
+    import itertools
+    import paper_2310_15668_amd as M
+    h = from_edge_lists([list(range(25))] + [list(c) for c in itertools.combinations(range(25), 3)], 25)
+    print(f"[gpu] distinct-signature hub row |E|={h.num_edges}", flush=True)
+    o26, o431, inv = native.mochy_e(h, nthreads=16)
+    assert inv == 0
+    g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+    try:
+        a26, a431 = M.mochy_count_exact(ctx, g)
+        ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 0)
+        b26, b431 = M.mochy_count_exact(ctx, g)
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 0)
+        c26, c431 = M.mochy_count_exact(ctx, g)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+        ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
+        g.close()
+    for x26, x431 in ((a26, a431), (b26, b431), (c26, c431)):
+        assert (x431 == o431).all() and (x26 == o26).all()
