@@ -118,6 +118,7 @@ __global__ __launch_bounds__(256) void k_aplus(
 // adjacent pair, its disjoint class is taken back and its exact class
 // added; a hit outside N_i is a path.
 constexpr int kHsThreads = 256;
+constexpr int kHsUnroll = 8;  // row entries per thread in flight at once
 constexpr int kBins = (MOCHY_MAX_EDGE + 1) * (MOCHY_MAX_EDGE + 1);
 
 __device__ __forceinline__ uint32_t bin_of(uint32_t size, uint32_t omega) {
@@ -289,31 +290,63 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       }
       __syncthreads();
       const int64_t total = c_pre[nj];
-      for (int64_t q = tid; q < total; q += kHsThreads) {
-        int lo = 0, hi = nj;  // last x with c_pre[x] <= q
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (c_pre[mid] <= q) lo = mid; else hi = mid;
+      // kHsUnroll entries per thread at a time; the loads of each stage are
+      // issued together with no branch between them (an entry past the end,
+      // or one that needs no record of row i, reads a valid dummy slot): the
+      // scan waits on loads, not on arithmetic
+      for (int64_t q0 = tid; q0 < total; q0 += kHsUnroll * kHsThreads) {
+        int lo[kHsUnroll];
+        int64_t pos[kHsUnroll];
+#pragma unroll
+        for (int u = 0; u < kHsUnroll; ++u) {
+          const int64_t q = q0 + u * kHsThreads;
+          int l = 0, h = nj;  // last x with c_pre[x] <= q
+          while (h - l > 1) {
+            const int mid = (l + h) >> 1;
+            if (c_pre[mid] <= q) l = mid; else h = mid;
+          }
+          lo[u] = l;
+          pos[u] = q < total ? c_base[l] + (q - c_pre[l]) : c_base[0];  // row j holds e_i: never empty
         }
-        const int32_t j = c_j[lo];
-        const int64_t pos = c_base[lo] + (q - c_pre[lo]);
-        const int32_t k = lg_col[pos];
-        if (k == int32_t(i)) continue;
-        const uint4 rjk = rec[pos];
-        const uint32_t mji = c_mji[lo], b = c_b[lo];
-        const uint32_t p = __popc(mji);
-        const uint32_t wjk = __popc(rjk.x);
-        const uint32_t c = wjk + (rjk.y & 0xffu);
-        const int64_t kl = int64_t(k) - e0;
-        const uint32_t kw = bm[kl >> 5], kbit = 1u << (kl & 31);
-        if (kw & kbit) {
-          if (!(j < k)) continue;  // an adjacent pair of N_i, once
-          const uint32_t wik = __popc(rec[ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u)))].x);
-          const uint32_t t = __popc(mji & rjk.x);
-          atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
-          atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
-        } else {
-          atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, 0u, 0u)]], 1ull);  // a path
+        int32_t kv[kHsUnroll];
+        uint4 rv[kHsUnroll];
+#pragma unroll
+        for (int u = 0; u < kHsUnroll; ++u) {
+          kv[u] = lg_col[pos[u]];
+          rv[u] = rec[pos[u]];
+        }
+        int64_t ipos[kHsUnroll];
+        uint32_t kin[kHsUnroll];
+#pragma unroll
+        for (int u = 0; u < kHsUnroll; ++u) {
+          const int64_t kl = int64_t(kv[u]) - e0;
+          const uint32_t kw = bm[kl >> 5], kbit = 1u << (kl & 31);
+          kin[u] = kw & kbit;  // e_k is a neighbour of e_i (never e_i itself)
+          ipos[u] = kin[u] ? ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u))) : ib;
+        }
+        uint32_t wiv[kHsUnroll];
+#pragma unroll
+        for (int u = 0; u < kHsUnroll; ++u) wiv[u] = rec[ipos[u]].x;
+#pragma unroll
+        for (int u = 0; u < kHsUnroll; ++u) {
+          if (q0 + u * kHsThreads >= total) continue;
+          const int32_t k = kv[u];
+          if (k == int32_t(i)) continue;
+          const int32_t j = c_j[lo[u]];
+          const uint4 rjk = rv[u];
+          const uint32_t mji = c_mji[lo[u]], b = c_b[lo[u]];
+          const uint32_t p = __popc(mji);
+          const uint32_t wjk = __popc(rjk.x);
+          const uint32_t c = wjk + (rjk.y & 0xffu);
+          if (kin[u]) {
+            if (!(j < k)) continue;  // an adjacent pair of N_i, once
+            const uint32_t wik = __popc(wiv[u]);
+            const uint32_t t = __popc(mji & rjk.x);
+            atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
+            atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
+          } else {
+            atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, 0u, 0u)]], 1ull);  // a path
+          }
         }
       }
       __syncthreads();
