@@ -166,10 +166,6 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
   __shared__ unsigned long long hist[kHistSlots];
   __shared__ uint32_t bins[kBins];
   __shared__ uint32_t blist[kBins];
-  __shared__ int32_t c_j[kHsThreads];
-  __shared__ int64_t c_base[kHsThreads];
-  __shared__ uint32_t c_mji[kHsThreads], c_b[kHsThreads];
-  __shared__ int64_t c_pre[kHsThreads + 1];
   __shared__ int32_t part[kHsThreads];
   __shared__ int64_t s_i, s_chunk;
   __shared__ uint32_t s_nb;
@@ -254,103 +250,70 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, sk, 0u)]], w);
     }
     __syncthreads();
-    // the rows of this item's 256 neighbours of e_i
-    for (int jc = int(chunk) * kHsThreads; jc < di && jc < int(chunk + 1) * kHsThreads; jc += kHsThreads) {
-      const int nj = min(kHsThreads, di - jc);
-      int64_t dj = 0;
-      if (tid < nj) {
-        const int32_t j = lg_col[ib + jc + tid];
+    // the rows of this item's 256 neighbours of e_i, one row per wave at a
+    // time (e_j, its overlap with e_i and its size are uniform); each lane
+    // keeps kHsUnroll entries in flight, the loads of each stage issued
+    // together with no branch between them (an entry past the row's end, or
+    // one that needs no record of row i, reads a valid dummy slot): the scan
+    // waits on loads, not on arithmetic
+    {
+      const int lane = tid & (kWave - 1), wave = tid / kWave;
+      const int x0 = int(chunk) * kHsThreads, nj = min(kHsThreads, di - x0);
+      for (int x = wave; x < nj; x += kHsThreads / kWave) {
+        const int32_t j = lg_col[ib + x0 + x];
         const int64_t jb = lg_ptr[j];
-        dj = lg_ptr[j + 1] - jb;
-        int lo = 0, hi = int(dj);  // e_i's position in row j
+        const int dj = int(lg_ptr[j + 1] - jb);  // >= 1: row j holds e_i
+        int lo = 0, hi = dj;  // e_i's position in row j
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (lg_col[jb + mid] < int32_t(i)) lo = mid + 1; else hi = mid;
         }
-        c_j[tid] = j;
-        c_base[tid] = jb;
-        c_mji[tid] = rec[jb + lo].x;
-        c_b[tid] = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
-      }
-      // prefix of the row lengths
-      part[tid] = 0;
-      __syncthreads();
-      {
-        __shared__ int64_t pre64[kHsThreads];
-        pre64[tid] = dj;
-        __syncthreads();
-        for (int off = 1; off < kHsThreads; off <<= 1) {
-          const int64_t add = tid >= off ? pre64[tid - off] : 0;
-          __syncthreads();
-          pre64[tid] += add;
-          __syncthreads();
-        }
-        c_pre[tid + 1] = pre64[tid];
-        if (tid == 0) c_pre[0] = 0;
-      }
-      __syncthreads();
-      const int64_t total = c_pre[nj];
-      // kHsUnroll entries per thread at a time; the loads of each stage are
-      // issued together with no branch between them (an entry past the end,
-      // or one that needs no record of row i, reads a valid dummy slot): the
-      // scan waits on loads, not on arithmetic
-      for (int64_t q0 = tid; q0 < total; q0 += kHsUnroll * kHsThreads) {
-        int lo[kHsUnroll];
-        int64_t pos[kHsUnroll];
+        const uint32_t mji = rec[jb + lo].x;
+        const uint32_t b = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
+        const uint32_t p = __popc(mji);
+        for (int r0 = lane; r0 < dj; r0 += kHsUnroll * kWave) {
+          int32_t kv[kHsUnroll];
+          uint4 rv[kHsUnroll];
 #pragma unroll
-        for (int u = 0; u < kHsUnroll; ++u) {
-          const int64_t q = q0 + u * kHsThreads;
-          int l = 0, h = nj;  // last x with c_pre[x] <= q
-          while (h - l > 1) {
-            const int mid = (l + h) >> 1;
-            if (c_pre[mid] <= q) l = mid; else h = mid;
+          for (int u = 0; u < kHsUnroll; ++u) {
+            const int r = min(r0 + u * kWave, dj - 1);
+            kv[u] = lg_col[jb + r];
+            rv[u] = rec[jb + r];
           }
-          lo[u] = l;
-          pos[u] = q < total ? c_base[l] + (q - c_pre[l]) : c_base[0];  // row j holds e_i: never empty
-        }
-        int32_t kv[kHsUnroll];
-        uint4 rv[kHsUnroll];
+          int64_t ipos[kHsUnroll];
+          uint32_t kin[kHsUnroll];
 #pragma unroll
-        for (int u = 0; u < kHsUnroll; ++u) {
-          kv[u] = lg_col[pos[u]];
-          rv[u] = rec[pos[u]];
-        }
-        int64_t ipos[kHsUnroll];
-        uint32_t kin[kHsUnroll];
+          for (int u = 0; u < kHsUnroll; ++u) {
+            const int64_t kl = int64_t(kv[u]) - e0;
+            const uint32_t kw = bm[kl >> 5], kbit = 1u << (kl & 31);
+            kin[u] = kw & kbit;  // e_k is a neighbour of e_i (never e_i itself)
+            ipos[u] = kin[u] ? ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u))) : ib;
+          }
+          uint32_t wiv[kHsUnroll];
 #pragma unroll
-        for (int u = 0; u < kHsUnroll; ++u) {
-          const int64_t kl = int64_t(kv[u]) - e0;
-          const uint32_t kw = bm[kl >> 5], kbit = 1u << (kl & 31);
-          kin[u] = kw & kbit;  // e_k is a neighbour of e_i (never e_i itself)
-          ipos[u] = kin[u] ? ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u))) : ib;
-        }
-        uint32_t wiv[kHsUnroll];
+          for (int u = 0; u < kHsUnroll; ++u) wiv[u] = rec[ipos[u]].x;
 #pragma unroll
-        for (int u = 0; u < kHsUnroll; ++u) wiv[u] = rec[ipos[u]].x;
-#pragma unroll
-        for (int u = 0; u < kHsUnroll; ++u) {
-          if (q0 + u * kHsThreads >= total) continue;
-          const int32_t k = kv[u];
-          if (k == int32_t(i)) continue;
-          const int32_t j = c_j[lo[u]];
-          const uint4 rjk = rv[u];
-          const uint32_t mji = c_mji[lo[u]], b = c_b[lo[u]];
-          const uint32_t p = __popc(mji);
-          const uint32_t wjk = __popc(rjk.x);
-          const uint32_t c = wjk + (rjk.y & 0xffu);
-          if (kin[u]) {
-            if (!(j < k)) continue;  // an adjacent pair of N_i, once
-            const uint32_t wik = __popc(wiv[u]);
-            const uint32_t t = __popc(mji & rjk.x);
-            atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
-            atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
-          } else {
-            atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, 0u, 0u)]], 1ull);  // a path
+          for (int u = 0; u < kHsUnroll; ++u) {
+            if (r0 + u * kWave >= dj) continue;
+            const int32_t k = kv[u];
+            if (k == int32_t(i)) continue;
+            const uint4 rjk = rv[u];
+            const uint32_t wjk = __popc(rjk.x);
+            const uint32_t c = wjk + (rjk.y & 0xffu);
+            if (kin[u]) {
+              if (!(j < k)) continue;  // an adjacent pair of N_i, once
+              const uint32_t wik = __popc(wiv[u]);
+              const uint32_t t = __popc(mji & rjk.x);
+              atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
+              atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
+            } else {
+              atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, 0u, 0u)]], 1ull);  // a path
+            }
           }
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     for (uint32_t q = tid; q < nb; q += kHsThreads) bins[blist[q]] = 0u;
     if (kProfile) {  // this item's part of the hyperedge's profile
       __syncthreads();
