@@ -151,7 +151,10 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
   const uint32_t H = hmask;
   const uint32_t sizej = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
   const uint32_t L = (sizej >= 32u ? 0xffffffffu : ((1u << sizej) - 1u)) & ~H;
-  for (int64_t pp = poff[blockIdx.x]; pp < poff[blockIdx.x + 1]; ++pp) {
+  // one partner per wave at a time (rows shorter than a block's sweep leave
+  // no lanes idle)
+  const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
+  for (int64_t pp = poff[blockIdx.x] + wave; pp < poff[blockIdx.x + 1]; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
     // record of e_k in row j
     const int64_t kl = k - e0;
@@ -166,8 +169,8 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
     // is not a centre reads a valid dummy slot), since the work is bound by
     // load latency: 3 of 4 scanned entries are centres on hub-heavy graphs
     constexpr int kUnroll = 8;
-    const int step = int(blockDim.x);
-    for (int r0 = threadIdx.x; r0 < dk; r0 += kUnroll * step) {
+    constexpr int step = kWave;
+    for (int r0 = lane; r0 < dk; r0 += kUnroll * step) {
       int32_t iv[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
