@@ -635,12 +635,13 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
   __builtin_amdgcn_wave_barrier();
 }
 
-// kShared (a single graph): the block's 8 histogram copies are shared by its
-// waves, lane l adding to copy l % 8 (8 lanes per copy instead of 32: fewer
-// same-word adds in one instruction), flushed once at the end; otherwise each
-// wave has 2 copies of its own, flushed whenever its rows change graph.  (16
-// shared copies in 512-thread blocks are no faster: the 60 KB of LDS halves
-// the resident waves.)
+// kShared (a single graph): the block's 4 histogram copies are shared by its
+// waves, lane l adding to copy l % 4, flushed once at the end: 18 KB of LDS
+// per block, so 8 blocks (32 waves) fit on a CU; 8 shared copies (fewer
+// same-word adds, but 5 blocks per CU) were 27 % slower, 16 copies in
+// 512-thread blocks slower still.  Otherwise each wave has 2 copies of its
+// own, flushed whenever its rows change graph.
+constexpr int kGSharedCopies = 4;
 template <bool kNarrow, bool kShared>
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
@@ -650,14 +651,14 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
     const int32_t* __restrict__ row_graph, unsigned long long* queue,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   __shared__ uint16_t lut[kNumCodes];
-  constexpr int kAll = kWavesPerGroup * kGCopies;
+  constexpr int kAll = kShared ? kGSharedCopies : kWavesPerGroup * kGCopies;
   __shared__ unsigned long long hist[kAll * kGStride];
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
   for (int t = threadIdx.x; t < kAll * kGStride; t += blockDim.x) hist[t] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  unsigned long long* whist = hist + wave * (kGCopies * kGStride);
+  unsigned long long* whist = kShared ? hist : hist + wave * (kGCopies * kGStride);  // per-wave copies only
   unsigned long long* myhist = kShared ? hist + (lane & (kAll - 1)) * kGStride
                                        : whist + (lane & (kGCopies - 1)) * kGStride;
   const int64_t total = rstart[nslots];
