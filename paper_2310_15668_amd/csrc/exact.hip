@@ -28,6 +28,8 @@
 // persistent waves.  Counts go to a per-workgroup LDS histogram (several
 // copies, picked by lane, to thin same-bin conflicts), flushed once per
 // workgroup with 64-bit global atomics.
+#include <vector>
+
 #include "classify.h"
 #include "common.h"
 
@@ -642,13 +644,16 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
 // 512-thread blocks slower still.  Otherwise each wave has 2 copies of its
 // own, flushed whenever its rows change graph.
 constexpr int kGSharedCopies = 4;
+// batches of up to this many graphs count each graph with its own launch of
+// the shared-histogram kernel; larger ones use per-wave histograms in one launch
+constexpr int kPerGraphLaunches = 256;
 template <bool kNarrow, bool kShared>
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
     const uint4* __restrict__ grec, const uint2* __restrict__ gcnt, const int32_t* __restrict__ gna,
     const int32_t* __restrict__ order, const int64_t* __restrict__ rstart, int64_t nslots,
-    const int32_t* __restrict__ row_graph, unsigned long long* queue,
+    int64_t item0, int64_t item1, const int32_t* __restrict__ row_graph, unsigned long long* queue,
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   __shared__ uint16_t lut[kNumCodes];
   constexpr int kAll = kShared ? kGSharedCopies : kWavesPerGroup * kGCopies;
@@ -661,13 +666,13 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
   unsigned long long* whist = kShared ? hist : hist + wave * (kGCopies * kGStride);  // per-wave copies only
   unsigned long long* myhist = kShared ? hist + (lane & (kAll - 1)) * kGStride
                                        : whist + (lane & (kGCopies - 1)) * kGStride;
-  const int64_t total = rstart[nslots];
+  const int64_t total = item1 >= 0 ? item1 : rstart[nslots];  // items [item0, total)
   int dirty_g = -1;
   for (;;) {
     unsigned long long qq = 0;
     if (lane == 0) qq = atomicAdd(queue, 1ull);
-    const int64_t q = (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(int(qq >> 32)) << 32) |
-                                (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(int(qq)));
+    const int64_t q = item0 + (int64_t)(((unsigned long long)__builtin_amdgcn_readfirstlane(int(qq >> 32)) << 32) |
+                                        (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(int(qq)));
     if (q >= total) break;
     int64_t lo = 0, hi = nslots;
     while (hi - lo > 1) {
@@ -755,6 +760,7 @@ struct Schedule {
   int32_t* order = nullptr;
   int64_t* rstart = nullptr;
   unsigned long long* queue = nullptr;
+  int64_t* gq = nullptr;  // [ng + 1] first item of each graph
   int64_t rows = 0;
 };
 
@@ -777,6 +783,7 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   unsigned long long* fill = (unsigned long long*)(item_start + ng * NB);
   int64_t* total = (int64_t*)(fill + ng * NB);
   int64_t* gq = total + ng;
+  S.gq = gq;
   int64_t* seg = gq + (ng + 1);
   S.queue = (unsigned long long*)(seg + ng);
   int64_t* nbk = (int64_t*)(S.queue + 1);
@@ -927,13 +934,30 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if (rc != MOCHY_OK) { release(); return rc; }
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
-  if (grouped)
-    (g->max_deg < (1 << 24) ? (g->ng == 1 ? k_exact_grouped<true, true> : k_exact_grouped<true, false>)
-                            : (g->ng == 1 ? k_exact_grouped<false, true> : k_exact_grouped<false, false>))
+  const bool narrow = g->max_deg < (1 << 24);
+  if (grouped && ng > 1 && ng <= kPerGraphLaunches) {
+    // a batch: the shared-histogram kernel once per graph (a graph's items
+    // are contiguous in the schedule), each launch with its own queue counter
+    std::vector<int64_t> hgq(size_t(ng) + 1);
+    MOCHY_HIP(hipMemcpyAsync(hgq.data(), S.gq, hgq.size() * 8, hipMemcpyDeviceToHost, st));
+    MOCHY_HIP(hipStreamSynchronize(st));
+    unsigned long long* gqueue = nullptr;
+    if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) { release(); return rc; }
+    MOCHY_HIP(hipMemsetAsync(gqueue, 0, size_t(ng) * 8, st));
+    for (int gi = 0; gi < ng; ++gi) {
+      if (hgq[gi + 1] <= hgq[gi]) continue;
+      (narrow ? k_exact_grouped<true, true> : k_exact_grouped<false, true>)<<<grid, 256, 0, st>>>(
+          g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, hgq[gi], hgq[gi + 1],
+          g->row_graph, gqueue + gi, ctx->d_code_to_id3, (unsigned long long*)d_hist + size_t(gi) * kHistSlots);
+    }
+    device_free(ctx, gqueue);
+  } else if (grouped) {
+    (narrow ? (ng == 1 ? k_exact_grouped<true, true> : k_exact_grouped<true, false>)
+            : (ng == 1 ? k_exact_grouped<false, true> : k_exact_grouped<false, false>))
         <<<grid, 256, 0, st>>>(
-        g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, g->row_graph, S.queue,
-        ctx->d_code_to_id3, (unsigned long long*)d_hist);
-  else
+        g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
+        S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
+  } else
     k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, S.order, S.rstart,
                                        S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
                                        (unsigned long long*)d_hist);
