@@ -69,6 +69,19 @@ def test_batched_equals_sequential(ctx):
     assert len(sizes) > 1  # uneven sizes after collapsing repeated members
 
 
+def test_batch_above_per_graph_launch_limit(ctx):
+    # more than 256 graphs: the pair kernel counts the whole batch in one
+    # launch with per-wave histograms flushed at every change of graph
+    base = powerlaw_hypergraph(120, 300, 2, 8, 2.5, 1.0, seed=5)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(200, 499)]
+    counts, *_ = run_profile(ctx, graphs)
+    assert counts.shape[0] == 300
+    assert (counts == sequential(ctx, graphs)).all()
+    for k in (0, 1, 150, 299):
+        r26, r431, _ = native.mochy_e(graphs[k], nthreads=8)
+        assert (counts[k, :26] == r26).all() and (counts[k, 26:] == r431).all(), k
+
+
 def test_uneven_and_degenerate_members(ctx):
     graphs = [make_config("tiny"), from_edge_lists([[0, 1], [2, 3]], 4),
               from_edge_lists([[0, 1], [1, 2], [2, 0]], 3), make_config("tiny", scale=0.5)]
