@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_light_pairs(
 // One block per owner; 512 threads, so that the LDS the row bitmap takes
 // still leaves room for 24 resident waves per CU (the scan waits on loads).
 constexpr int kFixThreads = 512;
+constexpr int kFixCopies = 4;
 
 __global__ __launch_bounds__(kFixThreads) void k_light_fix(
     int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
@@ -101,7 +102,10 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
     const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
-  __shared__ unsigned long long hist[kHistSlots];
+  // kFixCopies histogram copies, lane l adding to copy l % kFixCopies (fewer
+  // same-word adds in one instruction; the LDS they take costs no resident
+  // waves, which the registers limit)
+  __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
   const int32_t j = owners[blockIdx.x];
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
   const int64_t jb = lg_ptr[j];
   const int dj = int(lg_ptr[j + 1] - jb);
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
-  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0;
+  for (int t = threadIdx.x; t < kFixCopies * kHistSlots; t += blockDim.x) hist[t] = 0;
   for (int w = threadIdx.x; w < nwE; w += blockDim.x) bm[w] = 0;
   if (threadIdx.x == 0) {
     uint32_t h = 0;
@@ -154,6 +158,7 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
   // one partner per wave at a time (rows shorter than a block's sweep leave
   // no lanes idle)
   const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
+  unsigned long long* myhist = hist + (lane & (kFixCopies - 1)) * kHistSlots;
   for (int64_t pp = poff[blockIdx.x] + wave; pp < poff[blockIdx.x + 1]; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
     // record of e_k in row j
@@ -215,14 +220,17 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
         K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
         const uint32_t oj = sizej - pj;
         const bool above = (j > i) && (k > i);
-        if (above || (t | r5h) == 0u) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h)]], ~0ull);
-        if (above) atomicAdd(&hist[lut[pair_code(a, pj, oj, K, t, r5h + ls)]], 1ull);
+        if (above || (t | r5h) == 0u) atomicAdd(&myhist[lut[pair_code(a, pj, oj, K, t, r5h)]], ~0ull);
+        if (above) atomicAdd(&myhist[lut[pair_code(a, pj, oj, K, t, r5h + ls)]], 1ull);
       }
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x)
-    if (hist[t]) atomicAdd(&hist_out[int64_t(gj) * kHistSlots + t], hist[t]);
+  for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) {
+    unsigned long long v = 0;
+    for (int c = 0; c < kFixCopies; ++c) v += hist[c * kHistSlots + t];
+    if (v) atomicAdd(&hist_out[int64_t(gj) * kHistSlots + t], v);
+  }
 }
 
 // owners: hyperedges with at least one light partner, compacted.
