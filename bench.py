@@ -56,12 +56,9 @@ def source_digest(paths):
     return d.hexdigest()
 
 
-def measured_traffic(summary=None, source=None):
-    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
-    summary (default: the exact pair kernel's), or None if there is none or
-    the kernel source changed since the counters were taken."""
-    summary = summary or COUNTERS_SUMMARY
-    source = source or PAIR_KERNEL_SRC
+def summary_values(summary, source):
+    """'- key: value' lines of a committed rocprofv3 summary, or None if it is
+    missing or the kernel source changed since its counters were taken."""
     if not os.path.exists(summary):
         return None
     vals = {}
@@ -72,8 +69,34 @@ def measured_traffic(summary=None, source=None):
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != source_digest(source):
         return None
+    return vals
+
+
+# Integer VALU issue peak: a CU has 4 SIMD16 units, each taking 4 cycles per
+# wave64 instruction, so one wave instruction per CU per cycle.
+NUM_CUS, CLOCK_HZ = 256, 2.4e9
+
+
+def valu_issue(kernel_ms):
+    """The pair kernel's VALU wave-instructions per launch (SQ_INSTS_VALU from
+    the committed counter summary) over this run's kernel time, against one
+    per CU per cycle; None if the counters are stale."""
+    vals = summary_values(COUNTERS_SUMMARY, PAIR_KERNEL_SRC)
+    if vals is None or "SQ_INSTS_VALU" not in vals:
+        return None
+    n = float(vals["SQ_INSTS_VALU"])
+    rate = n / (NUM_CUS * CLOCK_HZ * kernel_ms * 1e-3)
+    return {"valu_wave_instructions_per_launch": n, "per_cu_per_cycle": rate, "peak_per_cu_per_cycle": 1.0,
+            "frac": rate, "source": "profiles/k_exact_grouped_medium_counters.md"}
+
+
+def measured_traffic(summary=None, source=None):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary (default: the exact pair kernel's), or None if there is none or
+    the kernel source changed since the counters were taken."""
+    vals = summary_values(summary or COUNTERS_SUMMARY, source or PAIR_KERNEL_SRC)
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals["traffic_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
         return None
 
@@ -563,7 +586,8 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "model": "8 + 4*min(|e_i|,|e_j|,|e_k|) bytes per MoCHy-E candidate",
-                     "kernel_ms": pair_ms, "candidates_per_s": st["candidates"] / (pair_ms * 1e-3)},
+                     "kernel_ms": pair_ms, "candidates_per_s": st["candidates"] / (pair_ms * 1e-3),
+                     "valu_issue": valu_issue(pair_ms)},
         "phases_ms": {k: v / K for k, v in phase_sum.items() if v},
         "identity_open_plus_3closed_eq_candidates": bool(identity_ok),
     }
