@@ -92,14 +92,17 @@ __global__ __launch_bounds__(256) void k_light_pairs(
 constexpr int kFixThreads = 512;
 constexpr int kFixCopies = 4;
 
-__global__ __launch_bounds__(kFixThreads) void k_light_fix(
+// At most 64 registers (8 waves per SIMD: 4 blocks, 32 waves per CU; the
+// scan waits on loads, so resident waves count more than entries per lane).
+__global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_light_fix(
     int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
     const int32_t* __restrict__ owners,
     const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
     const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
-    const uint16_t* __restrict__ code_to_id3, unsigned long long* hist_out) {
+    const uint32_t* __restrict__ esize, const uint16_t* __restrict__ code_to_id3,
+    unsigned long long* hist_out) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
   // kFixCopies histogram copies, lane l adding to copy l % kFixCopies (fewer
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
     // stage are issued together, with no branch between them (an entry that
     // is not a centre reads a valid dummy slot), since the work is bound by
     // load latency: 3 of 4 scanned entries are centres on hub-heavy graphs
-    constexpr int kUnroll = 8;
+    constexpr int kUnroll = 6;
     constexpr int step = kWave;
     for (int r0 = lane; r0 < dk; r0 += kUnroll * step) {
       int32_t iv[kUnroll];
@@ -195,15 +198,14 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
         qj[u] = hit[u] ? int(rank[il >> 5] + __popc(iw & (ibit - 1u))) : 0;
       }
       uint32_t mji[kUnroll], mik[kUnroll];
-      int64_t p0[kUnroll], p1[kUnroll];
+      uint32_t av[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int r = min(r0 + u * step, dk - 1);
         const int32_t iu = hit[u] ? iv[u] : j;
         mji[u] = recm[jb + qj[u]];
         mik[u] = recm[kb + r];
-        p0[u] = edge_ptr[iu];
-        p1[u] = edge_ptr[iu + 1];
+        av[u] = esize[iu];
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
         const uint32_t t = __popc(mji[u] & mjk);
         const uint32_t r5h = __popc(mjk & H & ~mji[u]);
         const uint32_t pj = __popc(mji[u]);
-        const uint32_t a = uint32_t(p1[u] - p0[u]);
+        const uint32_t a = av[u];
         Side K;
         K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
         const uint32_t oj = sizej - pj;
@@ -231,6 +233,12 @@ __global__ __launch_bounds__(kFixThreads) void k_light_fix(
     for (int c = 0; c < kFixCopies; ++c) v += hist[c * kHistSlots + t];
     if (v) atomicAdd(&hist_out[int64_t(gj) * kHistSlots + t], v);
   }
+}
+
+// esize[x] = |e_x|.
+__global__ void k_edge_sizes(int64_t E, const int64_t* __restrict__ edge_ptr, uint32_t* esize) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < E) esize[x] = uint32_t(edge_ptr[x + 1] - edge_ptr[x]);
 }
 
 // owners: hyperedges with at least one light partner, compacted.
@@ -305,10 +313,17 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);
-  k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners, g->edge_ptr,
-                                                   g->edge_nodes, g->heavy_bit, g->lg_ptr, g->lg_col,
-                                                   g->recm, ctx->d_code_to_id3,
-                                                   (unsigned long long*)d_hist);
+  // hyperedge sizes as 32-bit words: one load and one register per centre in
+  // flight (two 64-bit offsets otherwise), which keeps the kernel within 64
+  // registers, so 4 blocks (32 waves) are resident per CU instead of 3
+  uint32_t* esize = nullptr;
+  if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done2(rc);
+  k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
+  k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners,
+                                                           g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
+                                                           g->lg_col, g->recm, esize, ctx->d_code_to_id3,
+                                                           (unsigned long long*)d_hist);
+  device_free(ctx, esize);
   MOCHY_HIP(hipGetLastError());
   MOCHY_HIP(hipStreamSynchronize(st));
   return done2(MOCHY_OK);
