@@ -119,6 +119,9 @@ __global__ __launch_bounds__(256) void k_aplus(
 // added; a hit outside N_i is a path.
 constexpr int kHsThreads = 256;
 constexpr int kHsUnroll = 8;  // row entries per thread in flight at once
+// blocks launched per CU (a persistent queue of work items): as many as the
+// LDS and registers let reside, so that every CU keeps its waves busy
+constexpr unsigned kHsBlocksPerCu = 8;
 constexpr int kBins = (MOCHY_MAX_EDGE + 1) * (MOCHY_MAX_EDGE + 1);
 
 __device__ __forceinline__ uint32_t bin_of(uint32_t size, uint32_t omega) {
@@ -393,7 +396,7 @@ mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t 
   mochy_status rc = hs_items<false>(ctx, g, n0, s, seed, it);
   if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
-  k_hsample<false><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
+  k_hsample<false><<<unsigned(ctx->num_cus) * kHsBlocksPerCu, kHsThreads, dyn, st>>>(
       n0, s, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
       ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
   phase_end(ctx, kPhSample);
@@ -420,7 +423,7 @@ mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, i
   mochy_status rc = hs_items<true>(ctx, g, c0, n, 0ull, it);
   if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
-  k_hsample<true><<<unsigned(ctx->num_cus) * 2u, kHsThreads, dyn, st>>>(
+  k_hsample<true><<<unsigned(ctx->num_cus) * kHsBlocksPerCu, kHsThreads, dyn, st>>>(
       c0, n, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
       ctx->d_code_to_id3, queue, (unsigned long long*)d_prof);
   k_fold_rows<<<unsigned((n * MOCHY_NUM_H + 255) / 256), 256, 0, st>>>(n, d_prof, ctx->d_id3_to_id26,
