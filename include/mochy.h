@@ -39,7 +39,7 @@ typedef enum {
                              size exceeds what the library can address */
   MOCHY_ENOMEM = -4,      /* device or host allocation failed */
   MOCHY_EDEVICE = -5,     /* a HIP runtime call failed */
-  MOCHY_EUNSUPPORTED = -6 /* valid request this build does not handle (message says why) */
+  MOCHY_EUNSUPPORTED = -6 /* valid request the library does not handle (message says why) */
 } mochy_status;
 
 #define MOCHY_MAX_EDGE 32   /* nodes per hyperedge: the per-centre region masks are 32-bit */

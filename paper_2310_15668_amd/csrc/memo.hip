@@ -493,7 +493,7 @@ __global__ __launch_bounds__(kMemoThreads) void k_memo(
       memo_off[key] = off == ~0ull ? -1 : int64_t(off);
       if (off != ~0ull) {
         atomicAdd(n_memo, 1ull);
-        // list entries this build walks (one walk per pass of slots)
+        // list entries the memo build walks (one walk per pass of slots)
         const int per = int(kMemoCtr / (uint32_t(kDiff) * uint32_t(a) + uint32_t(kTally) + uint32_t(kCBins)));
         atomicAdd(n_memo + 1, (unsigned long long)(s_wpre[s_nw]) * (unsigned long long)((nq + per) / per));
       }
