@@ -524,7 +524,10 @@ constexpr int kGStride = kHistSlots + 1;
 // bit set or clear as row j has members above the centre or not, so the
 // selected lane count is zero exactly when the pair weighs nothing (every
 // group holds at least one neighbour, and kn = 0 on lanes past the row).
-template <bool kDiag, bool kNarrow>
+// kAllA: every lane's group and j have members above the centre, so every
+// pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
+// past the row's end has N = A = 0 and adds 0 at a valid class).
+template <bool kDiag, bool kNarrow, bool kAllA>
 __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks,
                                            const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
                                            uint32_t ka, int kp, const uint16_t* __restrict__ lut,
@@ -532,6 +535,17 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   const uint32_t mj = rj.x;
   const uint32_t xm = mj & k.m, xl = rj.z & khl, xh = rj.w & khh;
   const bool disjoint = (xm | xl | xh) == 0u;
+  if (kAllA && !kDiag) {
+    uint32_t cx = cj.x, cy = cj.y;
+    asm("" : "+s"(cx), "+s"(cy));
+    const uint32_t y = disjoint ? kn : ka;
+    const uint32_t x = kNarrow ? (disjoint ? cx : cy) & 0xffffffu : (disjoint ? cx : cy);
+    const uint32_t t = uint32_t(__popc(xm));
+    const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
+    const uint32_t code = pair_code_aks(aks, __popc(mj), rj.y & 0xffu, k, t, r5);
+    atomicAdd(&hist[lut[code]], uint64_t(x) * y);
+    return;
+  }
   // the counts of j are uniform: kept in scalar registers as two 32-bit
   // values (seen as one 64-bit word, the test below becomes a vector compare)
   uint32_t cx = cj.x, cy = cj.y;
@@ -550,7 +564,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   }
 }
 
-template <bool kDiag, bool kNarrow>
+template <bool kDiag, bool kNarrow, bool kAllA>
 __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
                                       int j0, int j1, uint32_t aks, const Side& k, uint32_t kn,
                                       uint32_t ka, int kp, const uint16_t* __restrict__ lut,
@@ -560,13 +574,13 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag, kNarrow>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow, kAllA>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow, kAllA>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow, kAllA>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow, kAllA>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
   }
   for (; j < j1; ++j)
-    gpair_step<kDiag, kNarrow>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kNarrow, kAllA>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
 }
 
 // A pair in which one group has no member above the centre counts only when
@@ -723,10 +737,13 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       owalk<false>(grow, gc, 0, na, aks, k0, k, kn, kp, lut, myhist);
       owalk<false>(growb, gcb, na, blo, aks, k0, k, kn, kp, lut, myhist);
       owalk<true>(growb, gcb, blo, kmax, aks, k0, k, kn, kp, lut, myhist);
+    } else if (blo + kWave <= na) {  // every lane has members above the centre
+      gwalk<false, kNarrow, true>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, kNarrow, false>(grow, gc, blo, kmax, aks, k, kn, ka, kp, lut, myhist);
     } else {  // j with members above the centre: every pair; the others: open only
       const int ka1 = min(kmax, na);
-      gwalk<false, kNarrow>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
-      gwalk<true, kNarrow>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<false, kNarrow, false>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, kNarrow, false>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
       owalk<true>(growb, gcb, ka1, kmax, aks, k0, k, kn, kp, lut, myhist);
     }
     if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
