@@ -90,10 +90,11 @@ __global__ __launch_bounds__(256) void k_light_pairs(
 // One block per owner; 512 threads, so that the LDS the row bitmap takes
 // still leaves room for 24 resident waves per CU (the scan waits on loads).
 constexpr int kFixThreads = 512;
-constexpr int kFixCopies = 4;
+constexpr int kFixCopies = 2;
 
-// At most 64 registers (8 waves per SIMD: 4 blocks, 32 waves per CU; the
-// scan waits on loads, so resident waves count more than entries per lane).
+// At most 64 registers (8 waves per SIMD, room for 4 blocks, 32 waves per CU,
+// when the LDS allows; the scan waits on loads, so resident waves count more
+// than entries per lane).
 __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_light_fix(
     int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
     const int32_t* __restrict__ owners,
@@ -106,8 +107,8 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
   // kFixCopies histogram copies, lane l adding to copy l % kFixCopies (fewer
-  // same-word adds in one instruction; the LDS they take costs no resident
-  // waves, which the registers limit)
+  // same-word adds in one instruction); 2 keep a block within 40 KB of LDS on
+  // graphs of up to 85k hyperedges, so that 4 blocks reside per CU
   __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
