@@ -658,8 +658,9 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
 // 512-thread blocks slower still.  Otherwise each wave has 2 copies of its
 // own, flushed whenever its rows change graph.
 constexpr int kGSharedCopies = 4;
-// batches of up to this many graphs count each graph with its own launch of
-// the shared-histogram kernel; larger ones use per-wave histograms in one launch
+// batches of up to this many graphs whose graphs average a full grid of
+// work items count each graph with its own launch of the shared-histogram
+// kernel; others use per-wave histograms in one launch
 constexpr int kPerGraphLaunches = 256;
 template <bool kNarrow, bool kShared>
 __global__ __launch_bounds__(256) void k_exact_grouped(
@@ -952,18 +953,27 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
   const bool narrow = g->max_deg < (1 << 24);
+  // a batch of graphs large enough to fill the device each: the
+  // shared-histogram kernel once per graph (a graph's items are contiguous in
+  // the schedule), each launch with its own queue counter; smaller graphs are
+  // counted together in one launch, which keeps their tails overlapped
+  std::vector<int64_t> hgq;
   if (grouped && ng > 1 && ng <= kPerGraphLaunches) {
-    // a batch: the shared-histogram kernel once per graph (a graph's items
-    // are contiguous in the schedule), each launch with its own queue counter
-    std::vector<int64_t> hgq(size_t(ng) + 1);
+    hgq.resize(size_t(ng) + 1);
     MOCHY_HIP(hipMemcpyAsync(hgq.data(), S.gq, hgq.size() * 8, hipMemcpyDeviceToHost, st));
     MOCHY_HIP(hipStreamSynchronize(st));
+    if (hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
+  }
+  if (!hgq.empty()) {
     unsigned long long* gqueue = nullptr;
     if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) { release(); return rc; }
     MOCHY_HIP(hipMemsetAsync(gqueue, 0, size_t(ng) * 8, st));
     for (int gi = 0; gi < ng; ++gi) {
-      if (hgq[gi + 1] <= hgq[gi]) continue;
-      (narrow ? k_exact_grouped<true, true> : k_exact_grouped<false, true>)<<<grid, 256, 0, st>>>(
+      const int64_t items = hgq[gi + 1] - hgq[gi];
+      if (items <= 0) continue;
+      // at most one wave per item
+      const unsigned ggrid = unsigned(std::min<int64_t>(grid, (items + kWavesPerGroup - 1) / kWavesPerGroup));
+      (narrow ? k_exact_grouped<true, true> : k_exact_grouped<false, true>)<<<ggrid, 256, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, hgq[gi], hgq[gi + 1],
           g->row_graph, gqueue + gi, ctx->d_code_to_id3, (unsigned long long*)d_hist + size_t(gi) * kHistSlots);
     }

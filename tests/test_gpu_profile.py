@@ -69,6 +69,16 @@ def test_batched_equals_sequential(ctx):
     assert len(sizes) > 1  # uneven sizes after collapsing repeated members
 
 
+def test_batch_of_large_graphs(ctx):
+    # graphs of 12k hyperedges have more work items than one launch has waves:
+    # the pair kernel runs once per graph (small graphs share one launch)
+    base = make_config("batched_base", scale=0.1)
+    assert base.num_edges > 8192
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 103)]
+    counts, *_ = run_profile(ctx, graphs)
+    assert (counts == sequential(ctx, graphs)).all()
+
+
 def test_batch_above_per_graph_launch_limit(ctx):
     # more than 256 graphs: the pair kernel counts the whole batch in one
     # launch with per-wave histograms flushed at every change of graph
