@@ -28,6 +28,16 @@
 // persistent waves.  Counts go to a per-workgroup LDS histogram (several
 // copies, picked by lane, to thin same-bin conflicts), flushed once per
 // workgroup with 64-bit global atomics.
+//
+// Grouped path (the default, k_group + k_exact_grouped): neighbours of e_i
+// with equal records (m, outside count clamped to popcount(h) + 2, h) form a
+// group with N members and A members above the centre; a pair of groups
+// stands for N_j N_k candidates if they look disjoint, A_j A_k otherwise,
+// and a group with itself for C(A, 2).  Each row's region holds the groups
+// with A > 0 first.  A pair involving a group with A = 0 counts only if open,
+// and an open class depends on j only through (popcount(m_j), min(o_j, 2)):
+// such pairs are summed per lane over runs of one such class (the groups are
+// class-ordered within each hash part) and added once per run.
 #include <vector>
 
 #include "classify.h"
@@ -651,8 +661,9 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
   __builtin_amdgcn_wave_barrier();
 }
 
-// kShared (a single graph): the block's 4 histogram copies are shared by its
-// waves, lane l adding to copy l % 4, flushed once at the end: 18 KB of LDS
+// kShared (one graph per launch: a single graph, or one graph of a batch of
+// large graphs): the block's 4 histogram copies are shared by its waves, lane
+// l adding to copy l % 4, flushed once at the end: 18 KB of LDS
 // per block, so 8 blocks (32 waves) fit on a CU; 8 shared copies (fewer
 // same-word adds, but 5 blocks per CU) were 27 % slower, 16 copies in
 // 512-thread blocks slower still.  Otherwise each wave has 2 copies of its
