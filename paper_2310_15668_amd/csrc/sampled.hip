@@ -152,7 +152,8 @@ __global__ void k_hs_items(int64_t n0, int64_t s, uint64_t seed, int64_t E,
 }
 
 // One block per work item (sample, chunk of 256 neighbours of e_i): N_i as an
-// LDS bitmap with ranks, the chunk's neighbours' rows, and for chunk 0 also
+// LDS bitmap with ranks, the chunk's neighbours' rows (each walked by one
+// wave), and for chunk 0 also
 // every pair of N_i counted as disjoint.  kProfile: the item's counts are
 // added to hist_out[(i - n0) * kHistSlots + id] (the hyperedge's profile,
 // zeroed before) instead of being summed.
