@@ -636,7 +636,7 @@ __device__ __forceinline__ void wave_hadd(unsigned long long* hist, uint32_t id,
 // key-only class if it is adjacent to the key, or the class of an e_k meeting
 // e_o only in its skipped nodes P if it holds some.
 template <bool kOvf>
-__device__ __forceinline__ void walk_other(EnumLds& L, int lane, int64_t T, uint32_t a, uint32_t b,
+__device__ __forceinline__ void walk_other(WalkLds& L, int lane, int64_t T, uint32_t a, uint32_t b,
                                            uint32_t p, uint32_t kin, uint32_t novf,
                                            const uint32_t* __restrict__ xoff,
                                            const int32_t* __restrict__ xnodes, const uint16_t* lut,
@@ -714,7 +714,7 @@ __device__ __forceinline__ void walk_other(EnumLds& L, int lane, int64_t T, uint
 }
 
 // One wave per sample of a memoized key (samples of other keys are skipped).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_msample(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_msample(
     int64_t cnt, int64_t E, const int2* __restrict__ gp, const uint32_t* __restrict__ sS,
     const uint32_t* __restrict__ smul, const int64_t* __restrict__ memo_off,
     const uint32_t* __restrict__ arena,
@@ -726,11 +726,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     unsigned long long* queue, unsigned long long* hist_out, int32_t* flags) {
   __shared__ uint16_t lut[kNumCodes];
   __shared__ unsigned long long hist[kHistSlots];
-  __shared__ EnumLds lds[kEnumWaves];
+  __shared__ WalkLds lds[kEnumWaves];
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
   for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) hist[t] = 0ull;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  EnumLds& L = lds[wave];
+  WalkLds& L = lds[wave];
   for (int t = lane; t < kBuckets; t += kWave) L.tab[t] = make_uint4(0u, 0u, 0u, 0u);
   if (lane == 0) L.novf = 0u;
   __syncthreads();

@@ -79,14 +79,14 @@ constexpr uint32_t kFI = 1, kFJ = 2;
 constexpr int kBatch = 4;                  // samples taken from the queue at a time
 constexpr int kMaxChunks = kWave * (MOCHY_MAX_EDGE / kXPad);  // chunks of one window
 
-struct EnumLds {
+// Per-wave LDS of one sample's walk.
+struct WalkLds {
   uint4 tab[kBuckets];
   uint32_t ovf[2 * MOCHY_MAX_EDGE];
   int32_t ei[MOCHY_MAX_EDGE], ej[MOCHY_MAX_EDGE];
   int32_t wn[2 * MOCHY_MAX_EDGE];          // walked nodes
   int64_t wb[2 * MOCHY_MAX_EDGE];          // node_ptr of each walked node
   int64_t pre[2 * MOCHY_MAX_EDGE + 1];     // prefix of walked list lengths
-  uint32_t tally[kPatterns * kSizeSlots];  // walked e_k by skipped nodes held and size
   // one window of 64 visits, split into 4-node chunks
   uint32_t vx[kWave];                      // start of the visit's node list in xnodes
   uint32_t vc[kWave];                      // its first chunk in the window
@@ -94,6 +94,13 @@ struct EnumLds {
   unsigned long long acc[kWave];           // packed sums of its chunks
   uint8_t cmap[kMaxChunks];                // chunk -> visit (lane)
   uint32_t novf;
+};
+
+// The plain enumeration's per-wave LDS: the walk's, and the walked e_k by
+// skipped nodes held and size (a memoized key's samples need no tally, so
+// their kernel keeps the smaller struct and more waves resident).
+struct EnumLds : WalkLds {
+  uint32_t tally[kPatterns * kSizeSlots];
 };
 
 __device__ __forceinline__ uint32_t bucket_of(int32_t z) {
