@@ -276,6 +276,14 @@ def batched_cp(args):
     for w in range(args.warmup):
         log(f"warmup {w + 1}/{args.warmup}")
         M.mochy_profile(ctx, dev[:3])
+    tuned = None
+    if args.tune:  # the pair kernel's launch shape, timed on this batch (untimed here)
+        from paper_2310_15668_amd.tune import tune_batch
+        log("tuning the pair kernel's launch shape on the batch")
+        res = tune_batch(ctx, dev)
+        tuned = {"batch_launch": res["launch"], "pair_blocks_per_cu": res["blocks"],
+                 "pair_ms": {f"launch={a},blocks={b}": t for (a, b), t in res["times"].items()}}
+        log(f"tuned: {tuned}")
     times_b, times_s = [], []
     for s in range(args.steps):
         log(f"step {s + 1}/{args.steps}: batched")
@@ -309,6 +317,8 @@ def batched_cp(args):
         "batched_triples_per_s": triples / tb, "sequential_triples_per_s": triples / ts,
         "identical_counts": True,
     }
+    if tuned is not None:
+        out["tuned"] = tuned
     print(json.dumps(out), flush=True)
 
 
@@ -480,6 +490,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2, help="large-aplus: Philox key")
     ap.add_argument("--scale", type=float, default=0.2,
                     help="batched-cp: scale of the base hypergraph and its copies")
+    ap.add_argument("--tune", action="store_true",
+                    help="batched-cp: pick the pair kernel's launch shape by timing before the steps")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: Poisson arrival rate (req/s)")
     ap.add_argument("--max-edges", type=int, default=20000,

@@ -104,6 +104,15 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                   any (0, default; the 16 with the most list entries
                                   if the key would need too many node sets) or always
                                   those 16 (1); same hits */
+#define MOCHY_OPT_BATCH_LAUNCH 7  /* exact counting of a batch (mochy_profile) launches the
+                                     group-pair kernel once for the whole batch (1), once
+                                     per graph (2; batches of at most 256 graphs, larger
+                                     ones take one launch), or per graph when the graphs
+                                     average a full grid of work items each (0, default);
+                                     same counts */
+#define MOCHY_OPT_PAIR_BLOCKS 8  /* blocks of the exact pair kernel launched per compute
+                                    unit, 1..16 (default 8; a launch per graph takes at
+                                    most one wave per work item); same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

@@ -26,6 +26,8 @@ MOCHY_OPT_MEMO_BUDGET = 3
 MOCHY_OPT_MEMO_ALL = 4
 MOCHY_OPT_MEMO_POOL = 5
 MOCHY_OPT_GROUP_CAPACITY = 6
+MOCHY_OPT_BATCH_LAUNCH = 7
+MOCHY_OPT_PAIR_BLOCKS = 8
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 

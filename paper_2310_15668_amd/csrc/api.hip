@@ -347,6 +347,14 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     ctx->memo_pool = value != 0;
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_BATCH_LAUNCH && value >= 0 && value <= 2) {
+    ctx->batch_launch = int(value);
+    return MOCHY_OK;
+  }
+  if (option == MOCHY_OPT_PAIR_BLOCKS && value >= 1 && value <= 16) {
+    ctx->pair_blocks = int(value);
+    return MOCHY_OK;
+  }
   ctx->err = "unknown option or value";
   return MOCHY_EINVAL;
 }

@@ -37,6 +37,8 @@ struct mochy_ctx {
   int64_t memo_budget = int64_t(16) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
   bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
+  int batch_launch = 0;               // pair kernel over a batch: 0 size rule, 1 one launch, 2 per graph
+  int pair_blocks = 8;                // pair kernel blocks launched per CU (MOCHY_OPT_PAIR_BLOCKS)
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]

@@ -932,7 +932,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int ng = g->ng;
   MOCHY_HIP(hipMemsetAsync(d_hist, 0, size_t(ng) * kHistSlots * 8, st));
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
-  const unsigned grid = unsigned(ctx->num_cus) * 8u;
+  const unsigned grid = unsigned(ctx->num_cus) * unsigned(ctx->pair_blocks);
   int64_t* goff = nullptr;
   const int64_t* gbase = nullptr;
   int64_t cap0 = 0;
@@ -968,12 +968,13 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   // shared-histogram kernel once per graph (a graph's items are contiguous in
   // the schedule), each launch with its own queue counter; smaller graphs are
   // counted together in one launch, which keeps their tails overlapped
+  // (MOCHY_OPT_BATCH_LAUNCH can force either form)
   std::vector<int64_t> hgq;
-  if (grouped && ng > 1 && ng <= kPerGraphLaunches) {
+  if (grouped && ng > 1 && ng <= kPerGraphLaunches && ctx->batch_launch != 1) {
     hgq.resize(size_t(ng) + 1);
     MOCHY_HIP(hipMemcpyAsync(hgq.data(), S.gq, hgq.size() * 8, hipMemcpyDeviceToHost, st));
     MOCHY_HIP(hipStreamSynchronize(st));
-    if (hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
+    if (ctx->batch_launch == 0 && hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
   }
   if (!hgq.empty()) {
     unsigned long long* gqueue = nullptr;

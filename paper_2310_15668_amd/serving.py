@@ -181,6 +181,22 @@ class CPServer:
                 self._dispatch(time.perf_counter())
             ticket._ev.set()
 
+    def apply_options(self, options: dict):
+        """Sets {option: value} (e.g. a tuned launch shape) on every slot's
+        context; call before submitting requests."""
+        for c in self._ctxs:
+            for opt, val in options.items():
+                c.set_option(opt, val)
+
+    def tune(self, graphs) -> dict:
+        """Tunes the batched pass's launch shape on one representative request
+        (``tune.tune_batch`` on the first slot) and applies it to every slot."""
+        from .tune import tune_batch
+        res = tune_batch(self._ctxs[0], graphs)
+        self.apply_options({_lib.MOCHY_OPT_BATCH_LAUNCH: res["launch"],
+                            _lib.MOCHY_OPT_PAIR_BLOCKS: res["blocks"]})
+        return res
+
     def close(self):
         with self._lock:
             self._stop = True

@@ -150,3 +150,39 @@ def test_chung_lu_copies_match_oracle(ctx):
         r26, r431, _ = native.mochy_e(h, nthreads=8)
         assert (counts[k, :26] == r26).all() and (counts[k, 26:] == r431).all(), k
     check_cp(counts, sig26, cp26, sig431, cp431)
+
+
+def test_launch_shapes_and_tuner(ctx):
+    # every launch shape of the pair kernel over a batch gives the same counts
+    # (one launch or one per graph, 1 to 16 blocks per CU); the tuner keeps one
+    # of them, and a server tuned on the first request answers as before
+    import paper_2310_15668_amd as M
+    from paper_2310_15668_amd.serving import CPServer
+    from paper_2310_15668_amd.tune import CANDIDATES, tune_batch
+    base = make_config("batched_base", scale=0.05)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 104)]
+    ref = sequential(ctx, graphs)
+    try:
+        for launch, blocks in list(CANDIDATES) + [(1, 1), (2, 16), (0, 3)]:
+            ctx.set_option(M.MOCHY_OPT_BATCH_LAUNCH, launch)
+            ctx.set_option(M.MOCHY_OPT_PAIR_BLOCKS, blocks)
+            print(f"[gpu] launch={launch} blocks={blocks}", flush=True)
+            counts, *_ = run_profile(ctx, graphs)
+            assert (counts == ref).all(), (launch, blocks)
+        for opt, val in ((M.MOCHY_OPT_BATCH_LAUNCH, 3), (M.MOCHY_OPT_PAIR_BLOCKS, 0),
+                         (M.MOCHY_OPT_PAIR_BLOCKS, 17)):
+            with pytest.raises(M.MochyError) as e:
+                ctx.set_option(opt, val)
+            assert e.value.status == -1
+        req = [(h.edge_ptr, h.edge_nodes, h.num_nodes) for h in graphs]
+        res = tune_batch(ctx, req)
+        print(f"[gpu] tuned: {res}", flush=True)
+        assert (res["launch"], res["blocks"]) in CANDIDATES
+        assert all(t > 0 for t in res["times"].values())
+        with CPServer(0, slots=2) as srv:
+            srv.tune(req)
+            out = [t.wait(timeout=120) for t in [srv.submit(req), srv.submit(req[:3])]]
+        assert (out[0]["counts"] == ref).all() and (out[1]["counts"] == ref[:3]).all()
+    finally:
+        ctx.set_option(M.MOCHY_OPT_BATCH_LAUNCH, 0)
+        ctx.set_option(M.MOCHY_OPT_PAIR_BLOCKS, 8)
