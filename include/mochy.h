@@ -113,6 +113,12 @@ const char* mochy_last_error(const mochy_ctx* ctx);
 #define MOCHY_OPT_PAIR_BLOCKS 8  /* blocks of the exact pair kernel launched per compute
                                     unit, 1..16 (default 8; a launch per graph takes at
                                     most one wave per work item); same counts */
+#define MOCHY_OPT_CACHE_BYTES 9  /* device buffers of 64 MiB or more that a call frees are
+                                    kept by the context, up to this many bytes in all, and
+                                    reused by later calls on it (default half of the
+                                    device memory; 0 = free at once, releasing what is
+                                    kept); an allocation that fails first releases them;
+                                    mochy_ctx_destroy frees them; same results */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

@@ -10,5 +10,6 @@ from ._lib import (  # noqa: F401
     mochy_count_sampled, mochy_count_sampled_edges, mochy_hyperedge_profiles, mochy_profile, motif_pattern, parent_motif, NUM_H, NUM_3H, MOCHY_DEDUP,
     MOCHY_LG_FREE, MOCHY_OPT_GROUPS, MOCHY_OPT_APLUS_ROWS, MOCHY_OPT_MEMO_BUDGET, MOCHY_OPT_MEMO_ALL,
     MOCHY_OPT_MEMO_POOL, MOCHY_OPT_GROUP_CAPACITY, MOCHY_OPT_BATCH_LAUNCH, MOCHY_OPT_PAIR_BLOCKS,
+    MOCHY_OPT_CACHE_BYTES,
     mochy_graph_stats, mochy_phase_ms, mochy_memo_stats,
 )

@@ -28,6 +28,7 @@ MOCHY_OPT_MEMO_POOL = 5
 MOCHY_OPT_GROUP_CAPACITY = 6
 MOCHY_OPT_BATCH_LAUNCH = 7
 MOCHY_OPT_PAIR_BLOCKS = 8
+MOCHY_OPT_CACHE_BYTES = 9
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 

@@ -220,23 +220,72 @@ extern "C" mochy_status mochy_memo_stats(const mochy_ctx* ctx, int64_t* out) {
 // Graph and scratch buffers are stream-ordered allocations on the context's
 // stream when the device has memory pools, so that a free never waits for
 // work queued by other contexts on other streams.
+static hipError_t raw_alloc(mochy_ctx* ctx, void** p, size_t n) {
+  return ctx->async_alloc ? hipMallocAsync(p, n, ctx->stream) : hipMalloc(p, n);
+}
+
+static void raw_free(mochy_ctx* ctx, void* p) {
+  if (ctx->async_alloc) (void)hipFreeAsync(p, ctx->stream);
+  else (void)hipFree(p);
+}
+
+void cache_release(mochy_ctx* ctx) {
+  for (auto& kv : ctx->cache_free) {
+    ctx->cache_live.erase(kv.second);
+    raw_free(ctx, kv.second);
+  }
+  ctx->cache_free.clear();
+  ctx->cache_bytes = 0;
+}
+
+// Buffers of at least kCacheMinBytes go through a per-context cache: a freed
+// block is kept (up to cache_limit bytes in all) and handed to a later
+// request that it fits with at most half of it unused.  Freeing and mapping
+// again the hundred-odd GB that a batch of 65 graphs holds costs up to
+// seconds per call; reusing the blocks costs nothing.  A context works on one
+// stream, so a reused block's earlier readers are ordered before its new
+// writers.
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
-  const size_t n = std::max<size_t>(bytes, 8);
-  const hipError_t e = ctx->async_alloc ? hipMallocAsync(p, n, ctx->stream) : hipMalloc(p, n);
+  size_t n = std::max<size_t>(bytes, 8);
+  const bool cached = ctx->cache_limit > 0 && n >= kCacheMinBytes;
+  if (cached) {
+    auto it = ctx->cache_free.lower_bound(n);
+    if (it != ctx->cache_free.end() && it->first / 2 <= n) {
+      *p = it->second;
+      ctx->cache_bytes -= int64_t(it->first);
+      ctx->cache_free.erase(it);
+      return MOCHY_OK;
+    }
+    n = (n + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);  // whole 2 MiB pages
+  }
+  hipError_t e = raw_alloc(ctx, p, n);
+  if (e != hipSuccess && !ctx->cache_free.empty()) {  // give the cached blocks back and retry
+    (void)hipGetLastError();
+    cache_release(ctx);
+    (void)hipStreamSynchronize(ctx->stream);
+    e = raw_alloc(ctx, p, n);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     ctx->err = "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
     return MOCHY_ENOMEM;
   }
+  if (cached) ctx->cache_live[*p] = n;
   return MOCHY_OK;
 }
 
 void device_free(mochy_ctx* ctx, void* p) {
   if (!p) return;
-  if (ctx->async_alloc) (void)hipFreeAsync(p, ctx->stream);
-  else (void)hipFree(p);
+  auto it = ctx->cache_live.find(p);
+  if (it != ctx->cache_live.end() && ctx->cache_bytes + int64_t(it->second) <= ctx->cache_limit) {
+    ctx->cache_free.emplace(it->second, p);  // stays in cache_live until released
+    ctx->cache_bytes += int64_t(it->second);
+    return;
+  }
+  if (it != ctx->cache_live.end()) ctx->cache_live.erase(it);
+  raw_free(ctx, p);
 }
 
 // Buffers that live as long as the context.
@@ -265,6 +314,7 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(MOCHY_EDEVICE);
   ctx->num_cus = prop.multiProcessorCount;
+  ctx->cache_limit = int64_t(prop.totalGlobalMem / 2);
   if (hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -304,6 +354,7 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
 extern "C" void mochy_ctx_destroy(mochy_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  cache_release(ctx);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(ctx->d_code_to_id3);
   (void)hipFree(ctx->d_id3_to_id26);
@@ -353,6 +404,11 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
   }
   if (option == MOCHY_OPT_PAIR_BLOCKS && value >= 1 && value <= 16) {
     ctx->pair_blocks = int(value);
+    return MOCHY_OK;
+  }
+  if (option == MOCHY_OPT_CACHE_BYTES && value >= 0) {
+    ctx->cache_limit = value;
+    if (ctx->cache_bytes > value) cache_release(ctx);
     return MOCHY_OK;
   }
   ctx->err = "unknown option or value";

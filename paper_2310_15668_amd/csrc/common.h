@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "mochy.h"
@@ -39,6 +41,13 @@ struct mochy_ctx {
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
   int batch_launch = 0;               // pair kernel over a batch: 0 size rule, 1 one launch, 2 per graph
   int pair_blocks = 8;                // pair kernel blocks launched per CU (MOCHY_OPT_PAIR_BLOCKS)
+  // freed transient buffers of at least kCacheMinBytes kept for reuse on this
+  // context's stream (MOCHY_OPT_CACHE_BYTES): size -> block, and the size of
+  // every block handed out from or destined for the cache
+  int64_t cache_limit = 0;            // bytes (half the device memory from creation)
+  int64_t cache_bytes = 0;
+  std::multimap<size_t, void*> cache_free;
+  std::unordered_map<void*, size_t> cache_live;
   int num_cus = 0;
   std::string err;
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
@@ -189,6 +198,8 @@ mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, i
 // api.hip helpers: allocation and release ordered on the context stream
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);
 void device_free(mochy_ctx* ctx, void* p);
+void cache_release(mochy_ctx* ctx);  // frees every cached block
+constexpr size_t kCacheMinBytes = size_t(64) << 20;
 
 // Largest graph (hyperedges) whose row bitmap and rank table fit in LDS.
 constexpr int64_t kMaxGraphEdges = 200000;

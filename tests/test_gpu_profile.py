@@ -186,3 +186,35 @@ def test_launch_shapes_and_tuner(ctx):
     finally:
         ctx.set_option(M.MOCHY_OPT_BATCH_LAUNCH, 0)
         ctx.set_option(M.MOCHY_OPT_PAIR_BLOCKS, 8)
+
+
+def test_buffer_cache_reuse_and_release(ctx):
+    # freed buffers of 64 MiB or more stay with the context and serve the next
+    # call of the same shape (no growth in device memory held), setting the
+    # limit to 0 gives them back, and the counts never change
+    import torch
+    import paper_2310_15668_amd as M
+    base = make_config("batched_base", scale=0.05)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 104)]
+    with M.Context(0) as c:
+        print("[gpu] cache: first call", flush=True)
+        a = run_profile(c, graphs)[0]
+        torch.cuda.synchronize()
+        f1 = torch.cuda.mem_get_info(0)[0]
+        for k in range(2):
+            print(f"[gpu] cache: repeat {k}", flush=True)
+            assert (run_profile(c, graphs)[0] == a).all()
+        torch.cuda.synchronize()
+        f2 = torch.cuda.mem_get_info(0)[0]
+        assert abs(f2 - f1) < (256 << 20), (f1, f2)
+        c.set_option(M.MOCHY_OPT_CACHE_BYTES, 0)
+        torch.cuda.synchronize()
+        f3 = torch.cuda.mem_get_info(0)[0]
+        assert f3 - f2 >= (64 << 20), (f2, f3)
+        assert (run_profile(c, graphs)[0] == a).all()
+        c.set_option(M.MOCHY_OPT_CACHE_BYTES, 1 << 30)  # a limit below what a call frees
+        assert (run_profile(c, graphs)[0] == a).all()
+        assert (run_profile(c, graphs)[0] == a).all()
+        with pytest.raises(M.MochyError):
+            c.set_option(M.MOCHY_OPT_CACHE_BYTES, -1)
+    assert (a == sequential(ctx, graphs)).all()
