@@ -117,7 +117,9 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                     kept by the context, up to this many bytes in all, and
                                     reused by later calls on it (default half of the
                                     device memory; 0 = free at once, releasing what is
-                                    kept); an allocation that fails first releases them;
+                                    kept); an allocation that fails first releases them
+                                    (this context's only: several contexts on one device
+                                    should share the memory by their limits);
                                     mochy_ctx_destroy frees them; same results */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 

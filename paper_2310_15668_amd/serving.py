@@ -117,13 +117,22 @@ class CPServer:
     """Serves profile requests on one device with ``slots`` concurrent streams."""
 
     def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int | None = None,
-                 eps: float = 1.0, aging_s: float = 1.0):
-        if budget_bytes is None:
+                 eps: float = 1.0, aging_s: float = 1.0, cache_bytes: int | None = None):
+        # device memory: budget_bytes for the admitted requests, and each
+        # slot's context keeps at most cache_bytes of the buffers its requests
+        # freed (by default 80 % and 20 % / slots of what is free now), so
+        # that an idle slot's kept buffers never hold what admission hands out
+        if budget_bytes is None or cache_bytes is None:
             import torch
             free, _ = torch.cuda.mem_get_info(device)
-            budget_bytes = int(0.8 * free)
+            if budget_bytes is None:
+                budget_bytes = int(0.8 * free)
+            if cache_bytes is None:
+                cache_bytes = max(0, int(min(0.2 * free, free - budget_bytes) / slots))
         self.eps = float(eps)
         self._ctxs = [_lib.Context(device) for _ in range(slots)]
+        for c in self._ctxs:
+            c.set_option(_lib.MOCHY_OPT_CACHE_BYTES, cache_bytes)
         self._adm = Admission(budget_bytes, aging_s)
         self._lock = threading.Lock()
         self._pending = {}            # rid -> (ticket, graphs, nbytes)
