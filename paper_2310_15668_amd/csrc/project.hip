@@ -210,19 +210,34 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
     const int32_t x = lg_col[base + p];
     uint32_t m = 0, o = 0, light = 0;
     unsigned long long hv = 0;
-    for (int64_t q = ptr[x]; q < ptr[x + 1]; ++q) {
-      const int32_t v = nodes[q];
-      int lo = 0, hi = a;  // binary search of v in e_i
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (ei[mid] < v) lo = mid + 1; else hi = mid;
+    const int64_t q1 = ptr[x + 1];
+    // four of e_x's nodes at a time, their loads (nodes, then heavy bits)
+    // issued together before any is used; -1 pads past the list's end
+    for (int64_t q = ptr[x]; q < q1; q += 4) {
+      int32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = q + u < q1 ? nodes[q + u] : -1;
+      int at[4];
+      int hb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int lo = 0, hi = a;  // binary search of v in e_i
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (ei[mid] < v[u]) lo = mid + 1; else hi = mid;
+        }
+        at[u] = lo < a && ei[lo] == v[u] ? lo : -1;
+        hb[u] = v[u] >= 0 && at[u] < 0 ? int(heavy_bit[v[u]]) : -1;
       }
-      if (lo < a && ei[lo] == v) {
-        m |= 1u << lo;
-      } else {
-        ++o;
-        const int hb = heavy_bit[v];
-        if (hb >= 0) hv |= 1ull << hb; else light = 1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (v[u] < 0) continue;
+        if (at[u] >= 0) {
+          m |= 1u << at[u];
+        } else {
+          ++o;
+          if (hb[u] >= 0) hv |= 1ull << hb[u]; else light = 1;
+        }
       }
     }
     if (o == 0 && __popc(m) == a) atomicOr(flags, kFlagDup);
