@@ -199,7 +199,9 @@ class CPServer:
 
     def tune(self, graphs) -> dict:
         """Tunes the batched pass's launch shape on one representative request
-        (``tune.tune_batch`` on the first slot) and applies it to every slot."""
+        (``tune.tune_batch`` on the first slot) and applies it to every slot;
+        call it before submitting requests (it uses a slot's context from the
+        calling thread)."""
         from .tune import tune_batch
         res = tune_batch(self._ctxs[0], graphs)
         self.apply_options({_lib.MOCHY_OPT_BATCH_LAUNCH: res["launch"],
