@@ -87,6 +87,15 @@ __global__ __launch_bounds__(256) void k_light_pairs(
   }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn; block b takes the owner that
+// gives each XCD a contiguous range of the owner list (a bijection onto
+// [0, nb)), so that owners listed together share one XCD's L2.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b % kXcds, k = b / kXcds, per = nb / kXcds, extra = nb % kXcds;
+  return int64_t(x) * per + (x < extra ? x : extra) + k;
+}
+
 // One block per owner; 512 threads, so that the LDS the row bitmap takes
 // still leaves room for 24 resident waves per CU (the scan waits on loads).
 constexpr int kFixThreads = 512;
@@ -112,7 +121,8 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
-  const int32_t j = owners[blockIdx.x];
+  const int64_t ob = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t j = owners[ob];
   const int gj = row_graph[j];
   const int64_t e0 = geoff[gj];  // row j's graph owns hyperedges [e0, geoff[gj + 1])
   const int nwE = int((geoff[gj + 1] - e0 + 31) / 32);
@@ -163,7 +173,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   // no lanes idle)
   const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
   unsigned long long* myhist = hist + (lane & (kFixCopies - 1)) * kHistSlots;
-  for (int64_t pp = poff[blockIdx.x] + wave; pp < poff[blockIdx.x + 1]; pp += kFixThreads / kWave) {
+  for (int64_t pp = poff[ob] + wave; pp < poff[ob + 1]; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
     // record of e_k in row j
     const int64_t kl = k - e0;
