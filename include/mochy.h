@@ -86,12 +86,12 @@ const char* mochy_last_error(const mochy_ctx* ctx);
 #define MOCHY_OPT_APLUS_ROWS 2  /* MoCHy-A+ on a graph with a stored line graph: enumerate
                                    N_i ∪ N_j on the fly from the node lists (0, default) or
                                    by merging the two stored rows (1); same hits */
-#define MOCHY_OPT_GROUP_CAPACITY 6  /* exact counting of a single graph groups each row's
-                                       neighbours in one pass into space for all of its
-                                       records when that takes at most this many bytes (24 per
-                                       record; default 24 GiB), else (and for batches) counts
-                                       the groups first and allocates them exactly; 0 = always
-                                       count first; same counts */
+#define MOCHY_OPT_GROUP_CAPACITY 6  /* exact counting (of a graph, or of a whole batch in
+                                       mochy_profile) groups each row's neighbours in one
+                                       pass into space for all of its records when that
+                                       takes at most this many bytes (24 per record; default
+                                       24 GiB), else counts the groups first and allocates
+                                       them exactly; 0 = always count first; same counts */
 #define MOCHY_OPT_MEMO_BUDGET 3  /* on-the-fly MoCHy-A+ groups its samples by key hyperedge
                                     (the endpoint of larger line-graph degree, Algorithm 9)
                                     and memoizes the neighbourhood counts of keys, in

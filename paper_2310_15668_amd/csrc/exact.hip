@@ -836,11 +836,11 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 // Groups of rows [c0, c1): goff[E+1] the prefix of the rows' group counts,
 // row i's groups in grec / gcnt [gbase[i] - cap0, gbase[i + 1] - cap0): the
 // gna[i] with members above the centre first, the others at the region's
-// end (the region holds exactly the groups in the compact layout).  For a single graph
-// with up to ctx->group_cap_bytes of row capacity, one pass writes each row's
-// groups at its line-graph offset (gbase = lg_ptr); otherwise (batches,
-// larger graphs) the groups are counted first and allocated exactly
-// (gbase = goff, cap0 = 0).  Returns MOCHY_ENOMEM (nothing held) if
+// end (the region holds exactly the groups in the compact layout).  With up
+// to ctx->group_cap_bytes of row capacity (a graph or a whole batch), one
+// pass writes each row's groups at its line-graph offset (gbase = lg_ptr);
+// otherwise the groups are counted first and allocated exactly (gbase = goff,
+// cap0 = 0).  Returns MOCHY_ENOMEM (nothing held) if
 // the group arrays do not fit or a row could not be grouped; the caller then
 // pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
@@ -872,9 +872,8 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   MOCHY_HIP(hipStreamSynchronize(st));
   const int64_t row0 = ctx->h_small[0];
   const int64_t cap = ctx->h_small[1] - row0;
-  // one pass into row capacity for a single graph (a batch's transient row
-  // capacity would be far larger than its groups)
-  const bool by_rows = g->ng == 1 && cap * 24 <= ctx->group_cap_bytes;
+  // one pass into row capacity (a graph or a batch) when that fits the limit
+  const bool by_rows = cap * 24 <= ctx->group_cap_bytes;
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||

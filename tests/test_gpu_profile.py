@@ -218,3 +218,22 @@ def test_buffer_cache_reuse_and_release(ctx):
         with pytest.raises(M.MochyError):
             c.set_option(M.MOCHY_OPT_CACHE_BYTES, -1)
     assert (a == sequential(ctx, graphs)).all()
+
+
+@pytest.mark.parametrize("capacity", [0, 1 << 40])
+def test_batch_group_layouts(ctx, capacity):
+    # a batch grouped in the counted-first layout (capacity 0) and in one pass
+    # into row capacity gives the counts of each graph alone
+    import paper_2310_15668_amd as M
+    base = make_config("batched_base", scale=0.05)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 104)]
+    small = [make_config("tiny")] + [stub_matching_copy(make_config("tiny"), s) for s in range(7)]
+    ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, capacity)
+    try:
+        print(f"[gpu] group capacity {capacity}", flush=True)
+        a = run_profile(ctx, graphs)[0]
+        b = run_profile(ctx, small)[0]
+    finally:
+        ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
+    assert (a == sequential(ctx, graphs)).all()
+    assert (b == sequential(ctx, small)).all()
