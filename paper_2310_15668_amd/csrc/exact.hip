@@ -839,8 +839,8 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 // end (the region holds exactly the groups in the compact layout).  With up
 // to ctx->group_cap_bytes of row capacity (a graph or a whole batch), one
 // pass writes each row's groups at its line-graph offset (gbase = lg_ptr);
-// otherwise the groups are counted first and allocated exactly (gbase = goff,
-// cap0 = 0).  Returns MOCHY_ENOMEM (nothing held) if
+// otherwise, or if that capacity cannot be allocated, the groups are counted
+// first and allocated exactly (gbase = goff, cap0 = 0).  Returns MOCHY_ENOMEM (nothing held) if
 // the group arrays do not fit or a row could not be grouped; the caller then
 // pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
@@ -873,7 +873,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int64_t row0 = ctx->h_small[0];
   const int64_t cap = ctx->h_small[1] - row0;
   // one pass into row capacity (a graph or a batch) when that fits the limit
-  const bool by_rows = cap * 24 <= ctx->group_cap_bytes;
+  bool by_rows = cap * 24 <= ctx->group_cap_bytes;
   mochy_status rc;
   if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
@@ -882,12 +882,19 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     return fail(rc);
   MOCHY_HIP(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st));
   MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st));
+  if (by_rows && (device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16) != MOCHY_OK ||
+                  device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8) != MOCHY_OK)) {
+    // no room for the row capacity: count the groups first and allocate them exactly
+    device_free(ctx, *grec);
+    device_free(ctx, *gcnt);
+    *grec = nullptr;
+    *gcnt = nullptr;
+    ctx->err.clear();
+    by_rows = false;
+  }
   if (by_rows) {
     *gbase = g->lg_ptr;
     *cap0 = row0;
-    if ((rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16)) != MOCHY_OK ||
-        (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8)) != MOCHY_OK)
-      return fail(rc);
     if (c1 > c0)
       k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                 cntarr, g->lg_ptr, row0, *grec, *gcnt,
