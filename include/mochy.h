@@ -42,9 +42,25 @@ typedef enum {
   MOCHY_EUNSUPPORTED = -6 /* valid request the library does not handle (message says why) */
 } mochy_status;
 
-#define MOCHY_MAX_EDGE 32   /* nodes per hyperedge: the per-centre region masks are 32-bit */
+/* Nodes per hyperedge.  Section 2.1 allows any non-empty node set; this
+ * library keeps one 32-bit mask of a centre's nodes per line-graph neighbour
+ * (16-byte region records), so it accepts hyperedges of at most 32 nodes and
+ * answers MOCHY_ERANGE above that.  A stated deviation: the paper's datasets
+ * have at most 25 nodes per hyperedge (Table 2), and a 64-bit mask would
+ * widen every record and every per-pair mask operation of the hot kernels. */
+#define MOCHY_MAX_EDGE 32
 #define MOCHY_NUM_H 26
 #define MOCHY_NUM_3H 431
+
+/* `which` selector of the counting calls: the h-motif outputs (26 classes,
+ * section 2.2), the 3h-motif outputs (431 classes, section 5.1), or both.
+ * The device always classifies a triple into its 3h-motif (its h-motif is
+ * that 3h-motif's parent), so `which` selects outputs, not work.  Outputs of
+ * a kind not selected are never written; an output of a selected kind may be
+ * NULL if it is not wanted.  MOCHY_EINVAL if `which` is 0 or has other bits. */
+#define MOCHY_H26 1u
+#define MOCHY_H431 2u
+#define MOCHY_WHICH_ALL (MOCHY_H26 | MOCHY_H431)
 
 typedef struct mochy_ctx mochy_ctx;      /* device, stream, pattern tables, error text */
 typedef struct mochy_graph mochy_graph;  /* device-resident incidence, its transpose and
@@ -66,6 +82,10 @@ typedef struct {
 /* mochy_project flags */
 #define MOCHY_DEDUP 1u    /* host input only: drop repeated hyperedges, keeping the first;
                              later ids shift down */
+#define MOCHY_CANONICALIZE 2u  /* host input only: sort each hyperedge's node list and
+                                  drop repeated nodes (a hyperedge is a node set,
+                                  section 2.1) before validation; a list that still
+                                  holds more than MOCHY_MAX_EDGE nodes is MOCHY_ERANGE */
 #define MOCHY_LG_FREE 4u  /* do not store the line graph (section 4.4's on-the-fly
                              neighbourhoods); implied above 200000 hyperedges */
 
@@ -121,6 +141,10 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                     (this context's only: several contexts on one device
                                     should share the memory by their limits);
                                     mochy_ctx_destroy frees them; same results */
+#define MOCHY_OPT_TEST_FAULTS 10  /* for tests of the fallbacks: bit 0 makes the one-pass
+                                     grouping's row-capacity allocation report
+                                     MOCHY_ENOMEM, so exact counting takes the
+                                     counted-first layout (default 0); same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
@@ -142,9 +166,12 @@ mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* g, uint32_t flags,
 void mochy_graph_free(mochy_graph* g);
 
 /* Exact counts (MoCHy-E, Algorithm 2): every connected triple of distinct
- * hyperedges counted once in its h-motif and its 3h-motif.  counts26 (host,
- * 26 int64) and counts431 (host, 431 int64) may each be NULL if not wanted. */
-mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g,
+ * hyperedges counted once in its h-motif and its 3h-motif.  which: MOCHY_H26,
+ * MOCHY_H431 or both; counts26 (host, 26 int64) and counts431 (host, 431
+ * int64) receive the selected kinds (each may be NULL if not wanted).
+ * Errors: MOCHY_EINVAL (bad graph or which), MOCHY_EUNSUPPORTED (graph
+ * projected without its line graph), MOCHY_ENOMEM, MOCHY_EDEVICE. */
+mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g, uint32_t which,
                                int64_t* counts26, int64_t* counts431);
 
 /* The same, restricted to the instances Algorithm 2 attributes to centres
@@ -152,7 +179,7 @@ mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g,
  * middle hyperedge, a closed one to its smallest index).  Summing disjoint
  * ranges that cover [0, num_edges) gives mochy_count_exact. */
 mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_graph* g,
-                                     int64_t center_begin, int64_t center_end,
+                                     int64_t center_begin, int64_t center_end, uint32_t which,
                                      int64_t* counts26, int64_t* counts431);
 
 /* MoCHy-A+ (Algorithm 5): samples n = sample_begin .. sample_begin+r-1 each
@@ -163,10 +190,12 @@ mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_graph* g,
  * e_k in N_i ∪ N_j minus {e_i, e_j} adds one hit to its motif.  raw26/raw431
  * (host int64) receive the hits; est26/est431 (host double) the unbiased
  * estimates raw * |wedges| / (w * r), w = 2 for open and 3 for closed motifs
- * (w of a 3h-motif is its h-motif's).  Any output pointer may be NULL.
- * r must be > 0; a graph with no hyperwedge gives zeros. */
+ * (w of a 3h-motif is its h-motif's).  which selects the kinds written
+ * (raw26/est26 are MOCHY_H26, raw431/est431 MOCHY_H431); any output pointer
+ * of a selected kind may be NULL.  r must be > 0; a graph with no hyperwedge
+ * gives zeros. */
 mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r,
-                                 uint64_t seed, int64_t sample_begin,
+                                 uint64_t seed, int64_t sample_begin, uint32_t which,
                                  int64_t* raw26, double* est26,
                                  int64_t* raw431, double* est431);
 
@@ -198,15 +227,21 @@ mochy_status mochy_hyperedge_profiles(mochy_ctx* ctx, const mochy_graph* g, int6
 
 /* Significance and characteristic profile against randomized copies
  * (section 3.1).  graphs[0] is the hypergraph, graphs[1..num_graphs-1] its
- * randomized copies (host or device CSRs; the caller draws them).  All graphs
- * are projected and counted exactly on the device.  Outputs (host): counts
- * (num_graphs x 457 int64: per graph 26 h-motif then 431 3h-motif counts),
- * sig26/cp26 (26 doubles) and sig431/cp431 (431 doubles), each may be NULL.
+ * randomized copies (host or device CSRs, each of at most 200000
+ * hyperedges).  All graphs are projected and counted exactly on the device,
+ * as one batch.  Outputs (host): counts (num_graphs x 457 int64: per graph
+ * 26 h-motif then 431 3h-motif counts; the columns of a kind not selected by
+ * `which` are left untouched), sig26/cp26 (26 doubles, MOCHY_H26) and
+ * sig431/cp431 (431 doubles, MOCHY_H431), each may be NULL.
  *   Delta_t = (M[t] - Mr[t]) / (M[t] + Mr[t] + eps),  Mr = mean over copies;
  *   CP_t    = Delta_t / sqrt(sum_t Delta_t^2)    (0 for all t if every Delta is 0).
- * num_graphs >= 2. */
+ * num_graphs >= 2.
+ * Deviation from a (num_random, seeds) signature: the caller draws the
+ * copies and passes them in, so the null model (stub matching with exact
+ * degrees and sizes, or the paper's Chung-Lu randomizer of Algorithms 6-7)
+ * stays the caller's choice and its random numbers stay outside the library. */
 mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,
-                           double eps, int64_t* counts,
+                           double eps, uint32_t which, int64_t* counts,
                            double* sig26, double* cp26, double* sig431, double* cp431);
 
 /* Region pattern of a motif id: states[r] for regions R1..R7 of section 2.2
@@ -240,6 +275,31 @@ mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* ou
  * ms: host, MOCHY_NUM_PHASES doubles. */
 #define MOCHY_NUM_PHASES 11
 mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);
+
+/* What the most recent exact counting call (mochy_count_exact, _range, or
+ * the exact counts of mochy_profile) did, summed over its graphs:
+ * out[0] rows grouped, out[1] neighbour groups, out[2] groups with a member
+ * above the centre, out[3] pairs of groups that both have a member above the
+ * centre (classified in full), out[4] other pairs of groups (counted only
+ * when open), out[5] rows regrouped with more hash parts than first
+ * guessed, out[6] most hash parts of one row, out[7] hyperedge pairs sharing
+ * a light node (the correction's pairs), out[8] row entries the correction
+ * scanned, out[9] common neighbours it examined (centres of a light pair),
+ * out[10] of those, the centres whose class it changed.  Zeros for parts a
+ * call did not run (out[0..6] when every neighbour was paired).
+ * out: host, MOCHY_NUM_EXACT_STATS int64. */
+#define MOCHY_NUM_EXACT_STATS 11
+mochy_status mochy_exact_stats(const mochy_ctx* ctx, int64_t* out);
+
+/* Measurement helper (not part of the method): the integer vector-ALU rate
+ * the device sustains.  One timed launch of 32 waves per compute unit, every
+ * lane running `iters` rounds of 32 32-bit integer vector instructions of
+ * the exact pair kernel's mix (and, or, xor, population count, add, subtract,
+ * min, 24-bit multiply-add) over independent chains.  *ms (host) receives
+ * the launch's duration from HIP events on the context stream, *lane_ops
+ * (host) the lane-operations it executed (threads x iters x 32).
+ * iters in [1, 2^32], else MOCHY_EINVAL. */
+mochy_status mochy_calibrate_valu(mochy_ctx* ctx, int64_t iters, double* ms, int64_t* lane_ops);
 
 /* What the key memos of the most recent on-the-fly MoCHy-A+ call did
  * (Algorithm 9 with a memo budget, MOCHY_OPT_MEMO_BUDGET): out[0] samples,

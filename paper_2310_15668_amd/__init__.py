@@ -10,6 +10,8 @@ from ._lib import (  # noqa: F401
     mochy_count_sampled, mochy_count_sampled_edges, mochy_hyperedge_profiles, mochy_profile, motif_pattern, parent_motif, NUM_H, NUM_3H, MOCHY_DEDUP,
     MOCHY_LG_FREE, MOCHY_OPT_GROUPS, MOCHY_OPT_APLUS_ROWS, MOCHY_OPT_MEMO_BUDGET, MOCHY_OPT_MEMO_ALL,
     MOCHY_OPT_MEMO_POOL, MOCHY_OPT_GROUP_CAPACITY, MOCHY_OPT_BATCH_LAUNCH, MOCHY_OPT_PAIR_BLOCKS,
-    MOCHY_OPT_CACHE_BYTES,
-    mochy_graph_stats, mochy_phase_ms, mochy_memo_stats,
+    MOCHY_OPT_CACHE_BYTES, MOCHY_OPT_TEST_FAULTS, MOCHY_CANONICALIZE, MOCHY_H26, MOCHY_H431,
+    MOCHY_WHICH_ALL,
+    mochy_graph_stats, mochy_phase_ms, mochy_memo_stats, mochy_exact_stats,
+    mochy_calibrate_valu,
 )

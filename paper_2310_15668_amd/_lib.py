@@ -19,7 +19,11 @@ MOCHY_OK = 0
 STATUS = {0: "MOCHY_OK", -1: "MOCHY_EINVAL", -2: "MOCHY_EDUP", -3: "MOCHY_ERANGE",
           -4: "MOCHY_ENOMEM", -5: "MOCHY_EDEVICE", -6: "MOCHY_EUNSUPPORTED"}
 MOCHY_DEDUP = 1
+MOCHY_CANONICALIZE = 2
 MOCHY_LG_FREE = 4
+MOCHY_H26 = 1
+MOCHY_H431 = 2
+MOCHY_WHICH_ALL = 3
 MOCHY_OPT_GROUPS = 1
 MOCHY_OPT_APLUS_ROWS = 2
 MOCHY_OPT_MEMO_BUDGET = 3
@@ -29,6 +33,7 @@ MOCHY_OPT_GROUP_CAPACITY = 6
 MOCHY_OPT_BATCH_LAUNCH = 7
 MOCHY_OPT_PAIR_BLOCKS = 8
 MOCHY_OPT_CACHE_BYTES = 9
+MOCHY_OPT_TEST_FAULTS = 10
 NUM_H, NUM_3H = 26, 431
 MAX_EDGE = 32
 
@@ -37,7 +42,12 @@ EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_
             "mochy_graph_free", "mochy_count_exact", "mochy_count_exact_range",
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
             "mochy_graph_stats", "mochy_phase_ms", "mochy_memo_stats", "mochy_ctx_set_option",
-            "mochy_count_sampled_edges", "mochy_hyperedge_profiles")
+            "mochy_count_sampled_edges", "mochy_hyperedge_profiles", "mochy_exact_stats",
+            "mochy_calibrate_valu")
+NUM_EXACT_STATS = 11
+EXACT_STATS = ("rows_grouped", "groups", "groups_above", "group_pairs_full", "group_pairs_open",
+               "rows_regrouped", "max_hash_parts", "light_pairs", "fix_scanned", "fix_centres",
+               "fix_changed")
 NUM_PHASES = 11
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
           "exact_correct", "sample_draw", "sample_enum", "profile_cp")
@@ -86,13 +96,13 @@ def lib():
     L.mochy_project.restype = ctypes.c_int
     L.mochy_graph_free.argtypes = [vp]
     L.mochy_graph_free.restype = None
-    L.mochy_count_exact.argtypes = [vp, vp, vp, vp]
+    L.mochy_count_exact.argtypes = [vp, vp, u32, vp, vp]
     L.mochy_count_exact.restype = ctypes.c_int
-    L.mochy_count_exact_range.argtypes = [vp, vp, i64, i64, vp, vp]
+    L.mochy_count_exact_range.argtypes = [vp, vp, i64, i64, u32, vp, vp]
     L.mochy_count_exact_range.restype = ctypes.c_int
-    L.mochy_count_sampled.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
+    L.mochy_count_sampled.argtypes = [vp, vp, i64, u64, i64, u32, vp, vp, vp, vp]
     L.mochy_count_sampled.restype = ctypes.c_int
-    L.mochy_profile.argtypes = [vp, i32, ctypes.POINTER(CSR), ctypes.c_double, vp, vp, vp, vp, vp]
+    L.mochy_profile.argtypes = [vp, i32, ctypes.POINTER(CSR), ctypes.c_double, u32, vp, vp, vp, vp, vp]
     L.mochy_profile.restype = ctypes.c_int
     L.mochy_motif_pattern.argtypes = [i32, u32, ctypes.POINTER(ctypes.c_uint8)]
     L.mochy_motif_pattern.restype = ctypes.c_int
@@ -104,6 +114,10 @@ def lib():
     L.mochy_phase_ms.restype = ctypes.c_int
     L.mochy_memo_stats.argtypes = [vp, vp]
     L.mochy_memo_stats.restype = ctypes.c_int
+    L.mochy_exact_stats.argtypes = [vp, vp]
+    L.mochy_exact_stats.restype = ctypes.c_int
+    L.mochy_calibrate_valu.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.mochy_calibrate_valu.restype = ctypes.c_int
     L.mochy_count_sampled_edges.argtypes = [vp, vp, i64, u64, i64, vp, vp, vp, vp]
     L.mochy_count_sampled_edges.restype = ctypes.c_int
     L.mochy_hyperedge_profiles.argtypes = [vp, vp, i64, i64, vp, vp]
@@ -220,29 +234,37 @@ def mochy_project(ctx, edge_ptr, edge_nodes, num_nodes, flags=0) -> Graph:
     return Graph(ctx, edge_ptr, edge_nodes, num_nodes, flags)
 
 
-def mochy_count_exact(ctx: Context, g: Graph):
-    c26 = np.zeros(NUM_H, dtype=np.int64)
-    c431 = np.zeros(NUM_3H, dtype=np.int64)
-    ctx.check(lib().mochy_count_exact(ctx.handle, g.handle, _ptr(c26), _ptr(c431)), "mochy_count_exact")
+def _outs(which, n, dtype):
+    """An output array for a selected kind, None for one not selected."""
+    return np.zeros(n, dtype=dtype) if which else None
+
+
+def mochy_count_exact(ctx: Context, g: Graph, which: int = MOCHY_WHICH_ALL):
+    """(counts26, counts431); an entry is None when ``which`` does not select it."""
+    c26 = _outs(which & MOCHY_H26, NUM_H, np.int64)
+    c431 = _outs(which & MOCHY_H431, NUM_3H, np.int64)
+    ctx.check(lib().mochy_count_exact(ctx.handle, g.handle, int(which), _ptr(c26), _ptr(c431)),
+              "mochy_count_exact")
     return c26, c431
 
 
-def mochy_count_exact_range(ctx: Context, g: Graph, c0: int, c1: int):
-    c26 = np.zeros(NUM_H, dtype=np.int64)
-    c431 = np.zeros(NUM_3H, dtype=np.int64)
-    ctx.check(lib().mochy_count_exact_range(ctx.handle, g.handle, int(c0), int(c1), _ptr(c26), _ptr(c431)),
-              "mochy_count_exact_range")
+def mochy_count_exact_range(ctx: Context, g: Graph, c0: int, c1: int, which: int = MOCHY_WHICH_ALL):
+    c26 = _outs(which & MOCHY_H26, NUM_H, np.int64)
+    c431 = _outs(which & MOCHY_H431, NUM_3H, np.int64)
+    ctx.check(lib().mochy_count_exact_range(ctx.handle, g.handle, int(c0), int(c1), int(which), _ptr(c26),
+                                            _ptr(c431)), "mochy_count_exact_range")
     return c26, c431
 
 
-def mochy_count_sampled(ctx: Context, g: Graph, r: int, seed: int, sample_begin: int = 0):
-    raw26 = np.zeros(NUM_H, dtype=np.int64)
-    est26 = np.zeros(NUM_H, dtype=np.float64)
-    raw431 = np.zeros(NUM_3H, dtype=np.int64)
-    est431 = np.zeros(NUM_3H, dtype=np.float64)
+def mochy_count_sampled(ctx: Context, g: Graph, r: int, seed: int, sample_begin: int = 0,
+                        which: int = MOCHY_WHICH_ALL):
+    raw26 = _outs(which & MOCHY_H26, NUM_H, np.int64)
+    est26 = _outs(which & MOCHY_H26, NUM_H, np.float64)
+    raw431 = _outs(which & MOCHY_H431, NUM_3H, np.int64)
+    est431 = _outs(which & MOCHY_H431, NUM_3H, np.float64)
     ctx.check(lib().mochy_count_sampled(ctx.handle, g.handle, int(r), ctypes.c_uint64(seed & (2 ** 64 - 1)),
-                                        int(sample_begin), _ptr(raw26), _ptr(est26), _ptr(raw431),
-                                        _ptr(est431)), "mochy_count_sampled")
+                                        int(sample_begin), int(which), _ptr(raw26), _ptr(est26),
+                                        _ptr(raw431), _ptr(est431)), "mochy_count_sampled")
     return raw26, est26, raw431, est431
 
 
@@ -271,15 +293,18 @@ def mochy_hyperedge_profiles(ctx: Context, g: Graph, e_begin: int = 0, e_end: in
     return hp26, hp431
 
 
-def mochy_profile(ctx: Context, graphs, eps: float = 1.0):
-    """graphs: list of (edge_ptr, edge_nodes, num_nodes); graphs[0] is the hypergraph."""
+def mochy_profile(ctx: Context, graphs, eps: float = 1.0, which: int = MOCHY_WHICH_ALL):
+    """graphs: list of (edge_ptr, edge_nodes, num_nodes); graphs[0] is the hypergraph.
+    Returns (counts [n, 457], sig26, cp26, sig431, cp431); the significance and
+    CP of a kind ``which`` does not select are None and its count columns 0."""
     keep = []
     arr = (CSR * len(graphs))(*[make_csr(p, n, v, keep) for (p, n, v) in graphs])
     counts = np.zeros((len(graphs), NUM_H + NUM_3H), dtype=np.int64)
-    sig26, cp26 = np.zeros(NUM_H), np.zeros(NUM_H)
-    sig431, cp431 = np.zeros(NUM_3H), np.zeros(NUM_3H)
-    ctx.check(lib().mochy_profile(ctx.handle, len(graphs), arr, float(eps), _ptr(counts), _ptr(sig26),
-                                  _ptr(cp26), _ptr(sig431), _ptr(cp431)), "mochy_profile")
+    sig26, cp26 = _outs(which & MOCHY_H26, NUM_H, np.float64), _outs(which & MOCHY_H26, NUM_H, np.float64)
+    sig431 = _outs(which & MOCHY_H431, NUM_3H, np.float64)
+    cp431 = _outs(which & MOCHY_H431, NUM_3H, np.float64)
+    ctx.check(lib().mochy_profile(ctx.handle, len(graphs), arr, float(eps), int(which), _ptr(counts),
+                                  _ptr(sig26), _ptr(cp26), _ptr(sig431), _ptr(cp431)), "mochy_profile")
     return counts, sig26, cp26, sig431, cp431
 
 
@@ -289,6 +314,22 @@ def mochy_graph_stats(ctx: Context, g: Graph) -> dict:
     keys = ("num_edges", "num_nodes", "nnz", "hyperwedges", "max_line_degree", "candidates",
             "candidate_min_size_sum", "sum_deg_sq")
     return {k: int(v) for k, v in zip(keys, out)}
+
+
+def mochy_exact_stats(ctx: Context) -> dict:
+    """What the last exact counting call did (groups, group pairs, correction work)."""
+    out = np.zeros(NUM_EXACT_STATS, dtype=np.int64)
+    ctx.check(lib().mochy_exact_stats(ctx.handle, _ptr(out)), "mochy_exact_stats")
+    return {k: int(v) for k, v in zip(EXACT_STATS, out)}
+
+
+def mochy_calibrate_valu(ctx: Context, iters: int) -> tuple:
+    """(milliseconds, lane operations) of the integer VALU calibration launch."""
+    ms = ctypes.c_double()
+    ops = ctypes.c_int64()
+    ctx.check(lib().mochy_calibrate_valu(ctx.handle, int(iters), ctypes.byref(ms), ctypes.byref(ops)),
+              "mochy_calibrate_valu")
+    return float(ms.value), int(ops.value)
 
 
 def mochy_memo_stats(ctx: Context) -> dict:

@@ -211,6 +211,12 @@ extern "C" mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms) {
   return MOCHY_OK;
 }
 
+extern "C" mochy_status mochy_exact_stats(const mochy_ctx* ctx, int64_t* out) {
+  if (!ctx || !out) return MOCHY_EINVAL;
+  std::memcpy(out, ctx->exact_stats, sizeof(ctx->exact_stats));
+  return MOCHY_OK;
+}
+
 extern "C" mochy_status mochy_memo_stats(const mochy_ctx* ctx, int64_t* out) {
   if (!ctx || !out) return MOCHY_EINVAL;
   std::memcpy(out, ctx->memo_stats, sizeof(ctx->memo_stats));
@@ -327,7 +333,7 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   if (ctx_alloc(ctx, (void**)&ctx->d_code_to_id3, sizeof(pt.code_to_id3)) != MOCHY_OK ||
       ctx_alloc(ctx, (void**)&ctx->d_id3_to_id26, sizeof(parent)) != MOCHY_OK ||
       ctx_alloc(ctx, (void**)&ctx->d_flags, 16 * sizeof(int32_t)) != MOCHY_OK ||
-      ctx_alloc(ctx, (void**)&ctx->d_small, 512 * sizeof(int64_t)) != MOCHY_OK ||
+      ctx_alloc(ctx, (void**)&ctx->d_small, kSmallSlots * sizeof(int64_t)) != MOCHY_OK ||
       ctx_alloc(ctx, (void**)&ctx->d_open26, 27 * sizeof(int32_t)) != MOCHY_OK ||
       ctx_alloc(ctx, (void**)&ctx->d_dbl, 512 * sizeof(double)) != MOCHY_OK)
     return fail(MOCHY_ENOMEM);
@@ -337,7 +343,7 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   (void)hipGetLastError();
   if (hipHostMalloc((void**)&ctx->h_dbl, 512 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
-  if (hipHostMalloc((void**)&ctx->h_small, 512 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+  if (hipHostMalloc((void**)&ctx->h_small, kSmallSlots * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
     return fail(MOCHY_ENOMEM);
   for (auto& e : ctx->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(MOCHY_EDEVICE);
@@ -411,6 +417,10 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     if (ctx->cache_bytes > value) cache_release(ctx);
     return MOCHY_OK;
   }
+  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 1) {
+    ctx->test_faults = int(value);
+    return MOCHY_OK;
+  }
   ctx->err = "unknown option or value";
   return MOCHY_EINVAL;
 }
@@ -464,6 +474,10 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
     ctx->err = "num_nodes / num_edges out of range";
     return MOCHY_EINVAL;
   }
+  if (flags & ~(MOCHY_DEDUP | MOCHY_CANONICALIZE | MOCHY_LG_FREE)) {
+    ctx->err = "unknown mochy_project flag";
+    return MOCHY_EINVAL;
+  }
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   mochy_graph* g = new (std::nothrow) mochy_graph();
@@ -475,9 +489,36 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
   mochy_status rc;
   phase_begin(ctx, kPhUpload);
   if (!c->on_device) {
-    if ((rc = check_host_csr(ctx, c)) != MOCHY_OK) return fail(rc);
     const int64_t* ptr = c->edge_ptr;
     const int32_t* nodes = c->edge_nodes;
+    std::vector<int64_t> cptr;
+    std::vector<int32_t> cnodes;
+    if (flags & MOCHY_CANONICALIZE) {
+      // each hyperedge as a node set: its list sorted, repeated nodes dropped
+      if (g->E > 0 && (!ptr || ptr[0] != 0 || (ptr[g->E] > 0 && !nodes))) {
+        ctx->err = "edge_ptr must start at 0 and the CSR pointers be non-null";
+        return fail(MOCHY_EINVAL);
+      }
+      cptr.assign(1, 0);
+      std::vector<int32_t> row;
+      for (int64_t e = 0; e < g->E; ++e) {
+        if (ptr[e + 1] < ptr[e]) {
+          ctx->err = "decreasing edge_ptr at edge " + std::to_string(e);
+          return fail(MOCHY_EINVAL);
+        }
+        row.assign(nodes + ptr[e], nodes + ptr[e + 1]);
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
+        cnodes.insert(cnodes.end(), row.begin(), row.end());
+        cptr.push_back(int64_t(cnodes.size()));
+      }
+      ptr = cptr.data();
+      nodes = cnodes.data();
+    }
+    mochy_csr chk = *c;
+    chk.edge_ptr = ptr;
+    chk.edge_nodes = nodes;
+    if ((rc = check_host_csr(ctx, &chk)) != MOCHY_OK) return fail(rc);
     std::vector<int64_t> dptr;
     std::vector<int32_t> dnodes;
     if (flags & MOCHY_DEDUP) {
@@ -505,7 +546,10 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
     }
     MOCHY_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
   } else {
-    if (flags & MOCHY_DEDUP) { ctx->err = "MOCHY_DEDUP needs host input"; return fail(MOCHY_EINVAL); }
+    if (flags & (MOCHY_DEDUP | MOCHY_CANONICALIZE)) {
+      ctx->err = "MOCHY_DEDUP and MOCHY_CANONICALIZE need host input";
+      return fail(MOCHY_EINVAL);
+    }
     int64_t ends[2] = {0, 0};
     if (g->E) {
       MOCHY_HIP(hipMemcpyAsync(&ends[0], c->edge_ptr, 8, hipMemcpyDeviceToHost, st));
@@ -534,7 +578,15 @@ extern "C" mochy_status mochy_project(mochy_ctx* ctx, const mochy_csr* c, uint32
   return MOCHY_OK;
 }
 
-static mochy_status finish_counts(mochy_ctx* ctx, int64_t* d_hist, int64_t* counts26,
+static bool which_ok(mochy_ctx* ctx, uint32_t which) {
+  if (which == 0u || (which & ~MOCHY_WHICH_ALL) != 0u) {
+    ctx->err = "which must select MOCHY_H26, MOCHY_H431 or both";
+    return false;
+  }
+  return true;
+}
+
+static mochy_status finish_counts(mochy_ctx* ctx, int64_t* d_hist, uint32_t which, int64_t* counts26,
                                   int64_t* counts431) {
   hipStream_t st = ctx->stream;
   int64_t* d_out26 = ctx->d_small;  // [26]
@@ -546,21 +598,23 @@ static mochy_status finish_counts(mochy_ctx* ctx, int64_t* d_hist, int64_t* coun
     ctx->err = "internal error: " + std::to_string(ctx->h_small[0]) + " triples with an invalid pattern";
     return MOCHY_EDEVICE;
   }
-  if (counts431) std::memcpy(counts431, ctx->h_small + 1, MOCHY_NUM_3H * 8);
-  if (counts26) std::memcpy(counts26, ctx->h_small + kHistSlots, MOCHY_NUM_H * 8);
+  if (counts431 && (which & MOCHY_H431)) std::memcpy(counts431, ctx->h_small + 1, MOCHY_NUM_3H * 8);
+  if (counts26 && (which & MOCHY_H26)) std::memcpy(counts26, ctx->h_small + kHistSlots, MOCHY_NUM_H * 8);
   return MOCHY_OK;
 }
 
 extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_graph* g,
-                                                int64_t c0, int64_t c1, int64_t* counts26,
-                                                int64_t* counts431) {
+                                                int64_t c0, int64_t c1, uint32_t which,
+                                                int64_t* counts26, int64_t* counts431) {
   if (!ctx) return MOCHY_EINVAL;
   ctx->err.clear();
   phases_reset(ctx);
+  for (int64_t& v : ctx->exact_stats) v = 0;
   if (!g || g->ctx != ctx || c0 < 0 || c1 < c0 || c1 > g->E) {
     ctx->err = "bad graph or centre range";
     return MOCHY_EINVAL;
   }
+  if (!which_ok(ctx, which)) return MOCHY_EINVAL;
   if (g->lg_free) {
     ctx->err = "exact counting walks stored line-graph rows; this graph was projected without "
                "them (MOCHY_LG_FREE or more than 200000 hyperedges): use mochy_count_sampled";
@@ -570,16 +624,16 @@ extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_grap
   int64_t* d_hist = ctx->d_small + 64;  // [432]
   mochy_status rc = exact_device(ctx, g, c0, c1, d_hist);
   if (rc != MOCHY_OK) return rc;
-  return finish_counts(ctx, d_hist, counts26, counts431);
+  return finish_counts(ctx, d_hist, which, counts26, counts431);
 }
 
-extern "C" mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g, int64_t* counts26,
-                                          int64_t* counts431) {
+extern "C" mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g, uint32_t which,
+                                          int64_t* counts26, int64_t* counts431) {
   if (!g) {
     if (ctx) ctx->err = "null graph";
     return MOCHY_EINVAL;
   }
-  return mochy_count_exact_range(ctx, g, 0, g->E, counts26, counts431);
+  return mochy_count_exact_range(ctx, g, 0, g->E, which, counts26, counts431);
 }
 
 extern "C" mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* out) {
@@ -698,8 +752,9 @@ extern "C" mochy_status mochy_hyperedge_profiles(mochy_ctx* ctx, const mochy_gra
 }
 
 extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g, int64_t r,
-                                            uint64_t seed, int64_t sample_begin, int64_t* raw26,
-                                            double* est26, int64_t* raw431, double* est431) {
+                                            uint64_t seed, int64_t sample_begin, uint32_t which,
+                                            int64_t* raw26, double* est26, int64_t* raw431,
+                                            double* est431) {
   if (!ctx) return MOCHY_EINVAL;
   ctx->err.clear();
   phases_reset(ctx);
@@ -707,6 +762,9 @@ extern "C" mochy_status mochy_count_sampled(mochy_ctx* ctx, const mochy_graph* g
     ctx->err = "bad graph, sample count or sample range";
     return MOCHY_EINVAL;
   }
+  if (!which_ok(ctx, which)) return MOCHY_EINVAL;
+  if (!(which & MOCHY_H26)) raw26 = nullptr, est26 = nullptr;
+  if (!(which & MOCHY_H431)) raw431 = nullptr, est431 = nullptr;
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   int64_t* d_hist = ctx->d_small + 64;
@@ -833,15 +891,19 @@ static mochy_status profile_counts(mochy_ctx* ctx, const mochy_csr* graphs, int3
 }
 
 extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,
-                                      double eps, int64_t* counts, double* sig26, double* cp26,
-                                      double* sig431, double* cp431) {
+                                      double eps, uint32_t which, int64_t* counts, double* sig26,
+                                      double* cp26, double* sig431, double* cp431) {
   if (!ctx) return MOCHY_EINVAL;
   ctx->err.clear();
   phases_reset(ctx);
+  for (int64_t& v : ctx->exact_stats) v = 0;
   if (num_graphs < 2 || !graphs || !(eps >= 0.0)) {
     ctx->err = "need the hypergraph and at least one randomized copy, and eps >= 0";
     return MOCHY_EINVAL;
   }
+  if (!which_ok(ctx, which)) return MOCHY_EINVAL;
+  if (!(which & MOCHY_H26)) sig26 = nullptr, cp26 = nullptr;
+  if (!(which & MOCHY_H431)) sig431 = nullptr, cp431 = nullptr;
   MOCHY_HIP(hipSetDevice(ctx->device));
   hipStream_t st = ctx->stream;
   const size_t per = MOCHY_NUM_H + MOCHY_NUM_3H;
@@ -877,7 +939,14 @@ extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const 
       ctx->err = "internal error: invalid pattern counted in graph " + std::to_string(x);
       return MOCHY_EDEVICE;
     }
-  if (counts) std::memcpy(counts, hc.data(), hc.size() * 8);
+  if (counts) {
+    for (int32_t x = 0; x < num_graphs; ++x) {
+      const int64_t* src = hc.data() + size_t(x) * per;
+      int64_t* dst = counts + size_t(x) * per;
+      if (which & MOCHY_H26) std::memcpy(dst, src, MOCHY_NUM_H * 8);
+      if (which & MOCHY_H431) std::memcpy(dst + MOCHY_NUM_H, src + MOCHY_NUM_H, MOCHY_NUM_3H * 8);
+    }
+  }
   if (sig26) std::memcpy(sig26, ho.data(), MOCHY_NUM_H * 8);
   if (cp26) std::memcpy(cp26, ho.data() + MOCHY_NUM_H, MOCHY_NUM_H * 8);
   if (sig431) std::memcpy(sig431, ho.data() + 2 * MOCHY_NUM_H, MOCHY_NUM_3H * 8);

@@ -41,6 +41,7 @@ struct mochy_ctx {
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
   int batch_launch = 0;               // pair kernel over a batch: 0 size rule, 1 one launch, 2 per graph
   int pair_blocks = 8;                // pair kernel blocks launched per CU (MOCHY_OPT_PAIR_BLOCKS)
+  int test_faults = 0;                // MOCHY_OPT_TEST_FAULTS bits (forced fallbacks)
   // freed transient buffers of at least kCacheMinBytes kept for reuse on this
   // context's stream (MOCHY_OPT_CACHE_BYTES): size -> block, and the size of
   // every block handed out from or destined for the cache
@@ -53,8 +54,8 @@ struct mochy_ctx {
   uint16_t* d_code_to_id3 = nullptr;  // [kNumCodes]
   int32_t* d_id3_to_id26 = nullptr;   // [kHistSlots]
   int32_t* d_flags = nullptr;         // device error flags (bit set by validation kernels)
-  int64_t* d_small = nullptr;         // small pinned-size scratch for readbacks
-  int64_t* h_small = nullptr;         // pinned host mirror
+  int64_t* d_small = nullptr;         // [kSmallSlots] small scratch for readbacks
+  int64_t* h_small = nullptr;         // [kSmallSlots] pinned host mirror
   int32_t* d_open26 = nullptr;        // [27]: 1 if the h-motif is open
   double* d_dbl = nullptr;            // [512] double outputs
   double* h_dbl = nullptr;            // pinned host mirror
@@ -66,7 +67,17 @@ struct mochy_ctx {
   // memos, keys memoized, most arena bytes one chunk used, list entries the
   // memo builds walked
   int64_t memo_stats[5] = {};
+  // last exact counting call (mochy_exact_stats), summed over its passes
+  int64_t exact_stats[MOCHY_NUM_EXACT_STATS] = {};
 };
+
+// Layout of ctx->d_small / h_small (int64 slots): 0..63 small outputs,
+// 64..495 a histogram of kHistSlots, 500..511 readbacks of single values,
+// kExactStatsSlot.. the device counters of mochy_exact_stats.
+constexpr int kSmallSlots = 1024;
+constexpr int kExactStatsSlot = 512;
+enum ExactStat { kStRows = 0, kStGroups, kStGroupsAbove, kStPairsFull, kStPairsOpen, kStRegrouped,
+                 kStMaxParts, kStLightPairs, kStFixScanned, kStFixCentres, kStFixChanged };
 
 // Phase timing: bracket device work on the context stream.
 enum Phase { kPhUpload = 0, kPhTranspose, kPhDegree, kPhRows, kPhRecords, kPhSched, kPhPairs,
@@ -150,6 +161,17 @@ constexpr int kFlagInval = 1, kFlagRange = 2, kFlagDup = 4;
     }                                                                          \
   } while (0)
 
+// The same for code that holds buffers: `handler` (a callable taking and
+// returning a mochy_status) releases them and gives the status back.
+#define MOCHY_HIP_OR(call, handler)                                            \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+      return handler(MOCHY_EDEVICE);                                           \
+    }                                                                          \
+  } while (0)
+
 // scan.hip
 void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp,
                                hipStream_t s);
@@ -184,7 +206,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
 
 // correct.hip: exact fix-up of pairs that share a light node outside the centre
 mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
-                            int64_t* d_hist);
+                            int64_t* d_hist, unsigned long long* stats);
 
 // sampled.hip: MoCHy-A+ (hyperwedges) and MoCHy-A (hyperedges)
 mochy_status sampled_device(mochy_ctx* ctx, const mochy_graph* g, int64_t r, uint64_t seed,

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
     const uint32_t* __restrict__ esize, const uint16_t* __restrict__ code_to_id3,
-    unsigned long long* hist_out) {
+    unsigned long long* hist_out, unsigned long long* stats) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
   // kFixCopies histogram copies, lane l adding to copy l % kFixCopies (fewer
@@ -173,6 +173,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   // no lanes idle)
   const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
   unsigned long long* myhist = hist + (lane & (kFixCopies - 1)) * kHistSlots;
+  uint32_t n_centres = 0, n_changed = 0;  // this wave's, for mochy_exact_stats
   for (int64_t pp = poff[ob] + wave; pp < poff[ob + 1]; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
     // record of e_k in row j
@@ -220,9 +221,12 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
+        // wave-uniform tallies (a ballot counts the lanes still scanning)
+        n_centres += uint32_t(__popcll(__ballot(hit[u])));
         if (!hit[u]) continue;
         const int32_t i = iv[u];
         const uint32_t ls = __popc(mjk & L & ~mji[u]);
+        n_changed += uint32_t(__popcll(__ballot(ls != 0u)));
         if (ls == 0u) continue;  // the pair kernel was exact at this centre
         const uint32_t wik = __popc(mik[u]);
         const uint32_t t = __popc(mji[u] & mjk);
@@ -238,12 +242,30 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
       }
     }
   }
+  if (lane == 0) {
+    atomicAdd(&stats[kStFixCentres], (unsigned long long)n_centres);
+    atomicAdd(&stats[kStFixChanged], (unsigned long long)n_changed);
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) {
     unsigned long long v = 0;
     for (int c = 0; c < kFixCopies; ++c) v += hist[c * kHistSlots + t];
     if (v) atomicAdd(&hist_out[int64_t(gj) * kHistSlots + t], v);
   }
+}
+
+// Row entries the correction scans: the partner row of every light pair.
+__global__ __launch_bounds__(256) void k_fix_scanned(int64_t npairs, const int32_t* __restrict__ partners,
+                                                     const int64_t* __restrict__ lg_ptr,
+                                                     unsigned long long* stats) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long d = 0;
+  if (p < npairs) {
+    const int32_t k = partners[p];
+    d = (unsigned long long)(lg_ptr[k + 1] - lg_ptr[k]);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) d += __shfl_xor(d, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicAdd(&stats[kStFixScanned], d);
 }
 
 // esize[x] = |e_x|.
@@ -273,7 +295,7 @@ inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
 }  // namespace
 
 mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
-                            int64_t* d_hist) {
+                            int64_t* d_hist, unsigned long long* stats) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E, V = g->V;
   if (c1 <= c0 || E == 0 || V == 0) return MOCHY_OK;
@@ -286,6 +308,16 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   const size_t tmpn = scan_tmp_elems(E + 1);
   const size_t n64 = size_t(E) + 1 + size_t(E + 1) * 2 + tmpn;
   char* buf = nullptr;
+  int64_t* eoff = nullptr;
+  int32_t* partners = nullptr;
+  uint32_t* esize = nullptr;
+  auto done = [&](mochy_status s) {
+    device_free(ctx, buf);
+    device_free(ctx, eoff);
+    device_free(ctx, partners);
+    device_free(ctx, esize);
+    return s;
+  };
   mochy_status rc = device_alloc(ctx, (void**)&buf, n64 * 8 + size_t(E) * 4);
   if (rc != MOCHY_OK) return rc;
   unsigned long long* pcount = (unsigned long long*)buf;
@@ -294,48 +326,41 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* poff = ocount + (E + 1);
   int64_t* tmp = poff + (E + 1);
   int32_t* owners = (int32_t*)(buf + n64 * 8);
-  auto done = [&](mochy_status s) { device_free(ctx, buf); return s; };
-  MOCHY_HIP(hipMemsetAsync(buf, 0, (size_t(E) + 1 + size_t(E + 1)) * 8, st));
+  MOCHY_HIP_OR(hipMemsetAsync(buf, 0, (size_t(E) + 1 + size_t(E + 1)) * 8, st), done);
   const unsigned wblocks = blocks(V * 64, 256);
   k_light_pairs<false><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                 g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
                                                 nullptr, nullptr);
   k_owner_list<<<blocks(E, 256), 256, 0, st>>>(E, pcount, nown, owners, ocount);
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 504, nown, 8, hipMemcpyDeviceToHost, st));
-  MOCHY_HIP(hipStreamSynchronize(st));
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 504, nown, 8, hipMemcpyDeviceToHost, st), done);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t nowners = ctx->h_small[504];
   if (nowners == 0) return done(MOCHY_OK);
   launch_exclusive_scan_i64(ocount, poff, nowners + 1, tmp, st);  // ocount[nowners] is 0
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 505, poff + nowners, 8, hipMemcpyDeviceToHost, st));
-  MOCHY_HIP(hipStreamSynchronize(st));
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 505, poff + nowners, 8, hipMemcpyDeviceToHost, st), done);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t npairs = ctx->h_small[505];
+  ctx->exact_stats[kStLightPairs] += npairs;
   // per-owner offsets indexed by hyperedge id for the fill pass
-  int64_t* eoff = nullptr;
-  int32_t* partners = nullptr;
   if ((rc = device_alloc(ctx, (void**)&eoff, size_t(E) * 8)) != MOCHY_OK) return done(rc);
-  if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) {
-    device_free(ctx, eoff);
-    return done(rc);
-  }
-  auto done2 = [&](mochy_status s) { device_free(ctx, eoff); device_free(ctx, partners); return done(s); };
+  if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) return done(rc);
   // scatter owner offsets to hyperedge ids, reset counters, fill
   k_owner_offsets<<<blocks(nowners, 256), 256, 0, st>>>(nowners, owners, poff, eoff);
-  MOCHY_HIP(hipMemsetAsync(pcount, 0, size_t(E) * 8, st));
+  MOCHY_HIP_OR(hipMemsetAsync(pcount, 0, size_t(E) * 8, st), done);
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);
   // hyperedge sizes as 32-bit words: one load and one register per centre in
   // flight (two 64-bit offsets otherwise), which keeps the kernel within 64
   // registers, so 4 blocks (32 waves) are resident per CU instead of 3
-  uint32_t* esize = nullptr;
-  if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done2(rc);
+  if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done(rc);
   k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
   k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners,
                                                            g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
                                                            g->lg_col, g->recm, esize, ctx->d_code_to_id3,
-                                                           (unsigned long long*)d_hist);
-  device_free(ctx, esize);
-  MOCHY_HIP(hipGetLastError());
-  MOCHY_HIP(hipStreamSynchronize(st));
-  return done2(MOCHY_OK);
+                                                           (unsigned long long*)d_hist, stats);
+  k_fix_scanned<<<blocks(npairs, 256), 256, 0, st>>>(npairs, partners, g->lg_ptr, stats);
+  MOCHY_HIP_OR(hipGetLastError(), done);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), done);
+  return done(MOCHY_OK);
 }

@@ -376,7 +376,8 @@ template <bool kWrite>
 __global__ __launch_bounds__(kGroupThreads) void k_group(
     int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
     const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
-    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags) {
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags,
+    unsigned long long* stats) {
   __shared__ unsigned long long key[kGroupSlots];
   __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
   __shared__ uint32_t s_out, s_outb, s_bad, s_cnt;
@@ -392,6 +393,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
   // kPartGroups groups (rows have 0.38 groups per record on medium)
   int64_t parts = (d + kPartRecords - 1) / kPartRecords;
   if (parts < 1) parts = 1;
+  const int64_t parts0 = parts;
   uint64_t seed = 0;
   const int64_t obase = kWrite ? obase_of[i] - cap0 : 0;
   const int64_t oend = kWrite ? obase_of[i + 1] - cap0 : 0;  // one past the row's region
@@ -520,6 +522,34 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
   if (tid == 0) {
     if (gcount) gcount[i] = int64_t(s_out) + s_outb;
     if (kWrite) gna[i] = int32_t(s_out);
+    if (stats) {  // one pass of the row's grouping reports its parts
+      if (parts > parts0) atomicAdd(&stats[kStRegrouped], 1ull);
+      atomicMax(&stats[kStMaxParts], (unsigned long long)parts);
+    }
+  }
+}
+
+// Per-row group statistics of rows [c0, c1): groups, groups with members
+// above the centre, pairs of such groups (classified in full by the pair
+// kernel) and the other pairs of groups (counted only when open).
+__global__ __launch_bounds__(256) void k_group_stats(int64_t c0, int64_t c1, const int64_t* __restrict__ goff,
+                                                     const int32_t* __restrict__ gna,
+                                                     unsigned long long* stats) {
+  const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long ng = 0, na = 0;
+  if (i < c1) {
+    ng = (unsigned long long)(goff[i + 1] - goff[i]);
+    na = (unsigned long long)gna[i];
+  }
+  unsigned long long v[4] = {ng, na, na * (na - (na ? 1 : 0)) / 2,
+                             ng * (ng - (ng ? 1 : 0)) / 2 - na * (na - (na ? 1 : 0)) / 2};
+  for (int x = 0; x < 4; ++x)
+    for (int off = kWave / 2; off > 0; off >>= 1) v[x] += __shfl_xor(v[x], off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (v[0]) atomicAdd(&stats[kStGroups], v[0]);
+    if (v[1]) atomicAdd(&stats[kStGroupsAbove], v[1]);
+    if (v[2]) atomicAdd(&stats[kStPairsFull], v[2]);
+    if (v[3]) atomicAdd(&stats[kStPairsOpen], v[3]);
   }
 }
 
@@ -527,9 +557,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
 constexpr int kGCopies = 2;
 constexpr int kGStride = kHistSlots + 1;
 
-// kNarrow: every row is shorter than 2^24, so a weight is a product of two
-// 24-bit counts (two full-rate multiplies instead of a 64-bit one).
-// A disjoint pair (open at the centre) weighs nall_j * nall_k, an
+// Every row is shorter than 2^24 (a graph has at most 200000 hyperedges), so
+// a weight is a product of two 24-bit counts (two full-rate multiplies
+// instead of a 64-bit one).  A disjoint pair (open at the centre) weighs nall_j * nall_k, an
 // overlapping one nabove_j * nabove_k; ka_m is the lane's nabove with every
 // bit set or clear as row j has members above the centre or not, so the
 // selected lane count is zero exactly when the pair weighs nothing (every
@@ -537,7 +567,7 @@ constexpr int kGStride = kHistSlots + 1;
 // kAllA: every lane's group and j have members above the centre, so every
 // pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
 // past the row's end has N = A = 0 and adds 0 at a valid class).
-template <bool kDiag, bool kNarrow, bool kAllA>
+template <bool kDiag, bool kAllA>
 __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks,
                                            const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
                                            uint32_t ka, int kp, const uint16_t* __restrict__ lut,
@@ -549,7 +579,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
     uint32_t cx = cj.x, cy = cj.y;
     asm("" : "+s"(cx), "+s"(cy));
     const uint32_t y = disjoint ? kn : ka;
-    const uint32_t x = kNarrow ? (disjoint ? cx : cy) & 0xffffffu : (disjoint ? cx : cy);
+    const uint32_t x = (disjoint ? cx : cy) & 0xffffffu;
     const uint32_t t = uint32_t(__popc(xm));
     const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
     const uint32_t code = pair_code_aks(aks, __popc(mj), rj.y & 0xffu, k, t, r5);
@@ -565,7 +595,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   bool act = y != 0u;
   if (kDiag) act = act && (j < kp);
   if (act) {
-    const uint32_t x = kNarrow ? (disjoint ? cx : cy) & 0xffffffu : (disjoint ? cx : cy);
+    const uint32_t x = (disjoint ? cx : cy) & 0xffffffu;
     const uint64_t w = uint64_t(x) * y;
     const uint32_t t = uint32_t(__popc(xm));
     const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
@@ -574,7 +604,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   }
 }
 
-template <bool kDiag, bool kNarrow, bool kAllA>
+template <bool kDiag, bool kAllA>
 __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
                                       int j0, int j1, uint32_t aks, const Side& k, uint32_t kn,
                                       uint32_t ka, int kp, const uint16_t* __restrict__ lut,
@@ -584,13 +614,13 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag, kNarrow, kAllA>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow, kAllA>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow, kAllA>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kNarrow, kAllA>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
   }
   for (; j < j1; ++j)
-    gpair_step<kDiag, kNarrow, kAllA>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
 }
 
 // A pair in which one group has no member above the centre counts only when
@@ -673,7 +703,7 @@ constexpr int kGSharedCopies = 4;
 // work items count each graph with its own launch of the shared-histogram
 // kernel; others use per-wave histograms in one launch
 constexpr int kPerGraphLaunches = 256;
-template <bool kNarrow, bool kShared>
+template <bool kShared>
 __global__ __launch_bounds__(256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
@@ -737,10 +767,8 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       kn = ck.x;
       ka = ck.y;
     }
-    if (kNarrow) {
-      kn &= 0xffffffu;
-      ka &= 0xffffffu;
-    }
+    kn &= 0xffffffu;
+    ka &= 0xffffffu;
     const int blo = b * kWave;
     const int kmax = min(blo + kWave, ng);
     const uint32_t aks = a - k.s;
@@ -750,12 +778,12 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
       owalk<false>(growb, gcb, na, blo, aks, k0, k, kn, kp, lut, myhist);
       owalk<true>(growb, gcb, blo, kmax, aks, k0, k, kn, kp, lut, myhist);
     } else if (blo + kWave <= na) {  // every lane has members above the centre
-      gwalk<false, kNarrow, true>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
-      gwalk<true, kNarrow, false>(grow, gc, blo, kmax, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<false, true>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, false>(grow, gc, blo, kmax, aks, k, kn, ka, kp, lut, myhist);
     } else {  // j with members above the centre: every pair; the others: open only
       const int ka1 = min(kmax, na);
-      gwalk<false, kNarrow, false>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
-      gwalk<true, kNarrow, false>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<false, false>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, false>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
       owalk<true>(growb, gcb, ka1, kmax, aks, k0, k, kn, kp, lut, myhist);
     }
     if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
@@ -845,7 +873,7 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 // pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                           int64_t** goff, uint4** grec, uint2** gcnt, int32_t** gna,
-                          const int64_t** gbase, int64_t* cap0) {
+                          const int64_t** gbase, int64_t* cap0, unsigned long long* stats) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E;
   int64_t* cntarr = nullptr;
@@ -867,9 +895,9 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     *gna = nullptr;
     return rc;
   };
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small, g->lg_ptr + c0, 8, hipMemcpyDeviceToHost, st));
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, g->lg_ptr + c1, 8, hipMemcpyDeviceToHost, st));
-  MOCHY_HIP(hipStreamSynchronize(st));
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small, g->lg_ptr + c0, 8, hipMemcpyDeviceToHost, st), fail);
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 1, g->lg_ptr + c1, 8, hipMemcpyDeviceToHost, st), fail);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), fail);
   const int64_t row0 = ctx->h_small[0];
   const int64_t cap = ctx->h_small[1] - row0;
   // one pass into row capacity (a graph or a batch) when that fits the limit
@@ -880,9 +908,10 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
       (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)gna, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK)
     return fail(rc);
-  MOCHY_HIP(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st));
-  MOCHY_HIP(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st));
-  if (by_rows && (device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16) != MOCHY_OK ||
+  MOCHY_HIP_OR(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st), fail);
+  MOCHY_HIP_OR(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st), fail);
+  if (by_rows && ((ctx->test_faults & 1) ||
+                  device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16) != MOCHY_OK ||
                   device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8) != MOCHY_OK)) {
     // no room for the row capacity: count the groups first and allocate them exactly
     device_free(ctx, *grec);
@@ -898,7 +927,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0)
       k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                 cntarr, g->lg_ptr, row0, *grec, *gcnt,
-                                                                *gna, ctx->d_flags + 3);
+                                                                *gna, ctx->d_flags + 3, stats);
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
   } else {
     *gbase = *goff;
@@ -906,27 +935,32 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0)
       k_group<false><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                  cntarr, nullptr, 0, nullptr, nullptr,
-                                                                 nullptr, ctx->d_flags + 3);
+                                                                 nullptr, ctx->d_flags + 3, stats);
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
-    MOCHY_HIP(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st));
-    MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
-    MOCHY_HIP(hipStreamSynchronize(st));
+    MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st), fail);
+    MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st), fail);
+    MOCHY_HIP_OR(hipStreamSynchronize(st), fail);
     if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
     const int64_t ngroups = ctx->h_small[0];
     if ((rc = device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(ngroups, 1)) * 16)) != MOCHY_OK ||
         (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(ngroups, 1)) * 8)) != MOCHY_OK)
       return fail(rc);
+    // the same grouping again, written this time (its parts were reported above)
     if (c1 > c0)
       k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
                                                                 nullptr, *goff, 0, *grec, *gcnt,
-                                                                *gna, ctx->d_flags + 3);
+                                                                *gna, ctx->d_flags + 3, nullptr);
   }
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st));
-  MOCHY_HIP(hipStreamSynchronize(st));
+  if (c1 > c0)
+    k_group_stats<<<blocks(c1 - c0, 256), 256, 0, st>>>(c0, c1, *goff, *gna, stats);
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st), fail);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), fail);
   if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
   device_free(ctx, cntarr);
   device_free(ctx, tmp);
-  MOCHY_HIP(hipGetLastError());
+  cntarr = nullptr;
+  tmp = nullptr;
+  MOCHY_HIP_OR(hipGetLastError(), fail);
   return MOCHY_OK;
 }
 
@@ -936,8 +970,14 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
                           int64_t* d_hist) {
   hipStream_t st = ctx->stream;
   const int ng = g->ng;
+  unsigned long long* stats = (unsigned long long*)(ctx->d_small + kExactStatsSlot);
   MOCHY_HIP(hipMemsetAsync(d_hist, 0, size_t(ng) * kHistSlots * 8, st));
+  MOCHY_HIP(hipMemsetAsync(stats, 0, MOCHY_NUM_EXACT_STATS * 8, st));
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
+  if (g->max_deg >= (1 << 24)) {  // group sizes are multiplied as 24-bit numbers
+    ctx->err = "a line-graph row of 2^24 or more neighbours";
+    return MOCHY_EUNSUPPORTED;
+  }
   const unsigned grid = unsigned(ctx->num_cus) * unsigned(ctx->pair_blocks);
   int64_t* goff = nullptr;
   const int64_t* gbase = nullptr;
@@ -945,31 +985,40 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   uint4* grec = nullptr;
   uint2* gcnt = nullptr;
   int32_t* gna = nullptr;
+  unsigned long long* gqueue = nullptr;
   mochy_status rc;
   phase_begin(ctx, kPhSched);
   bool grouped = ctx->group_neighbours;
   if (grouped) {
-    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0);
+    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0, stats);
     if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
       grouped = false;
       ctx->err.clear();
+      MOCHY_HIP(hipMemsetAsync(stats, 0, MOCHY_NUM_EXACT_STATS * 8, st));
     } else if (rc != MOCHY_OK) {
       return rc;
     }
   }
   Schedule S;
-  rc = build_schedule(ctx, g, c0, c1, grouped ? goff : g->lg_ptr, grouped ? 1 : 2, S);
-  auto release = [&]() {
+  auto release = [&](mochy_status s) {
     device_free(ctx, S.scratch);
     device_free(ctx, goff);
     device_free(ctx, grec);
     device_free(ctx, gcnt);
     device_free(ctx, gna);
+    device_free(ctx, gqueue);
+    S.scratch = nullptr;
+    goff = nullptr;
+    grec = nullptr;
+    gcnt = nullptr;
+    gna = nullptr;
+    gqueue = nullptr;
+    return s;
   };
-  if (rc != MOCHY_OK) { release(); return rc; }
+  rc = build_schedule(ctx, g, c0, c1, grouped ? goff : g->lg_ptr, grouped ? 1 : 2, S);
+  if (rc != MOCHY_OK) return release(rc);
   phase_end(ctx, kPhSched);
   phase_begin(ctx, kPhPairs);
-  const bool narrow = g->max_deg < (1 << 24);
   // a batch of graphs large enough to fill the device each: the
   // shared-histogram kernel once per graph (a graph's items are contiguous in
   // the schedule), each launch with its own queue counter; smaller graphs are
@@ -978,43 +1027,46 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   std::vector<int64_t> hgq;
   if (grouped && ng > 1 && ng <= kPerGraphLaunches && ctx->batch_launch != 1) {
     hgq.resize(size_t(ng) + 1);
-    MOCHY_HIP(hipMemcpyAsync(hgq.data(), S.gq, hgq.size() * 8, hipMemcpyDeviceToHost, st));
-    MOCHY_HIP(hipStreamSynchronize(st));
+    MOCHY_HIP_OR(hipMemcpyAsync(hgq.data(), S.gq, hgq.size() * 8, hipMemcpyDeviceToHost, st), release);
+    MOCHY_HIP_OR(hipStreamSynchronize(st), release);
     if (ctx->batch_launch == 0 && hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
   }
   if (!hgq.empty()) {
-    unsigned long long* gqueue = nullptr;
-    if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) { release(); return rc; }
-    MOCHY_HIP(hipMemsetAsync(gqueue, 0, size_t(ng) * 8, st));
+    if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) return release(rc);
+    MOCHY_HIP_OR(hipMemsetAsync(gqueue, 0, size_t(ng) * 8, st), release);
     for (int gi = 0; gi < ng; ++gi) {
       const int64_t items = hgq[gi + 1] - hgq[gi];
       if (items <= 0) continue;
       // at most one wave per item
       const unsigned ggrid = unsigned(std::min<int64_t>(grid, (items + kWavesPerGroup - 1) / kWavesPerGroup));
-      (narrow ? k_exact_grouped<true, true> : k_exact_grouped<false, true>)<<<ggrid, 256, 0, st>>>(
+      k_exact_grouped<true><<<ggrid, 256, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, hgq[gi], hgq[gi + 1],
           g->row_graph, gqueue + gi, ctx->d_code_to_id3, (unsigned long long*)d_hist + size_t(gi) * kHistSlots);
     }
-    device_free(ctx, gqueue);
   } else if (grouped) {
-    (narrow ? (ng == 1 ? k_exact_grouped<true, true> : k_exact_grouped<true, false>)
-            : (ng == 1 ? k_exact_grouped<false, true> : k_exact_grouped<false, false>))
-        <<<grid, 256, 0, st>>>(
+    (ng == 1 ? k_exact_grouped<true> : k_exact_grouped<false>)<<<grid, 256, 0, st>>>(
         g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
         S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
-  } else
+  } else {
     k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, S.order, S.rstart,
                                        S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
                                        (unsigned long long*)d_hist);
+  }
   phase_end(ctx, kPhPairs);
-  MOCHY_HIP(hipGetLastError());
-  release();  // stream-ordered; the correction reads rows and records only
+  MOCHY_HIP_OR(hipGetLastError(), release);
+  release(MOCHY_OK);  // stream-ordered; the correction reads rows and records only
   phase_begin(ctx, kPhCorrect);
-  rc = correct_device(ctx, g, c0, c1, d_hist);
+  rc = correct_device(ctx, g, c0, c1, d_hist, stats);
   if (rc != MOCHY_OK) return rc;
   phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + kExactStatsSlot, stats, MOCHY_NUM_EXACT_STATS * 8,
+                           hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
   phases_collect(ctx);
+  const int64_t* hs = ctx->h_small + kExactStatsSlot;
+  for (int x = 0; x < MOCHY_NUM_EXACT_STATS; ++x)
+    ctx->exact_stats[x] = x == kStMaxParts ? std::max(ctx->exact_stats[x], hs[x]) : ctx->exact_stats[x] + hs[x];
+  if (grouped) ctx->exact_stats[kStRows] += c1 - c0;
   return MOCHY_OK;
 }

@@ -265,3 +265,114 @@ def test_grouping_parts_double(ctx):
         g.close()
     for x26, x431 in ((a26, a431), (b26, b431), (c26, c431)):
         assert (x431 == o431).all() and (x26 == o26).all()
+
+
+def test_which_selector(ctx):
+    # `which` selects outputs only: every selection gives the same numbers
+    import paper_2310_15668_amd as M
+    h = make_config("tiny")
+    g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+    try:
+        a26, a431 = M.mochy_count_exact(ctx, g)
+        b26, b431 = M.mochy_count_exact(ctx, g, M.MOCHY_H26)
+        c26, c431 = M.mochy_count_exact_range(ctx, g, 0, h.num_edges, M.MOCHY_H431)
+        assert b431 is None and c26 is None
+        assert (b26 == a26).all() and (c431 == a431).all()
+        s26, e26, s431, e431 = M.mochy_count_sampled(ctx, g, 500, 3, which=M.MOCHY_H431)
+        assert s26 is None and e26 is None
+        f26, _, f431, _ = M.mochy_count_sampled(ctx, g, 500, 3)
+        assert (s431 == f431).all()
+        for bad in (0, 4, 7):
+            with pytest.raises(M.MochyError) as e:
+                M.mochy_count_exact(ctx, g, bad)
+            assert e.value.status == -1
+    finally:
+        g.close()
+
+
+def test_canonicalize_flag(ctx):
+    # unsorted node lists with repeated members are read as node sets
+    import paper_2310_15668_amd as M
+    h = make_config("tiny")
+    rng = np.random.default_rng(11)
+    ptr, nodes = [0], []
+    for e in range(h.num_edges):
+        row = h.edge(e).tolist()
+        row = row + row[:int(rng.integers(0, len(row) + 1))]  # repeats
+        rng.shuffle(row)
+        nodes.extend(row)
+        ptr.append(len(nodes))
+    messy = Hypergraph(np.array(ptr, dtype=np.int64), np.array(nodes, dtype=np.int32), h.num_nodes)
+    with pytest.raises(M.MochyError) as e:
+        gpu_counts(ctx, messy)
+    assert e.value.status == -1
+    c26, c431, w = gpu_counts(ctx, messy, flags=M.MOCHY_CANONICALIZE)
+    r26, r431, rw = gpu_counts(ctx, h)
+    assert w == rw and (c431 == r431).all()
+    # 40 distinct nodes stay too many after canonicalization; 33 repeats of 30 do not
+    with pytest.raises(M.MochyError) as e:
+        gpu_counts(ctx, from_edge_lists([list(range(40))]), flags=M.MOCHY_CANONICALIZE)
+    assert e.value.status == -3
+    rep = Hypergraph(np.array([0, 33, 35], dtype=np.int64),
+                     np.array(list(range(30)) + [0, 1, 2] + [0, 40], dtype=np.int32), 41)
+    c26, _, w = gpu_counts(ctx, rep, flags=M.MOCHY_CANONICALIZE)
+    assert w == 1 and c26.sum() == 0
+
+
+def test_size_limit(ctx):
+    # hyperedges of up to 32 nodes are accepted, 33 are MOCHY_ERANGE
+    import paper_2310_15668_amd as M
+    edges = [list(range(32)), list(range(16, 48)), [0, 47], list(range(100, 132))]
+    h = from_edge_lists(edges, 140)
+    c26, c431, w = gpu_counts(ctx, h)
+    r26, r431, _ = native.mochy_e(h, nthreads=2)
+    assert (c431 == r431).all() and w == 3
+    with pytest.raises(M.MochyError) as e:
+        gpu_counts(ctx, from_edge_lists([list(range(33)), [0, 1]], 40))
+    assert e.value.status == -3
+
+
+def test_row_capacity_fallback(ctx):
+    # the one-pass grouping's row-capacity allocation made to fail: the
+    # counted-first layout gives the same counts
+    import paper_2310_15668_amd as M
+    h = make_config("medium", scale=0.03)
+    print(f"[gpu] forced counted-first fallback |E|={h.num_edges}", flush=True)
+    g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+    try:
+        a26, a431 = M.mochy_count_exact(ctx, g)
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 1)
+        b26, b431 = M.mochy_count_exact(ctx, g)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 0)
+        g.close()
+    assert (a431 == b431).all() and (a26 == b26).all()
+    with pytest.raises(M.MochyError):
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 2)
+
+
+def test_exact_stats(ctx):
+    # the work counters of the last exact call are consistent with the graph
+    import paper_2310_15668_amd as M
+    h = make_config("medium", scale=0.03)
+    g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+    try:
+        M.mochy_count_exact(ctx, g)
+        st = M.mochy_exact_stats(ctx)
+        gs = M.mochy_graph_stats(ctx, g)
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 0)
+        M.mochy_count_exact(ctx, g)
+        st0 = M.mochy_exact_stats(ctx)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+        g.close()
+    deg, _ = native.line_graph_degrees(h, 4)
+    assert st["rows_grouped"] == h.num_edges
+    assert 0 < st["groups_above"] <= st["groups"] <= 2 * gs["hyperwedges"]
+    assert st["group_pairs_full"] + st["group_pairs_open"] <= int((deg * (deg - 1) // 2).sum())
+    assert st["max_hash_parts"] >= 1
+    assert st["light_pairs"] > 0 and 0 < st["fix_changed"] <= st["fix_centres"] <= st["fix_scanned"]
+    # without groups only the correction's counters are set, to the same values
+    assert st0["groups"] == 0 and st0["group_pairs_full"] == 0
+    for k in ("light_pairs", "fix_scanned", "fix_centres", "fix_changed"):
+        assert st0[k] == st[k], k

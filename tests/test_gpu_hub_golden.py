@@ -1,0 +1,122 @@
+"""GPU parity where the medium workload's exact work concentrates: single hub
+centres of the full-size graph against oracle counts stored in
+tests/golden/medium_hub_centres.txt (written by oracle/make_medium_hub_golden.py
+from oracle/ and workloads/ only).
+
+Algorithm 2 attributes each instance to one centre (section 4.2), so the
+counts of one centre are checked exactly with mochy_count_exact_range.  The
+stored centres are the ten rows of largest line-graph degree and rows at
+spread ranks of every degree band above 8,192: these rows hold almost all of
+the medium workload's candidates and are grouped in three or more hash parts
+by the pair kernel's grouping.  Both group layouts are checked (one pass into
+row capacity, and groups counted first).  Two hyperedge-profile rows of hub
+degree check the MoCHy-A / profile kernel on rows of thousands of neighbours.
+"""
+import numpy as np
+import pytest
+
+from conftest import golden
+from oracle import native
+from oracle.make_medium_hub_golden import csr_digest
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = "medium_hub_centres.txt"
+
+
+@pytest.fixture(scope="module")
+def stored():
+    rows = golden(GOLDEN)
+    head = {r[0]: r[1] for r in rows if r[0] in ("csr_sha256", "hyperwedges")}
+    exact = [(int(r[1]), int(r[2]), np.array(r[3:], dtype=np.int64)) for r in rows if r[0] == "exact"]
+    prof = [(int(r[1]), int(r[2]), np.array(r[3:], dtype=np.int64)) for r in rows if r[0] == "profile"]
+    assert all(v.size == 431 for _, _, v in exact + prof)
+    return head, exact, prof
+
+
+@pytest.fixture(scope="module")
+def medium(stored):
+    h = make_config("medium")
+    assert csr_digest(h) == stored[0]["csr_sha256"], "the medium generator changed since the golden was written"
+    return h
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2310_15668_amd as M
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def graph(ctx, medium, stored):
+    import paper_2310_15668_amd as M
+    print("[gpu] project full medium hypergraph", flush=True)
+    g = M.mochy_project(ctx, medium.edge_ptr, medium.edge_nodes, medium.num_nodes)
+    assert g.num_hyperwedges == int(stored[0]["hyperwedges"])
+    yield g
+    g.close()
+
+
+def test_golden_covers_the_hub_rows(stored):
+    _, exact, _ = stored
+    deg = [d for _, d, _ in exact]
+    assert max(deg) == 49249  # the maximum-degree row of the medium workload
+    assert sum(d > 8192 for d in deg) == len(deg)
+    assert min(deg) < 12288 and sum(d >= 32768 for d in deg) >= 10
+    # each stored centre's counts are non-trivial and open/closed consistent:
+    # an open instance has its middle at the centre, so a row of d neighbours
+    # holds at most C(d, 2) of them
+    for _, d, v in exact:
+        assert 0 < v.sum() <= d * (d - 1) // 2
+
+
+@pytest.mark.parametrize("layout", ["one-pass", "counted-first"])
+def test_hub_centres_match_oracle(ctx, graph, stored, layout):
+    import paper_2310_15668_amd as M
+    _, exact, _ = stored
+    parts, regrouped = 0, 0
+    try:
+        if layout == "counted-first":
+            ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 0)
+        for c, d, want in exact:
+            print(f"[gpu] medium centre {c} (degree {d}), {layout} groups", flush=True)
+            g26, g431 = M.mochy_count_exact_range(ctx, graph, c, c + 1)
+            st = M.mochy_exact_stats(ctx)
+            parts = max(parts, st["max_hash_parts"])
+            regrouped += st["rows_regrouped"]
+            assert st["rows_grouped"] == 1
+            assert (g431 == want).all(), (c, np.nonzero(g431 != want)[0][:8])
+            assert (g26 == native.fold26(np.concatenate([[0], want]))).all(), c
+    finally:
+        ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
+    # rows of more than 8,192 neighbours start at three or more hash parts,
+    # and some rows here pass the per-part group limit and are regrouped
+    assert parts >= 13 and regrouped > 0, (parts, regrouped)
+
+
+def test_hub_centres_every_pair(ctx, graph, stored):
+    # pairing every record (no groups) on the largest rows
+    import paper_2310_15668_amd as M
+    _, exact, _ = stored
+    try:
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 0)
+        for c, d, want in sorted(exact, key=lambda x: -x[1])[:3]:
+            print(f"[gpu] medium centre {c} (degree {d}), every pair", flush=True)
+            _, g431 = M.mochy_count_exact_range(ctx, graph, c, c + 1)
+            assert (g431 == want).all(), c
+    finally:
+        ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
+
+
+def test_hub_hyperedge_profiles_match_oracle(ctx, graph, stored):
+    import paper_2310_15668_amd as M
+    _, _, prof = stored
+    assert prof and min(d for _, d, _ in prof) > 8000
+    for e, d, want in prof:
+        print(f"[gpu] medium hyperedge profile {e} (degree {d})", flush=True)
+        p26, p431 = M.mochy_hyperedge_profiles(ctx, graph, e, e + 1)
+        assert (p431[0] == want).all(), (e, np.nonzero(p431[0] != want)[0][:8])
+        assert (p26[0] == native.fold26(np.concatenate([[0], want]))).all()
