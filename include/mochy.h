@@ -144,7 +144,9 @@ const char* mochy_last_error(const mochy_ctx* ctx);
 #define MOCHY_OPT_TEST_FAULTS 10  /* for tests of the fallbacks: bit 0 makes the one-pass
                                      grouping's row-capacity allocation report
                                      MOCHY_ENOMEM, so exact counting takes the
-                                     counted-first layout (default 0); same counts */
+                                     counted-first layout; bit 1 caps the scratch of
+                                     mochy_count_exact_range_noalloc at 64 KiB (default
+                                     0); same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
@@ -181,6 +183,31 @@ mochy_status mochy_count_exact(mochy_ctx* ctx, const mochy_graph* g, uint32_t wh
 mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_graph* g,
                                      int64_t center_begin, int64_t center_end, uint32_t which,
                                      int64_t* counts26, int64_t* counts431);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * counts as mochy_count_exact_range (same arguments, same results), computed
+ * without any device or host allocation.  Every neighbour pair of a centre
+ * is classified (no neighbour groups, which would need memory in proportion
+ * to the line graph), and the work-item schedule and the correction's
+ * light-pair lists live in a static device array of MOCHY_NOALLOC_SCRATCH
+ * bytes that each device the library runs on holds from the first context
+ * created on it until the process ends.  The graph, the context and the
+ * outputs are the caller's, as in mochy_count_exact_range.
+ * MOCHY_ERANGE (with the sizes in the message) if a call would need more
+ * scratch than that; the work it needs grows with |E|, the largest
+ * line-graph degree and the pairs of hyperedges that share a light node
+ * (about 40 MiB for the medium workload of 85,476 hyperedges).
+ * All calls on one device share its scratch array, whose contents persist
+ * from call to call (each call initializes what it reads); calls that
+ * overlap in time on one device, from any contexts or threads, race on it
+ * and must not be issued.  Slower than mochy_count_exact_range on large
+ * rows (every pair instead of pairs of groups). */
+#define MOCHY_NOALLOC_SCRATCH (64u << 20)
+mochy_status mochy_count_exact_range_noalloc(mochy_ctx* ctx, const mochy_graph* g,
+                                             int64_t center_begin, int64_t center_end,
+                                             uint32_t which, int64_t* counts26,
+                                             int64_t* counts431);
 
 /* MoCHy-A+ (Algorithm 5): samples n = sample_begin .. sample_begin+r-1 each
  * draw one hyperwedge uniformly with replacement, using Philox4x32-10 with

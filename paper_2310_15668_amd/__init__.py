@@ -13,5 +13,5 @@ from ._lib import (  # noqa: F401
     MOCHY_OPT_CACHE_BYTES, MOCHY_OPT_TEST_FAULTS, MOCHY_CANONICALIZE, MOCHY_H26, MOCHY_H431,
     MOCHY_WHICH_ALL,
     mochy_graph_stats, mochy_phase_ms, mochy_memo_stats, mochy_exact_stats,
-    mochy_calibrate_valu,
+    mochy_calibrate_valu, mochy_count_exact_range_noalloc,
 )

@@ -43,7 +43,8 @@ EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_
             "mochy_count_sampled", "mochy_profile", "mochy_motif_pattern", "mochy_parent_motif",
             "mochy_graph_stats", "mochy_phase_ms", "mochy_memo_stats", "mochy_ctx_set_option",
             "mochy_count_sampled_edges", "mochy_hyperedge_profiles", "mochy_exact_stats",
-            "mochy_calibrate_valu")
+            "mochy_calibrate_valu", "mochy_count_exact_range_noalloc")
+NOALLOC_SCRATCH = 64 << 20
 NUM_EXACT_STATS = 11
 EXACT_STATS = ("rows_grouped", "groups", "groups_above", "group_pairs_full", "group_pairs_open",
                "rows_regrouped", "max_hash_parts", "light_pairs", "fix_scanned", "fix_centres",
@@ -100,6 +101,8 @@ def lib():
     L.mochy_count_exact.restype = ctypes.c_int
     L.mochy_count_exact_range.argtypes = [vp, vp, i64, i64, u32, vp, vp]
     L.mochy_count_exact_range.restype = ctypes.c_int
+    L.mochy_count_exact_range_noalloc.argtypes = [vp, vp, i64, i64, u32, vp, vp]
+    L.mochy_count_exact_range_noalloc.restype = ctypes.c_int
     L.mochy_count_sampled.argtypes = [vp, vp, i64, u64, i64, u32, vp, vp, vp, vp]
     L.mochy_count_sampled.restype = ctypes.c_int
     L.mochy_profile.argtypes = [vp, i32, ctypes.POINTER(CSR), ctypes.c_double, u32, vp, vp, vp, vp, vp]
@@ -253,6 +256,16 @@ def mochy_count_exact_range(ctx: Context, g: Graph, c0: int, c1: int, which: int
     c431 = _outs(which & MOCHY_H431, NUM_3H, np.int64)
     ctx.check(lib().mochy_count_exact_range(ctx.handle, g.handle, int(c0), int(c1), int(which), _ptr(c26),
                                             _ptr(c431)), "mochy_count_exact_range")
+    return c26, c431
+
+
+def mochy_count_exact_range_noalloc(ctx: Context, g: Graph, c0: int, c1: int,
+                                    which: int = MOCHY_WHICH_ALL):
+    """mochy_count_exact_range without device allocation (static scratch array)."""
+    c26 = _outs(which & MOCHY_H26, NUM_H, np.int64)
+    c431 = _outs(which & MOCHY_H431, NUM_3H, np.int64)
+    ctx.check(lib().mochy_count_exact_range_noalloc(ctx.handle, g.handle, int(c0), int(c1), int(which),
+                                                    _ptr(c26), _ptr(c431)), "mochy_count_exact_range_noalloc")
     return c26, c431
 
 

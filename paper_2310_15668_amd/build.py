@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmochy.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["patterns.cpp", "scan.hip", "project.hip", "exact.hip", "correct.hip", "sampled.hip",
-           "free.hip", "memo.hip", "calibrate.hip", "api.hip"]
+           "free.hip", "memo.hip", "calibrate.hip", "noalloc.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -254,6 +254,17 @@ void cache_release(mochy_ctx* ctx) {
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   size_t n = std::max<size_t>(bytes, 8);
+  if (ctx->arena) {  // allocation-free call: carve from the static scratch array
+    const size_t at = (ctx->arena_used + 255) & ~size_t(255);
+    if (at + n > ctx->arena_cap) {
+      ctx->err = "the allocation-free call needs more than its " + std::to_string(ctx->arena_cap) +
+                 "-byte scratch array (" + std::to_string(at + n) + " bytes so far)";
+      return MOCHY_ERANGE;
+    }
+    *p = ctx->arena + at;
+    ctx->arena_used = at + n;
+    return MOCHY_OK;
+  }
   const bool cached = ctx->cache_limit > 0 && n >= kCacheMinBytes;
   if (cached) {
     auto it = ctx->cache_free.lower_bound(n);
@@ -283,7 +294,7 @@ mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes) {
 }
 
 void device_free(mochy_ctx* ctx, void* p) {
-  if (!p) return;
+  if (!p || ctx->arena) return;  // arena blocks are released with the call
   auto it = ctx->cache_live.find(p);
   if (it != ctx->cache_live.end() && ctx->cache_bytes + int64_t(it->second) <= ctx->cache_limit) {
     ctx->cache_free.emplace(it->second, p);  // stays in cache_live until released
@@ -347,6 +358,9 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
     return fail(MOCHY_ENOMEM);
   for (auto& e : ctx->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(MOCHY_EDEVICE);
+  // the allocation-free call's scratch address on this device; a failure
+  // here is reported by that call (it retries the lookup), not by this one
+  if (noalloc_setup(ctx) != MOCHY_OK) ctx->err.clear();
   int32_t open26[27];
   for (int t = 0; t < 27; ++t) open26[t] = pt.id26_open[t];
   if (hipMemcpy(ctx->d_open26, open26, sizeof(open26), hipMemcpyHostToDevice) != hipSuccess ||
@@ -417,7 +431,7 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     if (ctx->cache_bytes > value) cache_release(ctx);
     return MOCHY_OK;
   }
-  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 1) {
+  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 3) {
     ctx->test_faults = int(value);
     return MOCHY_OK;
   }
@@ -624,6 +638,43 @@ extern "C" mochy_status mochy_count_exact_range(mochy_ctx* ctx, const mochy_grap
   int64_t* d_hist = ctx->d_small + 64;  // [432]
   mochy_status rc = exact_device(ctx, g, c0, c1, d_hist);
   if (rc != MOCHY_OK) return rc;
+  return finish_counts(ctx, d_hist, which, counts26, counts431);
+}
+
+extern "C" mochy_status mochy_count_exact_range_noalloc(mochy_ctx* ctx, const mochy_graph* g,
+                                                        int64_t c0, int64_t c1, uint32_t which,
+                                                        int64_t* counts26, int64_t* counts431) {
+  if (!ctx) return MOCHY_EINVAL;
+  ctx->err.clear();
+  phases_reset(ctx);
+  for (int64_t& v : ctx->exact_stats) v = 0;
+  if (!g || g->ctx != ctx || c0 < 0 || c1 < c0 || c1 > g->E) {
+    ctx->err = "bad graph or centre range";
+    return MOCHY_EINVAL;
+  }
+  if (!which_ok(ctx, which)) return MOCHY_EINVAL;
+  if (g->lg_free) {
+    ctx->err = "exact counting walks stored line-graph rows; this graph was projected without them";
+    return MOCHY_EUNSUPPORTED;
+  }
+  MOCHY_HIP(hipSetDevice(ctx->device));
+  if (!ctx->noalloc_scratch && noalloc_setup(ctx) != MOCHY_OK) return MOCHY_EDEVICE;
+  // every neighbour pair (the groups would need memory in proportion to the
+  // line graph), schedule and light-pair lists carved from the scratch array
+  const bool grouped = ctx->group_neighbours;
+  ctx->group_neighbours = false;
+  ctx->arena = static_cast<char*>(ctx->noalloc_scratch);
+  ctx->arena_cap = (ctx->test_faults & 2) ? (size_t(64) << 10) : kNoallocBytes;
+  ctx->arena_used = 0;
+  int64_t* d_hist = ctx->d_small + 64;  // [432]
+  mochy_status rc = exact_device(ctx, g, c0, c1, d_hist);
+  ctx->group_neighbours = grouped;
+  ctx->arena = nullptr;
+  ctx->arena_cap = ctx->arena_used = 0;
+  if (rc != MOCHY_OK) {
+    (void)hipStreamSynchronize(ctx->stream);  // nothing may still use the scratch array
+    return rc;
+  }
   return finish_counts(ctx, d_hist, which, counts26, counts431);
 }
 

@@ -42,6 +42,11 @@ struct mochy_ctx {
   int batch_launch = 0;               // pair kernel over a batch: 0 size rule, 1 one launch, 2 per graph
   int pair_blocks = 8;                // pair kernel blocks launched per CU (MOCHY_OPT_PAIR_BLOCKS)
   int test_faults = 0;                // MOCHY_OPT_TEST_FAULTS bits (forced fallbacks)
+  // allocation-free calls: device_alloc carves from this device's static
+  // scratch array (bump allocation, reset per call; device_free does nothing)
+  char* arena = nullptr;              // nullptr: ordinary allocation
+  size_t arena_cap = 0, arena_used = 0;
+  void* noalloc_scratch = nullptr;    // this device's scratch array (from hipGetSymbolAddress)
   // freed transient buffers of at least kCacheMinBytes kept for reuse on this
   // context's stream (MOCHY_OPT_CACHE_BYTES): size -> block, and the size of
   // every block handed out from or destined for the cache
@@ -176,6 +181,10 @@ constexpr int kFlagInval = 1, kFlagRange = 2, kFlagDup = 4;
 void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp,
                                hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
+// Fills `bytes` (a multiple of 4) with a 32-bit pattern by a kernel on the
+// stream.  Used instead of hipMemsetAsync on the exact counting path, which
+// callers of the allocation-free entry point may record into a HIP graph.
+void launch_fill_u32(void* p, uint32_t value, size_t bytes, hipStream_t s);
 
 // project.hip: validation, transpose and heavy nodes (project_incidence),
 // then the line graph
@@ -216,6 +225,11 @@ mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t 
 // hyperedge profiles of [c0, c1): d_prof[(c1-c0) x kHistSlots], d_prof26[(c1-c0) x 26]
 mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                              int64_t* d_prof, int64_t* d_prof26);
+
+// noalloc.hip: the static scratch array of this device (looked up once per
+// device at context creation) and its size
+mochy_status noalloc_setup(mochy_ctx* ctx);
+extern const size_t kNoallocBytes;
 
 // api.hip helpers: allocation and release ordered on the context stream
 mochy_status device_alloc(mochy_ctx* ctx, void** p, size_t bytes);

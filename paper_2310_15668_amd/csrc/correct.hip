@@ -326,7 +326,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* poff = ocount + (E + 1);
   int64_t* tmp = poff + (E + 1);
   int32_t* owners = (int32_t*)(buf + n64 * 8);
-  MOCHY_HIP_OR(hipMemsetAsync(buf, 0, (size_t(E) + 1 + size_t(E + 1)) * 8, st), done);
+  launch_fill_u32(buf, 0u, (size_t(E) + 1 + size_t(E + 1)) * 8, st);
   const unsigned wblocks = blocks(V * 64, 256);
   k_light_pairs<false><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                 g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
@@ -346,7 +346,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) return done(rc);
   // scatter owner offsets to hyperedge ids, reset counters, fill
   k_owner_offsets<<<blocks(nowners, 256), 256, 0, st>>>(nowners, owners, poff, eoff);
-  MOCHY_HIP_OR(hipMemsetAsync(pcount, 0, size_t(E) * 8, st), done);
+  launch_fill_u32(pcount, 0u, size_t(E) * 8, st);
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);

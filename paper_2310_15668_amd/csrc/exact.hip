@@ -848,8 +848,8 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* tmp = S.rstart + (rows + 1);
   S.order = (int32_t*)(S.scratch + n8 * 8);
   S.rows = rows;
-  MOCHY_HIP(hipMemsetAsync(S.scratch, 0, (size_t(ng) * NB * 4 + size_t(ng) * 3 + 2) * 8, st));
-  MOCHY_HIP(hipMemsetAsync(S.order, 0xff, size_t(rows) * 4, st));
+  launch_fill_u32(S.scratch, 0u, (size_t(ng) * NB * 4 + size_t(ng) * 3 + 2) * 8, st);
+  launch_fill_u32(S.order, 0xffffffffu, size_t(rows) * 4, st);
   k_sched_count<<<blocks(rows, 256), 256, 0, st>>>(c0, c1, int32_t(NB), row_ptr, min_len, g->row_graph,
                                                    nbhist);
   k_sched_scan<<<unsigned(ng), 1024, 0, st>>>(maxnb, nbhist, cnt, item_start, total);
@@ -908,8 +908,8 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
       (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)gna, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK)
     return fail(rc);
-  MOCHY_HIP_OR(hipMemsetAsync(cntarr, 0, size_t(E + 1) * 8, st), fail);
-  MOCHY_HIP_OR(hipMemsetAsync(ctx->d_flags + 3, 0, 4, st), fail);
+  launch_fill_u32(cntarr, 0u, size_t(E + 1) * 8, st);
+  launch_fill_u32(ctx->d_flags + 3, 0u, 4, st);
   if (by_rows && ((ctx->test_faults & 1) ||
                   device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16) != MOCHY_OK ||
                   device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8) != MOCHY_OK)) {
@@ -971,8 +971,8 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   hipStream_t st = ctx->stream;
   const int ng = g->ng;
   unsigned long long* stats = (unsigned long long*)(ctx->d_small + kExactStatsSlot);
-  MOCHY_HIP(hipMemsetAsync(d_hist, 0, size_t(ng) * kHistSlots * 8, st));
-  MOCHY_HIP(hipMemsetAsync(stats, 0, MOCHY_NUM_EXACT_STATS * 8, st));
+  launch_fill_u32(d_hist, 0u, size_t(ng) * kHistSlots * 8, st);
+  launch_fill_u32(stats, 0u, MOCHY_NUM_EXACT_STATS * 8, st);
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
   if (g->max_deg >= (1 << 24)) {  // group sizes are multiplied as 24-bit numbers
     ctx->err = "a line-graph row of 2^24 or more neighbours";
@@ -994,7 +994,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
       grouped = false;
       ctx->err.clear();
-      MOCHY_HIP(hipMemsetAsync(stats, 0, MOCHY_NUM_EXACT_STATS * 8, st));
+      launch_fill_u32(stats, 0u, MOCHY_NUM_EXACT_STATS * 8, st);
     } else if (rc != MOCHY_OK) {
       return rc;
     }
@@ -1033,7 +1033,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   }
   if (!hgq.empty()) {
     if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) return release(rc);
-    MOCHY_HIP_OR(hipMemsetAsync(gqueue, 0, size_t(ng) * 8, st), release);
+    launch_fill_u32(gqueue, 0u, size_t(ng) * 8, st);
     for (int gi = 0; gi < ng; ++gi) {
       const int64_t items = hgq[gi + 1] - hgq[gi];
       if (items <= 0) continue;

@@ -1,6 +1,8 @@
 // Exclusive prefix sum of int64 arrays (row pointers of the CSR structures).
 // Tile of 1024 elements per 256-thread block, tile sums scanned recursively,
 // then added back.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -35,6 +37,11 @@ __global__ __launch_bounds__(256) void k_scan_tile(const int64_t* in, int64_t* o
   if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
 }
 
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < n; x += int64_t(gridDim.x) * blockDim.x)
+    p[x] = v;
+}
+
 __global__ void k_add_tile_offsets(int64_t* out, int64_t n, const int64_t* __restrict__ offs) {
   const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (x < n) out[x] += offs[x / kTile];
@@ -61,4 +68,11 @@ void launch_exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64
     launch_exclusive_scan_i64(tmp, tmp, tiles, tmp + tiles + 1, s);
     k_add_tile_offsets<<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(out, n, tmp);
   }
+}
+
+void launch_fill_u32(void* p, uint32_t value, size_t bytes, hipStream_t s) {
+  const int64_t n = int64_t(bytes / 4);
+  if (n <= 0) return;
+  const int64_t nb = std::min<int64_t>((n + 255) / 256, 4096);
+  k_fill_u32<<<dim3(unsigned(nb)), 256, 0, s>>>(static_cast<uint32_t*>(p), value, n);
 }
