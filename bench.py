@@ -18,8 +18,14 @@ light-node correction, and the 457 counts back on the host.
 
 Prints one JSON line.  value = connected triples classified per second
 (sum of all h-motif counts / step time).  The roofline object is for the pair
-kernel, timed with HIP events on the stream it runs on; the CPU baseline is
-the oracle (plain MoCHy-E) on a bounded sample of the same workload.
+kernel (integer-ALU bound: algorithmic operations per pair of neighbour
+groups against the integer VALU rate measured in the same run), timed with
+HIP events on the stream it runs on; correction_roofline is the light-pair
+fix kernel's (bytes against HBM).  The same line carries the batched CP
+comparison (base + 64 copies at --scale, one call against 65 sequential
+calls, identical counts) and a serving stream (--requests at --rate through
+the continuous-batching server, p50/p99 latency), and the CPU baseline: the
+oracle (plain MoCHy-E) on a degree-stratified sample of the same workload.
 """
 import argparse
 import json
@@ -34,6 +40,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PAIR_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "exact.hip")
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_exact_grouped_medium_counters.md")
+FIX_KERNEL_SRC = os.path.join(ROOT, "paper_2310_15668_amd", "csrc", "correct.hip")
+FIX_SUMMARY = os.path.join(ROOT, "profiles", "k_light_fix_medium_counters.md")
 # the on-the-fly enumeration phase: k_enum (free.hip), k_memo and k_msample
 # (memo.hip), their shared walk (walk.h)
 ENUM_SRCS = [os.path.join(ROOT, "paper_2310_15668_amd", "csrc", f) for f in ("free.hip", "memo.hip", "walk.h")]
@@ -72,22 +80,58 @@ def summary_values(summary, source):
     return vals
 
 
-# Integer VALU issue peak: a CU has 4 SIMD16 units, each taking 4 cycles per
-# wave64 instruction, so one wave instruction per CU per cycle.
-NUM_CUS, CLOCK_HZ = 256, 2.4e9
+# Integer vector-ALU ceiling from the chip's unit counts: 256 CUs, each with
+# 4 SIMD units of 16 lanes (one wave64 instruction per CU per cycle), at the
+# 2.4 GHz peak engine clock: 39.3e12 32-bit lane operations per second.  A
+# pure integer-VALU kernel of the pair kernel's instruction mix
+# (mochy_calibrate_valu) sustains about 1.06 of it on the box, so the
+# roofline takes the measured rate, from the same run, as its peak.
+NUM_CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
+VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
+
+# Algorithmic integer operations per unit of the exact pair kernel (Lemma 2's
+# region sizes from the two neighbours' records; every operation a 32-bit
+# lane operation):
+#  * a pair of neighbour groups that both have a member above the centre
+#    (its class is needed in full): the three mask intersections (centre
+#    nodes, two words of heavy outside nodes), two ORs and a compare for the
+#    disjointness test, three population counts and an add (t, R5), six
+#    subtractions for R1, R2, R3, R4, R6, seven min(., 2) for the ternary
+#    states, six multiply-adds for the base-3 code, two for the table lookup
+#    (address, read), four for the weight (two selects, a 48-bit product in
+#    two multiplies) and two for the histogram add (address, add): 36;
+#  * any other pair of groups (counted only when open): three
+#    intersections, two ORs, a compare and a select-add into the run sum: 8.
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 36, 8
+# Algorithmic bytes of the light-pair fix kernel: the partner row's entry
+# (4-byte hyperedge id) for every scanned entry, and for every centre it
+# finds the two 4-byte record masks (rows j and k) and the 4-byte size of e_i.
+FIX_BYTES_SCANNED, FIX_BYTES_CENTRE = 4, 12
 
 
-def valu_issue(kernel_ms):
+def valu_issue(kernel_ms, ceiling):
     """The pair kernel's VALU wave-instructions per launch (SQ_INSTS_VALU from
-    the committed counter summary) over this run's kernel time, against one
-    per CU per cycle; None if the counters are stale."""
+    the committed counter summary) over this run's kernel time, per CU per
+    cycle, beside the calibrated ceiling in the same unit; None if the
+    counters are stale."""
     vals = summary_values(COUNTERS_SUMMARY, PAIR_KERNEL_SRC)
     if vals is None or "SQ_INSTS_VALU" not in vals:
         return None
     n = float(vals["SQ_INSTS_VALU"])
     rate = n / (NUM_CUS * CLOCK_HZ * kernel_ms * 1e-3)
-    return {"valu_wave_instructions_per_launch": n, "per_cu_per_cycle": rate, "peak_per_cu_per_cycle": 1.0,
-            "frac": rate, "source": "profiles/k_exact_grouped_medium_counters.md"}
+    peak = ceiling / (LANES * NUM_CUS * CLOCK_HZ)
+    return {"valu_wave_instructions_per_launch": n, "per_cu_per_cycle": rate,
+            "calibrated_per_cu_per_cycle": peak, "frac": rate / peak,
+            "source": "profiles/k_exact_grouped_medium_counters.md"}
+
+
+def valu_calibration(M, ctx, iters=1 << 16, runs=3):
+    """Best integer-VALU rate (lane operations/s) of mochy_calibrate_valu."""
+    best = 0.0
+    for _ in range(runs):
+        ms, ops = M.mochy_calibrate_valu(ctx, iters)
+        best = max(best, ops / (ms * 1e-3))
+    return best
 
 
 def measured_traffic(summary=None, source=None):
@@ -115,41 +159,92 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(h, seconds):
-    """The oracle (plain MoCHy-E, OpenMP over centres) on a bounded sample of centres."""
+    """The oracle (plain MoCHy-E, OpenMP over centres) timed on this host.
+
+    Threads: every core this process may run on, within the host's share for
+    one GPU (OMP_NUM_THREADS when set).  Medium sample: centres stratified by
+    line-graph degree octave, each octave contributing candidates in
+    proportion to its share of the whole workload's (hubs included, up to
+    centres one core finishes within the time budget), largest first.  Also
+    the whole tiny workload on one thread (the paper's default setting)."""
     import numpy as np
     from oracle import native
+    from workloads import make_config
     try:
-        cores = len(os.sched_getaffinity(0))
+        avail = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        avail = os.cpu_count() or 1
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    cores = max(1, min(avail, share) if share > 0 else avail)
+
+    tiny = make_config("tiny")
+    t0 = time.perf_counter()
+    t26, _, _ = native.mochy_e(tiny, nthreads=1)
+    t_tiny = time.perf_counter() - t0
+
     deg, _ = native.line_graph_degrees(h, cores)
     cand = deg * (deg - 1) // 2
-
-    # centres of bounded size (at most 3e7 candidates each, so no single hub
-    # centre serializes the OpenMP loop over centres), evenly spread
-    cap = 3e7
-    pool = np.nonzero((cand > 0) & (cand <= cap))[0]
-
-    def run(n):
-        n = min(n, pool.size)
-        stride = max(1, pool.size // n)
-        centres = pool[stride // 2::stride][:n].astype(np.int64)
-        t0 = time.perf_counter()
-        c26, _, _ = native.mochy_e_centers(h, centres, nthreads=cores)
-        dt = time.perf_counter() - t0
-        return centres.size, int(c26.sum()), int(cand[centres].sum()), dt
-
-    n, tri, nc, dt = run(4 * cores)  # calibration
-    n = int(max(4 * cores, seconds * n / max(dt, 1e-3)))
-    n, tri, nc, dt = run(n)
+    total = int(cand.sum())
+    # per-core rate from a calibration run of mid-degree centres
+    mid = np.nonzero((deg >= 1000) & (deg < 2000))[0]
+    calib = mid[:: max(1, mid.size // (2 * cores))][: 2 * cores].astype(np.int64)
+    t0 = time.perf_counter()
+    native.mochy_e_centers(h, calib, nthreads=cores)
+    rate_core = max(float(cand[calib].sum()) / ((time.perf_counter() - t0) * cores), 1e5)
+    budget = rate_core * cores * seconds        # candidates the sample may hold
+    cap = rate_core * seconds * 0.9             # one centre within the budget on one core
+    octs = np.floor(np.log2(np.maximum(deg, 1))).astype(np.int64)
+    chosen, rows = [], []
+    for k in range(1, int(octs.max()) + 1):
+        in_oct = np.nonzero((octs == k) & (cand > 0))[0]
+        if in_oct.size == 0:
+            continue
+        want = budget * float(cand[in_oct].sum()) / total
+        ok = in_oct[cand[in_oct] <= cap]
+        if ok.size == 0:
+            rows.append({"degrees": [int(2 ** k), int(2 ** (k + 1) - 1)],
+                         "workload_share": float(cand[in_oct].sum()) / total, "centres": 0,
+                         "sampled_candidates": 0})
+            continue
+        n = int(min(ok.size, max(1, round(want / float(cand[ok].mean())))))
+        pick = ok[np.linspace(0, ok.size - 1, n).round().astype(np.int64)]
+        pick = np.unique(pick)
+        chosen.append(pick)
+        rows.append({"degrees": [int(2 ** k), int(2 ** (k + 1) - 1)],
+                     "workload_share": float(cand[in_oct].sum()) / total, "centres": int(pick.size),
+                     "sampled_candidates": int(cand[pick].sum())})
+    centres = np.concatenate(chosen)
+    centres = centres[np.argsort(-cand[centres], kind="stable")]  # largest start first
+    t0 = time.perf_counter()
+    c26, _, _ = native.mochy_e_centers(h, centres, nthreads=cores)
+    dt = time.perf_counter() - t0
+    tri, nc = int(c26.sum()), int(cand[centres].sum())
+    sampled_share = sum(r["workload_share"] for r in rows if r["centres"])
     return {
         "value": tri / dt, "unit": "triples/s", "cores": cores, "kind": "oracle",
-        "sample": f"{n} evenly spread centres of the medium hypergraph among those with at most "
-                  f"3e7 candidates: {nc} MoCHy-E candidates, {tri} connected triples attributed "
-                  f"to them, {dt:.1f} s",
+        "sample": f"{centres.size} medium centres stratified by line-graph degree octave (each octave's "
+                  f"candidates in proportion to its share of the workload; octaves holding "
+                  f"{100 * sampled_share:.1f} % of the candidates represented, hubs up to degree "
+                  f"{int(deg[centres].max())}): {nc} MoCHy-E candidates ({100.0 * nc / total:.3f} % of "
+                  f"the workload), {tri} connected triples attributed to them, {dt:.1f} s wall",
         "candidates_per_s": nc / dt,
+        "extrapolated_medium_s": total / (nc / dt),
+        "nproc": os.cpu_count(), "affinity_cores": avail, "cpu_model": cpu_model(),
+        "octaves": rows,
+        "tiny_one_thread": {"value": int(t26.sum()) / t_tiny, "unit": "triples/s", "seconds": t_tiny,
+                            "connected_triples": int(t26.sum()), "threads": 1},
     }
 
 
@@ -246,19 +341,19 @@ def large_aplus(args):
     print(json.dumps(out), flush=True)
 
 
-def batched_cp(args):
-    """Significance and CP of the batched base hypergraph against 64
-    stub-matched copies: one mochy_profile call (all 65 graphs projected and
-    counted together) versus 65 sequential project + count calls."""
+def run_batched(scale, steps=1, warmup=1, tune=False):
+    """One mochy_profile call over the batched base hypergraph and its 64
+    stub-matched copies, against 65 sequential project + count calls on the
+    same context (identical counts required); best of `steps` each."""
     import numpy as np
     import torch
     import paper_2310_15668_amd as M
     from workloads import make_config, stub_matching_copy
     from workloads.generators import BATCHED_COPY_SEEDS
 
-    base = make_config("batched_base", scale=args.scale)
+    base = make_config("batched_base", scale=scale)
     graphs = [base] + [stub_matching_copy(base, s) for s in BATCHED_COPY_SEEDS]
-    log(f"scale {args.scale}: base |E|={base.num_edges}, {len(graphs)} graphs, "
+    log(f"batched CP at scale {scale}: base |E|={base.num_edges}, {len(graphs)} graphs, "
         f"{sum(g.num_edges for g in graphs)} hyperedges in all")
     dev = [device_csr(g) for g in graphs]
     torch.cuda.synchronize()
@@ -273,11 +368,11 @@ def batched_cp(args):
             rows.append(np.concatenate([c26, c431]))
         return np.array(rows)
 
-    for w in range(args.warmup):
-        log(f"warmup {w + 1}/{args.warmup}")
+    for w in range(warmup):
+        log(f"batched warmup {w + 1}/{warmup}")
         M.mochy_profile(ctx, dev[:3])
     tuned = None
-    if args.tune:  # the pair kernel's launch shape, timed on this batch (untimed here)
+    if tune:  # the pair kernel's launch shape, timed on this batch (untimed here)
         from paper_2310_15668_amd.tune import tune_batch
         log("tuning the pair kernel's launch shape on the batch")
         res = tune_batch(ctx, dev)
@@ -285,14 +380,14 @@ def batched_cp(args):
                  "pair_ms": {f"launch={a},blocks={b}": t for (a, b), t in res["times"].items()}}
         log(f"tuned: {tuned}")
     times_b, times_s = [], []
-    for s in range(args.steps):
-        log(f"step {s + 1}/{args.steps}: batched")
+    for s in range(steps):
+        log(f"batched step {s + 1}/{steps}: one call")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         counts, sig26, cp26, sig431, cp431 = M.mochy_profile(ctx, dev)
         torch.cuda.synchronize()
         times_b.append(time.perf_counter() - t0)
-        log(f"step {s + 1}/{args.steps}: sequential")
+        log(f"batched step {s + 1}/{steps}: 65 sequential calls")
         t0 = time.perf_counter()
         seq = sequential()
         torch.cuda.synchronize()
@@ -302,46 +397,56 @@ def batched_cp(args):
     ctx.close()
     tb, ts = min(times_b), min(times_s)
     triples = int(counts[:, :26].sum())
-    out = {
-        "metric": "batched CP speedup over 65 sequential project+count calls",
-        "value": ts / tb, "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": tb * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"batched CP: base hypergraph (50,000 nodes, 150,000 drawn hyperedges, "
-                               f"sizes 2..20 P(s)~s^-2.5, Zipf(1.1), seed 3) and 64 stub-matched copies "
-                               f"(seeds 100..163), all scaled by {args.scale}",
-                   "scale": args.scale, "graphs": len(graphs),
-                   "hyperedges": [g.num_edges for g in graphs][:3] + ["..."],
-                   "connected_triples_all_graphs": triples, "parallelism": "single GPU"},
-        "batched_s": tb, "sequential_s": ts,
-        "batched_triples_per_s": triples / tb, "sequential_triples_per_s": triples / ts,
-        "identical_counts": True,
-    }
+    out = {"speedup": ts / tb, "batched_s": tb, "sequential_s": ts, "graphs": len(graphs),
+           "scale": scale, "base_hyperedges": base.num_edges,
+           "hyperedges_all_graphs": int(sum(g.num_edges for g in graphs)),
+           "connected_triples_all_graphs": triples, "batched_triples_per_s": triples / tb,
+           "sequential_triples_per_s": triples / ts, "identical_counts": True, "steps": steps,
+           "workload": f"batched CP: base hypergraph (50,000 nodes, 150,000 drawn hyperedges, sizes 2..20 "
+                       f"P(s)~s^-2.5, Zipf(1.1), seed 3) and 64 stub-matched copies (seeds 100..163), "
+                       f"nodes and hyperedges scaled by {scale}; one mochy_profile call against 65 "
+                       f"sequential project + count calls on one context"}
     if tuned is not None:
         out["tuned"] = tuned
+    return out
+
+
+def batched_cp(args):
+    """Significance and CP of the batched base hypergraph against 64
+    stub-matched copies: one mochy_profile call (all 65 graphs projected and
+    counted together) versus 65 sequential project + count calls."""
+    res = run_batched(args.scale, args.steps, args.warmup, args.tune)
+    out = {
+        "metric": "batched CP speedup over 65 sequential project+count calls",
+        "value": res["speedup"], "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["batched_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": res["workload"], "scale": args.scale, "graphs": res["graphs"],
+                   "parallelism": "single GPU"},
+        "batched": res,
+    }
     print(json.dumps(out), flush=True)
 
 
-def serving(args):
-    """CP requests (a hypergraph + 8 stub-matched copies each) arriving as a
-    Poisson stream, served by the continuous-batching server with `slots`
-    concurrent streams, and the same stream with one slot for comparison."""
+def run_serving(requests, rate, max_edges, slots_list, seed_log_every=50):
+    """A Poisson stream of CP requests (a hypergraph + 8 stub-matched copies
+    each) through the continuous-batching server, once per slot count;
+    answers must not depend on the slot count."""
     import numpy as np
     import torch
     from paper_2310_15668_amd.serving import CPServer
     from workloads import poisson_arrivals, serving_copies, serving_request
 
-    log(f"generating {args.requests} requests (|E| log-uniform in [1000, {args.max_edges}], 8 copies each)")
+    log(f"generating {requests} requests (|E| log-uniform in [1000, {max_edges}], 8 copies each)")
     reqs, sizes = [], []
-    for n in range(args.requests):
-        h = serving_request(n, 1000, args.max_edges)
+    for n in range(requests):
+        h = serving_request(n, 1000, max_edges)
         sizes.append(h.num_edges)
         reqs.append([(g.edge_ptr, g.edge_nodes, g.num_nodes) for g in [h] + serving_copies(n, h, 8)])
-    arrivals = poisson_arrivals(args.requests, args.rate)
+    arrivals = poisson_arrivals(requests, rate)
     torch.cuda.init()
-    runs = {}
-    answers = {}
-    for slots in (args.slots, 1):
+    runs, answers = {}, {}
+    for slots in slots_list:
         with CPServer(0, slots=slots) as srv:
             for t in [srv.submit(r) for r in reqs[:2]]:  # warm-up
                 t.wait()
@@ -354,7 +459,7 @@ def serving(args):
                 tickets.append(srv.submit(r, arrival=t0 + arrivals[n]))
             for k, t in enumerate(tickets):
                 t.wait()
-                if (k + 1) % 50 == 0:
+                if (k + 1) % seed_log_every == 0:
                     log(f"  slots={slots}: {k + 1}/{len(tickets)} answered")
             end = max(t.done for t in tickets)
         lat = np.array([t.latency for t in tickets])
@@ -364,22 +469,32 @@ def serving(args):
                        "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
                        "makespan_s": end - t0, "triples_per_s": triples / (end - t0)}
         log(f"slots={slots}: {runs[slots]}")
-    same = all((a == b).all() for a, b in zip(answers[args.slots], answers[1]))
-    if not same:
-        raise SystemExit("answers differ between the server configurations")
-    best = runs[args.slots]
+    first = answers[slots_list[0]]
+    for slots in slots_list[1:]:
+        if not all((a == b).all() for a, b in zip(first, answers[slots])):
+            raise SystemExit("answers differ between the server configurations")
+    return {"runs": runs, "median_edges": int(np.median(sizes)), "max_edges_drawn": int(max(sizes)),
+            "workload": f"serving CP requests: {requests} hypergraphs, |E| log-uniform in [1000, {max_edges}], "
+                        f"nodes 0.4|E|, sizes 2..25 P(s)~s^-2.5, Zipf(1.0), Poisson arrivals at {rate} req/s, "
+                        f"each request = exact counts of the hypergraph and 8 stub-matched copies -> "
+                        f"significance and CP"}
+
+
+def serving(args):
+    """CP requests arriving as a Poisson stream, served by the
+    continuous-batching server with `slots` concurrent streams, and the same
+    stream with one slot for comparison."""
+    res = run_serving(args.requests, args.rate, args.max_edges, [args.slots, 1])
+    best = res["runs"][args.slots]
     out = {
         "metric": "CP requests served/s (p50/p99 latency beside)",
         "value": best["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": best["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"serving CP requests: {args.requests} hypergraphs, |E| log-uniform in "
-                               f"[1000, {args.max_edges}], nodes 0.4|E|, sizes 2..25 P(s)~s^-2.5, "
-                               f"Zipf(1.0), Poisson arrivals at {args.rate} req/s, each request = exact "
-                               f"counts of the hypergraph and 8 stub-matched copies -> significance and CP",
-                   "slots": args.slots, "median_edges": int(np.median(sizes)), "parallelism": "single GPU"},
+        "config": {"workload": res["workload"], "slots": args.slots, "median_edges": res["median_edges"],
+                   "parallelism": "single GPU"},
         "p50_s": best["p50_s"], "p99_s": best["p99_s"],
-        "continuous_batching": runs[args.slots], "one_slot": runs[1],
+        "continuous_batching": best, "one_slot": res["runs"][1],
         "answers_identical_across_configurations": True,
     }
     print(json.dumps(out), flush=True)
@@ -489,7 +604,8 @@ def main():
                     help="large-aplus: samples per step (default 5%% of the hyperwedges)")
     ap.add_argument("--seed", type=int, default=2, help="large-aplus: Philox key")
     ap.add_argument("--scale", type=float, default=0.2,
-                    help="batched-cp: scale of the base hypergraph and its copies")
+                    help="batched-cp (and the batched part of medium-exact): scale of the base "
+                         "hypergraph and its copies")
     ap.add_argument("--tune", action="store_true",
                     help="batched-cp: pick the pair kernel's launch shape by timing before the steps")
     ap.add_argument("--requests", type=int, default=200, help="serving: requests in the stream")
@@ -497,8 +613,12 @@ def main():
     ap.add_argument("--max-edges", type=int, default=20000,
                     help="serving: largest request (hyperedges; the stream's range is [1000, max])")
     ap.add_argument("--slots", type=int, default=4, help="serving: concurrent streams of the server")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="medium-exact: leave out the batched CP comparison")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="medium-exact: leave out the serving stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -527,7 +647,13 @@ def main():
     if args.workload == "tradeoff":
         tradeoff(args)
         return
+    medium_exact(args)
 
+
+def medium_exact(args):
+    """The default line: exact counts of the medium workload (value), the pair
+    kernel's ALU roofline, the correction kernel's byte roofline, the oracle's
+    CPU baseline, and the batched CP and serving measurements beside."""
     import numpy as np
     import torch
     import paper_2310_15668_amd as M
@@ -554,6 +680,7 @@ def main():
             for k in phase_sum:
                 phase_sum[k] += ph[k] + ph2[k]
         result["c26"], result["c431"] = c26, c431
+        result["exact_stats"] = M.mochy_exact_stats(ctx)
         if "stats" not in result:
             result["stats"] = M.mochy_graph_stats(ctx, g)
         g.close()
@@ -570,18 +697,23 @@ def main():
     dt = time.perf_counter() - t0
     K = max(args.steps, 1)
     ms_step = dt * 1e3 / K
+    log("integer VALU calibration")
+    valu_peak = valu_calibration(M, ctx)
+    ctx.close()
 
     c26 = result["c26"]
     st = result["stats"]
+    xs = result["exact_stats"]
     triples = int(c26.sum())
-    open_ids = [t for t in range(17, 23)]
-    s_open = int(sum(c26[t - 1] for t in open_ids))
+    s_open = int(sum(c26[t - 1] for t in range(17, 23)))
     s_closed = triples - s_open
     identity_ok = (s_open + 3 * s_closed) == st["candidates"]
 
     pair_ms = phase_sum["exact_pairs"] / K
-    alg_bytes = 8 * st["candidates"] + 4 * st["candidate_min_size_sum"]
-    achieved = alg_bytes / (pair_ms * 1e-3) / 1e9
+    ops = OPS_FULL_PAIR * xs["group_pairs_full"] + OPS_OPEN_PAIR * xs["group_pairs_open"]
+    achieved = ops / (pair_ms * 1e-3)
+    fix_ms = phase_sum["exact_fix_kernel"] / K
+    fix_bytes = FIX_BYTES_SCANNED * xs["fix_scanned"] + FIX_BYTES_CENTRE * xs["fix_centres"]
     out = {
         "metric": "connected triples classified/s",
         "value": triples / (dt / K),
@@ -594,16 +726,42 @@ def main():
                    "incidences": st["nnz"], "hyperwedges": st["hyperwedges"],
                    "max_line_degree": st["max_line_degree"], "candidates": st["candidates"],
                    "connected_triples": triples, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "k_exact_grouped (MoCHy-E pairs of neighbour groups)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "model": "8 + 4*min(|e_i|,|e_j|,|e_k|) bytes per MoCHy-E candidate",
-                     "kernel_ms": pair_ms, "candidates_per_s": st["candidates"] / (pair_ms * 1e-3),
-                     "valu_issue": valu_issue(pair_ms)},
+        "roofline": {"bound": "alu", "kernel": "k_exact_grouped (MoCHy-E pairs of neighbour groups)",
+                     "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
+                     "frac": achieved / valu_peak, "traffic": measured_traffic(),
+                     "model": f"{OPS_FULL_PAIR} integer lane operations per pair of neighbour groups "
+                              f"classified in full, {OPS_OPEN_PAIR} per other pair (counted only when open)",
+                     "peak_source": "integer VALU rate of mochy_calibrate_valu measured in this run "
+                                    f"(chip-derived: 256 CUs x 64 lanes x 2.4 GHz = "
+                                    f"{VALU_PEAK_DERIVED / 1e12:.1f} TOP/s)",
+                     "peak_derived": VALU_PEAK_DERIVED / 1e12,
+                     "kernel_ms": pair_ms, "group_pairs_full": xs["group_pairs_full"],
+                     "group_pairs_open": xs["group_pairs_open"],
+                     "candidates_per_s": st["candidates"] / (pair_ms * 1e-3),
+                     "valu_issue": valu_issue(pair_ms, valu_peak)},
+        "correction_roofline": {"bound": "hbm", "kernel": "k_light_fix (light-pair correction)",
+                                "achieved": fix_bytes / (fix_ms * 1e-3) / 1e9 if fix_ms else None,
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": fix_bytes / (fix_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if fix_ms else None,
+                                "traffic": measured_traffic(FIX_SUMMARY, FIX_KERNEL_SRC),
+                                "model": f"{FIX_BYTES_SCANNED} B per scanned row entry + {FIX_BYTES_CENTRE} B "
+                                         "per centre examined",
+                                "kernel_ms": fix_ms, "scanned_entries": xs["fix_scanned"],
+                                "centres": xs["fix_centres"], "light_pairs": xs["light_pairs"]},
+        "exact_stats": xs,
         "phases_ms": {k: v / K for k, v in phase_sum.items() if v},
         "identity_open_plus_3closed_eq_candidates": bool(identity_ok),
     }
-    ctx.close()
+    if not args.no_batched:
+        log("batched CP comparison")
+        out["batched_cp"] = run_batched(args.scale, steps=1, warmup=1)
+    if not args.no_serving:
+        log("serving stream")
+        res = run_serving(args.requests, args.rate, args.max_edges, [args.slots])
+        run = res["runs"][args.slots]
+        out["serving"] = {"requests_per_s": run["requests_per_s"], "p50_s": run["p50_s"], "p99_s": run["p99_s"],
+                          "mean_s": run["mean_s"], "slots": args.slots, "requests": args.requests,
+                          "median_edges": res["median_edges"], "workload": res["workload"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(h, args.cpu_seconds)

@@ -298,9 +298,10 @@ mochy_status mochy_graph_stats(mochy_ctx* ctx, const mochy_graph* g, int64_t* ou
  * lists and heavy-node tables), 4 region records,
  * 5 exact scheduling, 6 exact pair kernel, 7 exact light-node correction,
  * 8 sampling draws (line-graph-free mode: with grouping by row and the pick
- * of e_j), 9 sampled enumeration, 10 profile significance + CP.
+ * of e_j), 9 sampled enumeration, 10 profile significance + CP, 11 the
+ * light-pair fix kernel alone (part of phase 7).
  * ms: host, MOCHY_NUM_PHASES doubles. */
-#define MOCHY_NUM_PHASES 11
+#define MOCHY_NUM_PHASES 12
 mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);
 
 /* What the most recent exact counting call (mochy_count_exact, _range, or

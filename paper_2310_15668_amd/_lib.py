@@ -49,9 +49,9 @@ NUM_EXACT_STATS = 11
 EXACT_STATS = ("rows_grouped", "groups", "groups_above", "group_pairs_full", "group_pairs_open",
                "rows_regrouped", "max_hash_parts", "light_pairs", "fix_scanned", "fix_centres",
                "fix_changed")
-NUM_PHASES = 11
+NUM_PHASES = 12
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
-          "exact_correct", "sample_draw", "sample_enum", "profile_cp")
+          "exact_correct", "sample_draw", "sample_enum", "profile_cp", "exact_fix_kernel")
 
 
 class MochyError(RuntimeError):

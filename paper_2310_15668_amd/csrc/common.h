@@ -86,7 +86,7 @@ enum ExactStat { kStRows = 0, kStGroups, kStGroupsAbove, kStPairsFull, kStPairsO
 
 // Phase timing: bracket device work on the context stream.
 enum Phase { kPhUpload = 0, kPhTranspose, kPhDegree, kPhRows, kPhRecords, kPhSched, kPhPairs,
-             kPhCorrect, kPhDraw, kPhSample, kPhProfile };
+             kPhCorrect, kPhDraw, kPhSample, kPhProfile, kPhFix };
 inline void phase_begin(mochy_ctx* c, int p) {
   if (hipEventRecord(c->ev[2 * p], c->stream) == hipSuccess) c->phases_begun |= 1u << p;
 }

@@ -355,10 +355,12 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   // registers, so 4 blocks (32 waves) are resident per CU instead of 3
   if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done(rc);
   k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
+  phase_begin(ctx, kPhFix);
   k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners,
                                                            g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
                                                            g->lg_col, g->recm, esize, ctx->d_code_to_id3,
                                                            (unsigned long long*)d_hist, stats);
+  phase_end(ctx, kPhFix);
   k_fix_scanned<<<blocks(npairs, 256), 256, 0, st>>>(npairs, partners, g->lg_ptr, stats);
   MOCHY_HIP_OR(hipGetLastError(), done);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
