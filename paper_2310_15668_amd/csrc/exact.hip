@@ -322,14 +322,27 @@ __global__ __launch_bounds__(256) void k_exact_main(
 // e_i, so never disjoint).  Pairs sharing a light node are corrected from the
 // ungrouped records afterwards, as before.
 //
-// One 512-thread block per row groups the row's records in an LDS hash table
+// One block per row groups the row's records in an LDS hash table
 // keyed by a 64-bit hash of the signature.  A row longer than the table is
 // cut into parts by the hash (records of one part per pass); a pass whose
 // table fills is redone with twice the parts.  After each pass every record
 // checks its signature against its slot's first member: two signatures with
 // one hash restart the row with another hash seed, so groups are exact.
-constexpr int kGroupThreads = 512;
-constexpr int kGroupSlots = 2048;
+// One 1024-thread block per row with an 8000-slot table (160 KB of LDS, one
+// block per CU): a larger table means fewer hash parts, and every part
+// re-reads the row twice.  On medium this took the grouping from 62 ms
+// (512 threads, 2048 slots: up to 18 parts, 12,805 rows regrouped) to 37 ms
+// (up to 4 parts, 1,398 rows regrouped); 512 threads with 4032 slots (two
+// blocks per CU) took 48 ms.
+constexpr int kGroupThreads = 1024;
+constexpr int kGroupSlots = 8000;
+
+// Home slot of a 64-bit signature hash (multiply-shift range reduction of
+// its low 32 bits, any table size) and the next slot of a linear probe.
+__device__ __forceinline__ uint32_t home_slot(uint64_t kk) {
+  return uint32_t((uint64_t(uint32_t(kk)) * uint32_t(kGroupSlots)) >> 32);
+}
+__device__ __forceinline__ uint32_t next_slot(uint32_t s) { return s + 1u == uint32_t(kGroupSlots) ? 0u : s + 1u; }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   // SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA'14)
@@ -427,7 +440,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         const uint4 rr = row[r];
         const uint64_t kk = sig_hash(rr, clamp_outside(rr), seed);
         if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
-        uint32_t slot = uint32_t(kk) & (kGroupSlots - 1);
+        uint32_t slot = home_slot(kk);
         int n = 0;
         for (; n < kGroupSlots; ++n) {
           const unsigned long long old = atomicCAS(&key[slot], 0ull, kk);
@@ -437,7 +450,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
             break;
           }
           if (old == kk) break;
-          slot = (slot + 1) & (kGroupSlots - 1);
+          slot = next_slot(slot);
         }
         if (n == kGroupSlots) { atomicOr(&s_bad, 1u); continue; }
         atomicAdd(&nall[slot], 1u);
@@ -457,8 +470,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         const uint32_t o = clamp_outside(rr);
         const uint64_t kk = sig_hash(rr, o, seed);
         if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
-        uint32_t slot = uint32_t(kk) & (kGroupSlots - 1);
-        while (key[slot] != kk) slot = (slot + 1) & (kGroupSlots - 1);
+        uint32_t slot = home_slot(kk);
+        while (key[slot] != kk) slot = next_slot(slot);
         const uint4 f = row[first[slot]];
         if (f.x != rr.x || f.z != rr.z || f.w != rr.w || clamp_outside(f) != o) atomicOr(&s_bad, 2u);
       }

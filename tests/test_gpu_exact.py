@@ -242,29 +242,40 @@ def test_grouped_equals_every_pair(ctx):
 
 
 def test_grouping_parts_double(ctx):
-    # a centre of 25 nodes whose 2300 neighbours (every 3-subset of its nodes)
-    # all have distinct signatures: its row's single hash part passes the
-    # per-part group limit, so the row is regrouped with twice the parts, in
-    # the one-pass layout and in the counted-first one
+    # a centre e_0 (nodes 0..24) whose 7,080 neighbours all have distinct
+    # signatures: each neighbour holds one of the centre nodes 0..3 and a
+    # distinct pair of the 60 nodes 100..159 (with nodes 0..3 the 64
+    # highest-degree nodes, so every pair is a distinct heavy mask); the row's
+    # one hash part passes the per-part group limit and is regrouped with two,
+    # in the one-pass layout and in the counted-first one
     import itertools
     import paper_2310_15668_amd as M
-    h = from_edge_lists([list(range(25))] + [list(c) for c in itertools.combinations(range(25), 3)], 25)
+    heavy = list(range(100, 160))
+    edges = [list(range(25))] + [[a, h1, h2] for a in range(4) for h1, h2 in itertools.combinations(heavy, 2)]
+    h = from_edge_lists(edges, 160)
     print(f"[gpu] distinct-signature hub row |E|={h.num_edges}", flush=True)
-    o26, o431, inv = native.mochy_e(h, nthreads=16)
-    assert inv == 0
+    o26, o431, inv = native.mochy_e_centers(h, [0], nthreads=1)
+    assert inv == 0 and o26.sum() > 0
     g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
     try:
-        a26, a431 = M.mochy_count_exact(ctx, g)
+        a26, a431 = M.mochy_count_exact_range(ctx, g, 0, 1)
+        st = M.mochy_exact_stats(ctx)
+        assert st["rows_regrouped"] == 1 and st["max_hash_parts"] == 2, st
+        full_a = M.mochy_count_exact(ctx, g)[1]
         ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 0)
-        b26, b431 = M.mochy_count_exact(ctx, g)
+        b26, b431 = M.mochy_count_exact_range(ctx, g, 0, 1)
+        assert M.mochy_exact_stats(ctx)["rows_regrouped"] == 1
+        full_b = M.mochy_count_exact(ctx, g)[1]
         ctx.set_option(M.MOCHY_OPT_GROUPS, 0)
-        c26, c431 = M.mochy_count_exact(ctx, g)
+        c26, c431 = M.mochy_count_exact_range(ctx, g, 0, 1)
+        full_c = M.mochy_count_exact(ctx, g)[1]
     finally:
         ctx.set_option(M.MOCHY_OPT_GROUPS, 1)
         ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
         g.close()
     for x26, x431 in ((a26, a431), (b26, b431), (c26, c431)):
         assert (x431 == o431).all() and (x26 == o26).all()
+    assert (full_a == full_c).all() and (full_b == full_c).all()
 
 
 def test_which_selector(ctx):
