@@ -96,18 +96,23 @@ __device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
   return int64_t(x) * per + (x < extra ? x : extra) + k;
 }
 
-// One block per owner; 512 threads, so that the LDS the row bitmap takes
-// still leaves room for 24 resident waves per CU (the scan waits on loads).
+// One block per work item, an item being up to kFixChunk partners of one
+// owner (an owner's items are consecutive, so they run at the same time on
+// one XCD and share the owner's row in its L2); 512 threads, so that the LDS
+// the row bitmap takes still leaves room for 24 resident waves per CU (the
+// scan waits on loads).
 constexpr int kFixThreads = 512;
 constexpr int kFixCopies = 2;
+constexpr int kFixChunk = 64;
 
 // At most 64 registers (8 waves per SIMD, room for 4 blocks, 32 waves per CU,
 // when the LDS allows; the scan waits on loads, so resident waves count more
 // than entries per lane).
 __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_light_fix(
     int64_t c0, int64_t c1, const int32_t* __restrict__ row_graph, const int64_t* __restrict__ geoff,
-    const int32_t* __restrict__ owners,
-    const int64_t* __restrict__ poff, const int32_t* __restrict__ partners,
+    const int32_t* __restrict__ owners, const int32_t* __restrict__ item_owner,
+    const int64_t* __restrict__ ioff, const int64_t* __restrict__ poff,
+    const int32_t* __restrict__ partners,
     const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
@@ -121,8 +126,11 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
-  const int64_t ob = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t it = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t ob = item_owner[it];
   const int32_t j = owners[ob];
+  const int64_t p0 = poff[ob] + (it - ioff[ob]) * kFixChunk;  // this item's partners
+  const int64_t p1 = min(poff[ob + 1], p0 + kFixChunk);
   const int gj = row_graph[j];
   const int64_t e0 = geoff[gj];  // row j's graph owns hyperedges [e0, geoff[gj + 1])
   const int nwE = int((geoff[gj + 1] - e0 + 31) / 32);
@@ -174,7 +182,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
   unsigned long long* myhist = hist + (lane & (kFixCopies - 1)) * kHistSlots;
   uint32_t n_centres = 0, n_changed = 0;  // this wave's, for mochy_exact_stats
-  for (int64_t pp = poff[ob] + wave; pp < poff[ob + 1]; pp += kFixThreads / kWave) {
+  for (int64_t pp = p0 + wave; pp < p1; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
     // record of e_k in row j
     const int64_t kl = k - e0;
@@ -285,9 +293,20 @@ __global__ void k_owner_list(int64_t E, const unsigned long long* __restrict__ p
 }
 
 __global__ void k_owner_offsets(int64_t n, const int32_t* __restrict__ owners,
-                                const int64_t* __restrict__ poff, int64_t* eoff) {
+                                const int64_t* __restrict__ poff, int64_t* eoff, int64_t* icount) {
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (s < n) eoff[owners[s]] = poff[s];
+  if (s < n) {
+    eoff[owners[s]] = poff[s];
+    icount[s] = (poff[s + 1] - poff[s] + kFixChunk - 1) / kFixChunk;
+  }
+  if (s == n) icount[n] = 0;
+}
+
+// item_owner[q] = the owner of work item q (items of owner s: [ioff[s], ioff[s + 1])).
+__global__ void k_item_owners(int64_t n, const int64_t* __restrict__ ioff, int32_t* item_owner) {
+  const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  for (int64_t q = ioff[s]; q < ioff[s + 1]; ++q) item_owner[q] = int32_t(s);
 }
 
 inline unsigned blocks(int64_t n, int t) { return unsigned((n + t - 1) / t); }
@@ -311,11 +330,15 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* eoff = nullptr;
   int32_t* partners = nullptr;
   uint32_t* esize = nullptr;
+  int64_t* ioff = nullptr;
+  int32_t* item_owner = nullptr;
   auto done = [&](mochy_status s) {
     device_free(ctx, buf);
     device_free(ctx, eoff);
     device_free(ctx, partners);
     device_free(ctx, esize);
+    device_free(ctx, ioff);
+    device_free(ctx, item_owner);
     return s;
   };
   mochy_status rc = device_alloc(ctx, (void**)&buf, n64 * 8 + size_t(E) * 4);
@@ -344,8 +367,12 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   // per-owner offsets indexed by hyperedge id for the fill pass
   if ((rc = device_alloc(ctx, (void**)&eoff, size_t(E) * 8)) != MOCHY_OK) return done(rc);
   if ((rc = device_alloc(ctx, (void**)&partners, size_t(npairs) * 4)) != MOCHY_OK) return done(rc);
-  // scatter owner offsets to hyperedge ids, reset counters, fill
-  k_owner_offsets<<<blocks(nowners, 256), 256, 0, st>>>(nowners, owners, poff, eoff);
+  if ((rc = device_alloc(ctx, (void**)&ioff, size_t(nowners + 1) * 8)) != MOCHY_OK) return done(rc);
+  // scatter owner offsets to hyperedge ids and count each owner's work items
+  // (ioff holds the counts, then their prefix, in place), reset counters, fill
+  k_owner_offsets<<<blocks(nowners + 1, 256), 256, 0, st>>>(nowners, owners, poff, eoff, ioff);
+  launch_exclusive_scan_i64(ioff, ioff, nowners + 1, tmp, st);
+  MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 506, ioff + nowners, 8, hipMemcpyDeviceToHost, st), done);
   launch_fill_u32(pcount, 0u, size_t(E) * 8, st);
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
@@ -355,8 +382,13 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   // registers, so 4 blocks (32 waves) are resident per CU instead of 3
   if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done(rc);
   k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
+  MOCHY_HIP_OR(hipStreamSynchronize(st), done);
+  const int64_t nitems = ctx->h_small[506];
+  if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK) return done(rc);
+  k_item_owners<<<blocks(nowners, 256), 256, 0, st>>>(nowners, ioff, item_owner);
   phase_begin(ctx, kPhFix);
-  k_light_fix<<<unsigned(nowners), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, poff, partners,
+  k_light_fix<<<unsigned(nitems), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, item_owner,
+                                                          ioff, poff, partners,
                                                            g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
                                                            g->lg_col, g->recm, esize, ctx->d_code_to_id3,
                                                            (unsigned long long*)d_hist, stats);
