@@ -358,14 +358,19 @@ def run_batched(scale, steps=1, warmup=1, tune=False):
     dev = [device_csr(g) for g in graphs]
     torch.cuda.synchronize()
     ctx = M.Context(0, torch.cuda.current_stream().cuda_stream)
+    big = scale >= 0.5  # calls of minutes: progress lines (the library's per sub-batch lines too)
+    if big:
+        os.environ["MOCHY_LOG_BATCHES"] = "1"
 
     def sequential():
         rows = []
-        for p, n, V in dev:
+        for x, (p, n, V) in enumerate(dev):
             g = M.mochy_project(ctx, p, n, V)
             c26, c431 = M.mochy_count_exact(ctx, g)
             g.close()
             rows.append(np.concatenate([c26, c431]))
+            if big and (x + 1) % 8 == 0:
+                log(f"  sequential: {x + 1}/{len(dev)} graphs counted")
         return np.array(rows)
 
     for w in range(warmup):
@@ -387,6 +392,7 @@ def run_batched(scale, steps=1, warmup=1, tune=False):
         counts, sig26, cp26, sig431, cp431 = M.mochy_profile(ctx, dev)
         torch.cuda.synchronize()
         times_b.append(time.perf_counter() - t0)
+        batches = M.mochy_exact_stats(ctx)["profile_batches"]
         log(f"batched step {s + 1}/{steps}: 65 sequential calls")
         t0 = time.perf_counter()
         seq = sequential()
@@ -398,6 +404,7 @@ def run_batched(scale, steps=1, warmup=1, tune=False):
     tb, ts = min(times_b), min(times_s)
     triples = int(counts[:, :26].sum())
     out = {"speedup": ts / tb, "batched_s": tb, "sequential_s": ts, "graphs": len(graphs),
+           "sub_batches": batches,
            "scale": scale, "base_hyperedges": base.num_edges,
            "hyperedges_all_graphs": int(sum(g.num_edges for g in graphs)),
            "connected_triples_all_graphs": triples, "batched_triples_per_s": triples / tb,

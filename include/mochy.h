@@ -110,8 +110,9 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                        mochy_profile) groups each row's neighbours in one
                                        pass into space for all of its records when that
                                        takes at most this many bytes (24 per record; default
-                                       24 GiB), else counts the groups first and allocates
-                                       them exactly; 0 = always count first; same counts */
+                                       half the device memory) and can be allocated, else
+                                       counts the groups first and allocates them exactly;
+                                       0 = always count first; same counts */
 #define MOCHY_OPT_MEMO_BUDGET 3  /* on-the-fly MoCHy-A+ groups its samples by key hyperedge
                                     (the endpoint of larger line-graph degree, Algorithm 9)
                                     and memoizes the neighbourhood counts of keys, in
@@ -145,8 +146,10 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                      grouping's row-capacity allocation report
                                      MOCHY_ENOMEM, so exact counting takes the
                                      counted-first layout; bit 1 caps the scratch of
-                                     mochy_count_exact_range_noalloc at 64 KiB (default
-                                     0); same counts */
+                                     mochy_count_exact_range_noalloc at 64 KiB; bit 2
+                                     makes the grouping of a batch of more than two
+                                     graphs report MOCHY_ENOMEM, so mochy_profile splits
+                                     it (default 0); same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,
@@ -313,10 +316,12 @@ mochy_status mochy_phase_ms(const mochy_ctx* ctx, double* ms);
  * guessed, out[6] most hash parts of one row, out[7] hyperedge pairs sharing
  * a light node (the correction's pairs), out[8] row entries the correction
  * scanned, out[9] common neighbours it examined (centres of a light pair),
- * out[10] of those, the centres whose class it changed.  Zeros for parts a
- * call did not run (out[0..6] when every neighbour was paired).
+ * out[10] of those, the centres whose class it changed, out[11] the
+ * sub-batches a mochy_profile call counted its graphs in (a batch that does
+ * not fit in device memory is split).  Zeros for parts a call did not run
+ * (out[0..6] when every neighbour was paired).
  * out: host, MOCHY_NUM_EXACT_STATS int64. */
-#define MOCHY_NUM_EXACT_STATS 11
+#define MOCHY_NUM_EXACT_STATS 12
 mochy_status mochy_exact_stats(const mochy_ctx* ctx, int64_t* out);
 
 /* Measurement helper (not part of the method): the integer vector-ALU rate

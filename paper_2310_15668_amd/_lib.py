@@ -45,10 +45,10 @@ EXPORTED = ("mochy_ctx_create", "mochy_ctx_destroy", "mochy_last_error", "mochy_
             "mochy_count_sampled_edges", "mochy_hyperedge_profiles", "mochy_exact_stats",
             "mochy_calibrate_valu", "mochy_count_exact_range_noalloc")
 NOALLOC_SCRATCH = 64 << 20
-NUM_EXACT_STATS = 11
+NUM_EXACT_STATS = 12
 EXACT_STATS = ("rows_grouped", "groups", "groups_above", "group_pairs_full", "group_pairs_open",
                "rows_regrouped", "max_hash_parts", "light_pairs", "fix_scanned", "fix_centres",
-               "fix_changed")
+               "fix_changed", "profile_batches")
 NUM_PHASES = 12
 PHASES = ("upload", "transpose", "lg_degree", "lg_rows", "records", "exact_sched", "exact_pairs",
           "exact_correct", "sample_draw", "sample_enum", "profile_cp", "exact_fix_kernel")

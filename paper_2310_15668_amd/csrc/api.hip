@@ -1,5 +1,7 @@
 // C ABI of the library (declared in include/mochy.h).
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -332,6 +334,7 @@ extern "C" mochy_status mochy_ctx_create(int device, void* hip_stream, mochy_ctx
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(MOCHY_EDEVICE);
   ctx->num_cus = prop.multiProcessorCount;
   ctx->cache_limit = int64_t(prop.totalGlobalMem / 2);
+  ctx->group_cap_bytes = int64_t(prop.totalGlobalMem / 2);
   if (hip_stream) {
     ctx->stream = static_cast<hipStream_t>(hip_stream);
   } else {
@@ -431,7 +434,7 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     if (ctx->cache_bytes > value) cache_release(ctx);
     return MOCHY_OK;
   }
-  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 3) {
+  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 7) {
     ctx->test_faults = int(value);
     return MOCHY_OK;
   }
@@ -922,23 +925,36 @@ static mochy_status build_set(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g
   return MOCHY_OK;
 }
 
-// Exact counts of graphs [g0, g1) into d_all[g][kHistSlots]; halves the batch
-// when the device runs out of memory.
+// Exact counts of graphs [g0, g1) into d_all[g][kHistSlots], in consecutive
+// sub-batches: a sub-batch that runs out of device memory (projection or
+// neighbour groups) is halved, and the size that fitted is kept for the rest
+// (graphs of one batch are of similar size).  A single graph whose groups do
+// not fit pairs every neighbour instead.
 static mochy_status profile_counts(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g0, int32_t g1,
                                    int64_t* d_all) {
-  mochy_graph* set = nullptr;
-  mochy_status rc = build_set(ctx, graphs, g0, g1, &set);
-  if (rc == MOCHY_OK) {
-    rc = exact_device(ctx, set, 0, set->E, d_all + int64_t(g0) * kHistSlots);
-    mochy_graph_free(set);
+  int32_t size = g1 - g0;
+  // MOCHY_LOG_BATCHES=1: one line on stderr per sub-batch counted (progress of long calls)
+  const char* lb = std::getenv("MOCHY_LOG_BATCHES");
+  const bool log_batches = lb && lb[0] == '1';
+  for (int32_t a = g0; a < g1;) {
+    const int32_t b = std::min(g1, a + size);
+    mochy_graph* set = nullptr;
+    mochy_status rc = build_set(ctx, graphs, a, b, &set);
+    if (rc == MOCHY_OK) {
+      rc = exact_device(ctx, set, 0, set->E, d_all + int64_t(a) * kHistSlots);
+      mochy_graph_free(set);
+    }
+    if (rc == MOCHY_ENOMEM && b - a > 1) {
+      ctx->err.clear();
+      size = (b - a + 1) / 2;  // halved, rounded up (still smaller: b - a >= 2)
+      continue;
+    }
+    if (rc != MOCHY_OK) return rc;
+    ctx->exact_stats[kStBatches] += 1;
+    if (log_batches) std::fprintf(stderr, "[mochy] profile: graphs [%d, %d) of %d counted\n", a, b, g1);
+    a = b;
   }
-  if (rc == MOCHY_ENOMEM && g1 - g0 > 1) {
-    ctx->err.clear();
-    const int32_t mid = g0 + (g1 - g0) / 2;
-    if ((rc = profile_counts(ctx, graphs, g0, mid, d_all)) != MOCHY_OK) return rc;
-    return profile_counts(ctx, graphs, mid, g1, d_all);
-  }
-  return rc;
+  return MOCHY_OK;
 }
 
 extern "C" mochy_status mochy_profile(mochy_ctx* ctx, int32_t num_graphs, const mochy_csr* graphs,

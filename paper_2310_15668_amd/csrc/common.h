@@ -35,7 +35,8 @@ struct mochy_ctx {
   bool async_alloc = false;           // stream-ordered allocation of graph / scratch buffers
   bool group_neighbours = true;       // exact counting over neighbour groups (MOCHY_OPT_GROUPS)
   bool aplus_rows = false;            // A+ by merging stored rows (MOCHY_OPT_APLUS_ROWS)
-  int64_t group_cap_bytes = int64_t(24) << 30;  // one-pass grouping limit (MOCHY_OPT_GROUP_CAPACITY)
+  int64_t group_cap_bytes = 0;        // one-pass grouping limit (MOCHY_OPT_GROUP_CAPACITY; half the
+                                      // device memory from creation)
   int64_t memo_budget = int64_t(16) << 30;  // key memo arena bytes (MOCHY_OPT_MEMO_BUDGET)
   bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
@@ -82,7 +83,7 @@ struct mochy_ctx {
 constexpr int kSmallSlots = 1024;
 constexpr int kExactStatsSlot = 512;
 enum ExactStat { kStRows = 0, kStGroups, kStGroupsAbove, kStPairsFull, kStPairsOpen, kStRegrouped,
-                 kStMaxParts, kStLightPairs, kStFixScanned, kStFixCentres, kStFixChanged };
+                 kStMaxParts, kStLightPairs, kStFixScanned, kStFixCentres, kStFixChanged, kStBatches };
 
 // Phase timing: bracket device work on the context stream.
 enum Phase { kPhUpload = 0, kPhTranspose, kPhDegree, kPhRows, kPhRecords, kPhSched, kPhPairs,

@@ -985,7 +985,7 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int ng = g->ng;
   unsigned long long* stats = (unsigned long long*)(ctx->d_small + kExactStatsSlot);
   launch_fill_u32(d_hist, 0u, size_t(ng) * kHistSlots * 8, st);
-  launch_fill_u32(stats, 0u, MOCHY_NUM_EXACT_STATS * 8, st);
+  launch_fill_u32(stats, 0u, kStBatches * 8, st);
   if (c1 <= c0 || g->max_deg < 2) return MOCHY_OK;
   if (g->max_deg >= (1 << 24)) {  // group sizes are multiplied as 24-bit numbers
     ctx->err = "a line-graph row of 2^24 or more neighbours";
@@ -1003,11 +1003,15 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   phase_begin(ctx, kPhSched);
   bool grouped = ctx->group_neighbours;
   if (grouped) {
-    rc = build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0, stats);
-    if (rc == MOCHY_ENOMEM) {  // not enough memory for the groups: pair every record
+    rc = (ctx->test_faults & 4) && ng > 2
+             ? MOCHY_ENOMEM  // forced for tests of the batch split
+             : build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0, stats);
+    if (rc == MOCHY_ENOMEM && ng > 1) {
+      return rc;  // a batch: the caller splits it and counts the parts with groups
+    } else if (rc == MOCHY_ENOMEM) {  // not enough memory for one graph's groups: pair every record
       grouped = false;
       ctx->err.clear();
-      launch_fill_u32(stats, 0u, MOCHY_NUM_EXACT_STATS * 8, st);
+      launch_fill_u32(stats, 0u, kStBatches * 8, st);
     } else if (rc != MOCHY_OK) {
       return rc;
     }
@@ -1073,12 +1077,12 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if (rc != MOCHY_OK) return rc;
   phase_end(ctx, kPhCorrect);
   MOCHY_HIP(hipGetLastError());
-  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + kExactStatsSlot, stats, MOCHY_NUM_EXACT_STATS * 8,
+  MOCHY_HIP(hipMemcpyAsync(ctx->h_small + kExactStatsSlot, stats, kStBatches * 8,
                            hipMemcpyDeviceToHost, st));
   MOCHY_HIP(hipStreamSynchronize(st));
   phases_collect(ctx);
   const int64_t* hs = ctx->h_small + kExactStatsSlot;
-  for (int x = 0; x < MOCHY_NUM_EXACT_STATS; ++x)
+  for (int x = 0; x < kStBatches; ++x)  // the device counters (the batch count is the host's)
     ctx->exact_stats[x] = x == kStMaxParts ? std::max(ctx->exact_stats[x], hs[x]) : ctx->exact_stats[x] + hs[x];
   if (grouped) ctx->exact_stats[kStRows] += c1 - c0;
   return MOCHY_OK;

@@ -359,7 +359,7 @@ def test_row_capacity_fallback(ctx):
         g.close()
     assert (a431 == b431).all() and (a26 == b26).all()
     with pytest.raises(M.MochyError):
-        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 4)
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 8)
 
 
 def test_exact_stats(ctx):

@@ -237,3 +237,27 @@ def test_batch_group_layouts(ctx, capacity):
         ctx.set_option(M.MOCHY_OPT_GROUP_CAPACITY, 24 << 30)
     assert (a == sequential(ctx, graphs)).all()
     assert (b == sequential(ctx, small)).all()
+
+
+def test_batch_split_when_memory_runs_out(ctx):
+    # grouping of a batch made to report MOCHY_ENOMEM above two graphs: the
+    # batch is counted in sub-batches of two (halved once, the size kept),
+    # with the same counts, significance and CP
+    import paper_2310_15668_amd as M
+    base = make_config("batched_base", scale=0.02)
+    graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 106)]
+    print(f"[gpu] forced batch split, {len(graphs)} graphs", flush=True)
+    ref = run_profile(ctx, graphs)
+    assert M.mochy_exact_stats(ctx)["profile_batches"] == 1
+    ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 4)
+    try:
+        got = run_profile(ctx, graphs)
+        st = M.mochy_exact_stats(ctx)
+    finally:
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 0)
+    # 7 graphs: 7 fails, 4 fails, then 2 + 2 + 2 + 1
+    assert st["profile_batches"] == 4, st
+    assert (got[0] == ref[0]).all()
+    for x, y in zip(got[1:], ref[1:]):
+        assert np.array_equal(x, y)
+    assert (got[0] == sequential(ctx, graphs)).all()
