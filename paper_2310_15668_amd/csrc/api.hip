@@ -926,32 +926,61 @@ static mochy_status build_set(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g
 }
 
 // Exact counts of graphs [g0, g1) into d_all[g][kHistSlots], in consecutive
-// sub-batches: a sub-batch that runs out of device memory (projection or
-// neighbour groups) is halved, and the size that fitted is kept for the rest
-// (graphs of one batch are of similar size).  A single graph whose groups do
-// not fit pairs every neighbour instead.
+// sub-batches.  The first takes graphs up to kFirstBatchEdges hyperedges;
+// the hyperwedges and device bytes per hyperedge that each one needed (its
+// graph set, and row capacity for one-pass grouping: 24 B per row entry)
+// size the next: at most three quarters of the memory then free (including
+// this context's cached buffers), row capacity within the one-pass limit,
+// and at most kBatchWedges hyperwedges, about what fills the device (a
+// hypergraph of that size already keeps every kernel's grid full, and a
+// sub-batch of such graphs would only need more memory than counting them
+// one by one).  A sub-batch that still runs out of memory is halved.  A
+// single graph whose groups do not fit pairs every neighbour instead.
+constexpr int64_t kFirstBatchEdges = 200000;
+constexpr double kBatchWedges = 1e9;
 static mochy_status profile_counts(mochy_ctx* ctx, const mochy_csr* graphs, int32_t g0, int32_t g1,
                                    int64_t* d_all) {
-  int32_t size = g1 - g0;
   // MOCHY_LOG_BATCHES=1: one line on stderr per sub-batch counted (progress of long calls)
   const char* lb = std::getenv("MOCHY_LOG_BATCHES");
   const bool log_batches = lb && lb[0] == '1';
+  int64_t budget_edges = kFirstBatchEdges;  // hyperedges the next sub-batch may hold
+  int32_t cap = g1 - g0;                    // graphs it may hold (halved on running out)
   for (int32_t a = g0; a < g1;) {
-    const int32_t b = std::min(g1, a + size);
+    int32_t b = a + 1;
+    int64_t edges = std::max<int64_t>(graphs[a].num_edges, 0);
+    while (b < g1 && b - a < cap && edges + std::max<int64_t>(graphs[b].num_edges, 0) <= budget_edges)
+      edges += std::max<int64_t>(graphs[b++].num_edges, 0);
     mochy_graph* set = nullptr;
     mochy_status rc = build_set(ctx, graphs, a, b, &set);
+    double per_edge = 0.0, wedges_per_edge = 0.0;
     if (rc == MOCHY_OK) {
       rc = exact_device(ctx, set, 0, set->E, d_all + int64_t(a) * kHistSlots);
+      if (set->E > 0) {
+        per_edge = (double(set->bytes) + 48.0 * double(set->W)) / double(set->E);
+        wedges_per_edge = double(set->W) / double(set->E);
+      }
       mochy_graph_free(set);
     }
     if (rc == MOCHY_ENOMEM && b - a > 1) {
       ctx->err.clear();
-      size = (b - a + 1) / 2;  // halved, rounded up (still smaller: b - a >= 2)
+      cap = (b - a + 1) / 2;  // halved, rounded up (still smaller: b - a >= 2)
       continue;
     }
     if (rc != MOCHY_OK) return rc;
     ctx->exact_stats[kStBatches] += 1;
     if (log_batches) std::fprintf(stderr, "[mochy] profile: graphs [%d, %d) of %d counted\n", a, b, g1);
+    size_t free_b = 0, total_b = 0;
+    if (per_edge > 0.0 && hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const double avail = 0.75 * (double(free_b) + double(ctx->cache_bytes));
+      double e = avail / per_edge;
+      if (wedges_per_edge > 0.0) {
+        e = std::min(e, double(ctx->group_cap_bytes) / (48.0 * wedges_per_edge));
+        e = std::min(e, kBatchWedges / wedges_per_edge);
+      }
+      budget_edges = std::max<int64_t>(1, int64_t(e));
+    } else {
+      (void)hipGetLastError();
+    }
     a = b;
   }
   return MOCHY_OK;

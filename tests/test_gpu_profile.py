@@ -241,14 +241,14 @@ def test_batch_group_layouts(ctx, capacity):
 
 def test_batch_split_when_memory_runs_out(ctx):
     # grouping of a batch made to report MOCHY_ENOMEM above two graphs: the
-    # batch is counted in sub-batches of two (halved once, the size kept),
-    # with the same counts, significance and CP
+    # batch is counted in sub-batches of two (halved until it fits, the size
+    # kept), with the same counts, significance and CP
     import paper_2310_15668_amd as M
     base = make_config("batched_base", scale=0.02)
     graphs = [base] + [stub_matching_copy(base, s) for s in range(100, 106)]
     print(f"[gpu] forced batch split, {len(graphs)} graphs", flush=True)
     ref = run_profile(ctx, graphs)
-    assert M.mochy_exact_stats(ctx)["profile_batches"] == 1
+    assert M.mochy_exact_stats(ctx)["profile_batches"] == 1  # 7 graphs of ~2,300 hyperedges fit one
     ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 4)
     try:
         got = run_profile(ctx, graphs)
