@@ -328,21 +328,27 @@ __global__ __launch_bounds__(256) void k_exact_main(
 // table fills is redone with twice the parts.  After each pass every record
 // checks its signature against its slot's first member: two signatures with
 // one hash restart the row with another hash seed, so groups are exact.
-// One 1024-thread block per row with an 8000-slot table (160 KB of LDS, one
-// block per CU): a larger table means fewer hash parts, and every part
-// re-reads the row twice.  On medium this took the grouping from 62 ms
-// (512 threads, 2048 slots: up to 18 parts, 12,805 rows regrouped) to 37 ms
-// (up to 4 parts, 1,398 rows regrouped); 512 threads with 4032 slots (two
-// blocks per CU) took 48 ms.
-constexpr int kGroupThreads = 1024;
-constexpr int kGroupSlots = 8000;
+// Two table sizes.  Rows of at most kShortRow records: 512-thread blocks,
+// 2048 slots (41 KB of LDS, three blocks per CU), one block per row over all
+// rows (a longer row's block returns at once).  Longer rows: 1024-thread
+// blocks with 8000 slots (160 KB, one block per CU) over a list of those
+// rows: a larger table means fewer hash parts, and every part re-reads the
+// row twice.  On medium the long-row table took the grouping from 62 ms (all
+// rows at 2048 slots: up to 18 parts, 12,805 rows regrouped) to 37 ms (up to
+// 4 parts); 4032 slots in 512-thread blocks took 48 ms.  Small graphs keep
+// the short-row table, whose blocks clear only 2048 slots and share the CU.
+constexpr int kShortThreads = 512, kShortSlots = 2048;
+constexpr int kLongThreads = 1024, kLongSlots = 8000;
+constexpr int64_t kShortRow = 2 * kShortSlots;
 
 // Home slot of a 64-bit signature hash (multiply-shift range reduction of
 // its low 32 bits, any table size) and the next slot of a linear probe.
+template <int kSlots>
 __device__ __forceinline__ uint32_t home_slot(uint64_t kk) {
-  return uint32_t((uint64_t(uint32_t(kk)) * uint32_t(kGroupSlots)) >> 32);
+  return uint32_t((uint64_t(uint32_t(kk)) * uint32_t(kSlots)) >> 32);
 }
-__device__ __forceinline__ uint32_t next_slot(uint32_t s) { return s + 1u == uint32_t(kGroupSlots) ? 0u : s + 1u; }
+template <int kSlots>
+__device__ __forceinline__ uint32_t next_slot(uint32_t s) { return s + 1u == uint32_t(kSlots) ? 0u : s + 1u; }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
   // SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA'14)
@@ -367,8 +373,6 @@ __device__ __forceinline__ uint64_t sig_hash(const uint4& r, uint32_t o, uint64_
 }
 
 constexpr int kGroupTries = 40;  // restarts before a row gives up (flags bit 0)
-constexpr int kPartRecords = 2 * kGroupSlots;        // records per hash part, first guess
-constexpr int kPartGroups = kGroupSlots * 3 / 4;     // groups per part before the parts double
 
 // Open class of a group: (|its overlap with e_i|, min(outside, 2)); the code
 // of an open pair depends on j only through it.  Below kOpenClasses.
@@ -377,33 +381,38 @@ __device__ __forceinline__ uint32_t open_class(uint32_t m, uint32_t o) {
   return uint32_t(__popc(m)) * 3u + st3(o);
 }
 
-// kWrite: row i's groups go to its region [base[i] - cap0, base[i + 1] - cap0)
-// of grec / gcnt: base = lg_ptr with the row-capacity layout (a row has at
-// most as many groups as records), or the prefix of the counts with cap0 = 0
-// (compact layout, counted by a first pass).  Groups with members above the
-// centre fill the region from its start (their count goes to gna[i]), the
-// others from its end, so that the pair kernel can take the pairs that can
-// only be open apart; within each hash part of the row, both kinds are
-// ordered by open class.  The count goes to gcount[i].
-template <bool kWrite>
-__global__ __launch_bounds__(kGroupThreads) void k_group(
-    int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
-    const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
-    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags,
-    unsigned long long* stats) {
-  __shared__ unsigned long long key[kGroupSlots];
-  __shared__ uint32_t nall[kGroupSlots], nabove[kGroupSlots], first[kGroupSlots];
-  __shared__ uint32_t s_out, s_outb, s_bad, s_cnt;
-  __shared__ uint32_t cfill[2 * kOpenClasses];  // per (above, open class): count, then next slot
+template <int kSlots>
+struct GroupTable {
+  unsigned long long key[kSlots];
+  uint32_t nall[kSlots], nabove[kSlots], first[kSlots];
+  uint32_t s_out, s_outb, s_bad, s_cnt;
+  uint32_t cfill[2 * kOpenClasses];  // per (above, open class): count, then next slot
+};
+
+// Groups of row i with the block's table.  kWrite: row i's groups go to its
+// region [base[i] - cap0, base[i + 1] - cap0) of grec / gcnt: base = lg_ptr
+// with the row-capacity layout (a row has at most as many groups as
+// records), or the prefix of the counts with cap0 = 0 (compact layout,
+// counted by a first pass).  Groups with members above the centre fill the
+// region from its start (their count goes to gna[i]), the others from its
+// end, so that the pair kernel can take the pairs that can only be open
+// apart; within each hash part of the row, both kinds are ordered by open
+// class.  The count goes to gcount[i].  Hash parts: a first guess of
+// 2 * kSlots records per part, doubled whenever a part has more than
+// 3/4 * kSlots groups (rows have 0.38 groups per record on medium).
+template <bool kWrite, int kThreads, int kSlots>
+__device__ __forceinline__ void group_row(
+    GroupTable<kSlots>& T, int64_t i, const int64_t* __restrict__ lg_ptr,
+    const int32_t* __restrict__ up_first, const uint4* __restrict__ rec, int64_t* gcount,
+    const int64_t* __restrict__ obase_of, int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna,
+    int32_t* flags, unsigned long long* stats) {
+  constexpr int64_t kPartRecords = 2 * kSlots;
+  constexpr uint32_t kPartGroups = kSlots * 3 / 4;
   const int tid = threadIdx.x;
-  const int64_t i = c0 + blockIdx.x;
   const int64_t base = lg_ptr[i];
   const int64_t d = lg_ptr[i + 1] - base;
   const int64_t u = up_first[i];
   const uint4* row = rec + base;
-  // hash parts of the row, each grouped in the LDS table: a first guess of
-  // kPartRecords records per part, doubled whenever a part has more than
-  // kPartGroups groups (rows have 0.38 groups per record on medium)
   int64_t parts = (d + kPartRecords - 1) / kPartRecords;
   if (parts < 1) parts = 1;
   const int64_t parts0 = parts;
@@ -420,44 +429,44 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
     }
     __syncthreads();
     if (tid == 0) {
-      s_out = 0u;
-      s_outb = 0u;
+      T.s_out = 0u;
+      T.s_outb = 0u;
     }
     bool redo = false;
     for (int64_t part = 0; part < parts && !redo; ++part) {
-      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
-        key[t] = 0ull;
-        nall[t] = 0u;
-        nabove[t] = 0u;
+      for (int t = tid; t < kSlots; t += kThreads) {
+        T.key[t] = 0ull;
+        T.nall[t] = 0u;
+        T.nabove[t] = 0u;
       }
       if (tid == 0) {
-        s_bad = 0u;
-        s_cnt = 0u;
+        T.s_bad = 0u;
+        T.s_cnt = 0u;
       }
       __syncthreads();
-      for (int64_t r = tid; r < d; r += kGroupThreads) {
-        if (*(volatile uint32_t*)&s_bad) break;  // this part overflowed: the row is redone
+      for (int64_t r = tid; r < d; r += kThreads) {
+        if (*(volatile uint32_t*)&T.s_bad) break;  // this part overflowed: the row is redone
         const uint4 rr = row[r];
         const uint64_t kk = sig_hash(rr, clamp_outside(rr), seed);
         if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
-        uint32_t slot = home_slot(kk);
+        uint32_t slot = home_slot<kSlots>(kk);
         int n = 0;
-        for (; n < kGroupSlots; ++n) {
-          const unsigned long long old = atomicCAS(&key[slot], 0ull, kk);
+        for (; n < kSlots; ++n) {
+          const unsigned long long old = atomicCAS(&T.key[slot], 0ull, kk);
           if (old == 0ull) {
-            first[slot] = uint32_t(r);
-            if (atomicAdd(&s_cnt, 1u) >= uint32_t(kPartGroups)) atomicOr(&s_bad, 4u);
+            T.first[slot] = uint32_t(r);
+            if (atomicAdd(&T.s_cnt, 1u) >= kPartGroups) atomicOr(&T.s_bad, 4u);
             break;
           }
           if (old == kk) break;
-          slot = next_slot(slot);
+          slot = next_slot<kSlots>(slot);
         }
-        if (n == kGroupSlots) { atomicOr(&s_bad, 1u); continue; }
-        atomicAdd(&nall[slot], 1u);
-        if (r >= u) atomicAdd(&nabove[slot], 1u);
+        if (n == kSlots) { atomicOr(&T.s_bad, 1u); continue; }
+        atomicAdd(&T.nall[slot], 1u);
+        if (r >= u) atomicAdd(&T.nabove[slot], 1u);
       }
       __syncthreads();
-      const uint32_t full = s_bad;
+      const uint32_t full = T.s_bad;
       __syncthreads();  // every thread has read the flag before it is written again
       if (full) {  // too many groups in the part: twice the parts
         parts *= 2;
@@ -465,18 +474,18 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         break;
       }
       // every record against its slot's first member
-      for (int64_t r = tid; r < d; r += kGroupThreads) {
+      for (int64_t r = tid; r < d; r += kThreads) {
         const uint4 rr = row[r];
         const uint32_t o = clamp_outside(rr);
         const uint64_t kk = sig_hash(rr, o, seed);
         if (int64_t((kk >> 40) % uint64_t(parts)) != part) continue;
-        uint32_t slot = home_slot(kk);
-        while (key[slot] != kk) slot = next_slot(slot);
-        const uint4 f = row[first[slot]];
-        if (f.x != rr.x || f.z != rr.z || f.w != rr.w || clamp_outside(f) != o) atomicOr(&s_bad, 2u);
+        uint32_t slot = home_slot<kSlots>(kk);
+        while (T.key[slot] != kk) slot = next_slot<kSlots>(slot);
+        const uint4 f = row[T.first[slot]];
+        if (f.x != rr.x || f.z != rr.z || f.w != rr.w || clamp_outside(f) != o) atomicOr(&T.s_bad, 2u);
       }
       __syncthreads();
-      const uint32_t clash = s_bad;
+      const uint32_t clash = T.s_bad;
       __syncthreads();
       if (clash) {  // two signatures with one hash: another seed
         seed += 0x9E3779B97F4A7C15ull;
@@ -484,62 +493,106 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(
         break;
       }
       if (!kWrite) {
-        for (int t = tid; t < kGroupSlots; t += kGroupThreads)
-          if (key[t] != 0ull) atomicAdd(&s_out, 1u);
+        for (int t = tid; t < kSlots; t += kThreads)
+          if (T.key[t] != 0ull) atomicAdd(&T.s_out, 1u);
         __syncthreads();
         continue;
       }
       // counting sort of the part's groups by (above, open class)
-      for (int t = tid; t < 2 * kOpenClasses; t += kGroupThreads) cfill[t] = 0u;
+      for (int t = tid; t < 2 * kOpenClasses; t += kThreads) T.cfill[t] = 0u;
       __syncthreads();
-      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
-        if (key[t] == 0ull) continue;
-        const uint4 f = row[first[t]];
-        atomicAdd(&cfill[(nabove[t] != 0u ? 0 : kOpenClasses) + open_class(f.x, clamp_outside(f))], 1u);
+      for (int t = tid; t < kSlots; t += kThreads) {
+        if (T.key[t] == 0ull) continue;
+        const uint4 f = row[T.first[t]];
+        atomicAdd(&T.cfill[(T.nabove[t] != 0u ? 0 : kOpenClasses) + open_class(f.x, clamp_outside(f))], 1u);
       }
       __syncthreads();
       if (tid < 2 * kWave) {  // exclusive prefix per kind (one wave each), from where its output stands
         static_assert(kOpenClasses == 2 * kWave, "two classes per lane");
         const int kind = tid / kWave, ln = tid % kWave;
-        uint32_t* cf = cfill + kind * kOpenClasses + 2 * ln;
+        uint32_t* cf = T.cfill + kind * kOpenClasses + 2 * ln;
         const uint32_t n0 = cf[0], n1 = cf[1];
         uint32_t inc = n0 + n1;
         for (int off = 1; off < kWave; off <<= 1) {
           const uint32_t up = __shfl_up(inc, off, kWave);
           if (ln >= off) inc += up;
         }
-        const uint32_t start = (kind == 0 ? s_out : s_outb) + inc - (n0 + n1);
+        const uint32_t start = (kind == 0 ? T.s_out : T.s_outb) + inc - (n0 + n1);
         cf[0] = start;
         cf[1] = start + n0;
       }
       __syncthreads();
-      for (int t = tid; t < kGroupSlots; t += kGroupThreads) {
-        if (key[t] == 0ull) continue;
-        const bool above = nabove[t] != 0u;
-        const uint4 f = row[first[t]];
+      for (int t = tid; t < kSlots; t += kThreads) {
+        if (T.key[t] == 0ull) continue;
+        const bool above = T.nabove[t] != 0u;
+        const uint4 f = row[T.first[t]];
         const uint32_t oc = clamp_outside(f);
-        const uint32_t pos = atomicAdd(&cfill[(above ? 0 : kOpenClasses) + open_class(f.x, oc)], 1u);
+        const uint32_t pos = atomicAdd(&T.cfill[(above ? 0 : kOpenClasses) + open_class(f.x, oc)], 1u);
         const int64_t o = above ? obase + pos : oend - 1 - pos;
         grec[o] = make_uint4(f.x, oc, f.z, f.w);
-        gcnt[o] = make_uint2(nall[t], nabove[t]);
+        gcnt[o] = make_uint2(T.nall[t], T.nabove[t]);
       }
       __syncthreads();
       if (tid == 0) {  // both kinds' ends: the last class's next slot
-        s_out = cfill[kOpenClasses - 1];
-        s_outb = cfill[2 * kOpenClasses - 1];
+        T.s_out = T.cfill[kOpenClasses - 1];
+        T.s_outb = T.cfill[2 * kOpenClasses - 1];
       }
       __syncthreads();
     }
     if (!redo) break;
   }
   if (tid == 0) {
-    if (gcount) gcount[i] = int64_t(s_out) + s_outb;
-    if (kWrite) gna[i] = int32_t(s_out);
+    if (gcount) gcount[i] = int64_t(T.s_out) + T.s_outb;
+    if (kWrite) gna[i] = int32_t(T.s_out);
     if (stats) {  // one pass of the row's grouping reports its parts
       if (parts > parts0) atomicAdd(&stats[kStRegrouped], 1ull);
       atomicMax(&stats[kStMaxParts], (unsigned long long)parts);
     }
   }
+  __syncthreads();  // the table is free for the block's next row
+}
+
+// Short rows: one block per row of [c0, c0 + gridDim.x); longer rows are
+// the long-row kernel's.
+template <bool kWrite>
+__global__ __launch_bounds__(kShortThreads) void k_group_short(
+    int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
+    const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats) {
+  __shared__ GroupTable<kShortSlots> T;
+  const int64_t i = c0 + blockIdx.x;
+  if (lg_ptr[i + 1] - lg_ptr[i] > kShortRow) return;  // uniform
+  group_row<kWrite, kShortThreads, kShortSlots>(T, i, lg_ptr, up_first, rec, gcount, obase_of, cap0, grec,
+                                                gcnt, gna, flags, stats);
+}
+
+// Long rows: rows[0 .. *nrows), each block pulling the next from `queue`.
+template <bool kWrite>
+__global__ __launch_bounds__(kLongThreads) void k_group_long(
+    const int32_t* __restrict__ rows, const unsigned long long* __restrict__ nrows,
+    unsigned long long* queue,
+    const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
+    const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats) {
+  __shared__ GroupTable<kLongSlots> T;
+  __shared__ int64_t s_q;
+  const int64_t n = int64_t(*nrows);
+  for (;;) {  // rows pulled from a counter; every block leaves once the list is taken
+    if (threadIdx.x == 0) s_q = int64_t(atomicAdd(queue, 1ull));
+    __syncthreads();
+    const int64_t q = s_q;
+    __syncthreads();
+    if (q >= n) break;
+    group_row<kWrite, kLongThreads, kLongSlots>(T, rows[q], lg_ptr, up_first, rec, gcount, obase_of, cap0,
+                                                grec, gcnt, gna, flags, stats);
+  }
+}
+
+// The rows of [c0, c1) longer than kShortRow, appended to rows[] (any order).
+__global__ void k_long_rows(int64_t c0, int64_t c1, const int64_t* __restrict__ lg_ptr,
+                            int32_t* rows, unsigned long long* nrows) {
+  const int64_t i = c0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < c1 && lg_ptr[i + 1] - lg_ptr[i] > kShortRow) rows[atomicAdd(nrows, 1ull)] = int32_t(i);
 }
 
 // Per-row group statistics of rows [c0, c1): groups, groups with members
@@ -891,6 +944,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int64_t E = g->E;
   int64_t* cntarr = nullptr;
   int64_t* tmp = nullptr;
+  int32_t* longrows = nullptr;
   *goff = nullptr;
   *grec = nullptr;
   *gcnt = nullptr;
@@ -898,6 +952,7 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   auto fail = [&](mochy_status rc) {
     device_free(ctx, cntarr);
     device_free(ctx, tmp);
+    device_free(ctx, longrows);
     device_free(ctx, *goff);
     device_free(ctx, *grec);
     device_free(ctx, *gcnt);
@@ -919,10 +974,18 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if ((rc = device_alloc(ctx, (void**)&cntarr, size_t(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)&tmp, scan_tmp_elems(E + 1) * 8)) != MOCHY_OK ||
       (rc = device_alloc(ctx, (void**)goff, size_t(E + 1) * 8)) != MOCHY_OK ||
-      (rc = device_alloc(ctx, (void**)gna, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK)
+      (rc = device_alloc(ctx, (void**)gna, size_t(std::max<int64_t>(E, 1)) * 4)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&longrows, size_t(std::max<int64_t>(c1 - c0, 1)) * 4)) != MOCHY_OK)
     return fail(rc);
   launch_fill_u32(cntarr, 0u, size_t(E + 1) * 8, st);
   launch_fill_u32(ctx->d_flags + 3, 0u, 4, st);
+  // the rows too long for the short-row table, listed once; two queue
+  // counters (one per grouping pass), all in the context's small scratch
+  unsigned long long* nlong = (unsigned long long*)(ctx->d_small + 508);
+  unsigned long long* lqueue = nlong + 1;  // [2]
+  launch_fill_u32(nlong, 0u, 3 * 8, st);
+  if (c1 > c0) k_long_rows<<<blocks(c1 - c0, 256), 256, 0, st>>>(c0, c1, g->lg_ptr, longrows, nlong);
+  const unsigned lgrid = unsigned(ctx->num_cus);  // one 160 KB block per CU
   if (by_rows && ((ctx->test_faults & 1) ||
                   device_alloc(ctx, (void**)grec, size_t(std::max<int64_t>(cap, 1)) * 16) != MOCHY_OK ||
                   device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(cap, 1)) * 8) != MOCHY_OK)) {
@@ -937,18 +1000,25 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if (by_rows) {
     *gbase = g->lg_ptr;
     *cap0 = row0;
-    if (c1 > c0)
-      k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
-                                                                cntarr, g->lg_ptr, row0, *grec, *gcnt,
-                                                                *gna, ctx->d_flags + 3, stats);
+    if (c1 > c0) {
+      k_group_short<true><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
+          c0, g->lg_ptr, g->up_first, g->rec, cntarr, g->lg_ptr, row0, *grec, *gcnt, *gna, ctx->d_flags + 3, stats);
+      k_group_long<true><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue, g->lg_ptr, g->up_first, g->rec,
+                                                         cntarr, g->lg_ptr, row0, *grec, *gcnt, *gna,
+                                                         ctx->d_flags + 3, stats);
+    }
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
   } else {
     *gbase = *goff;
     *cap0 = 0;
-    if (c1 > c0)
-      k_group<false><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
-                                                                 cntarr, nullptr, 0, nullptr, nullptr,
-                                                                 nullptr, ctx->d_flags + 3, stats);
+    if (c1 > c0) {
+      k_group_short<false><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
+          c0, g->lg_ptr, g->up_first, g->rec, cntarr, nullptr, 0, nullptr, nullptr, nullptr, ctx->d_flags + 3,
+          stats);
+      k_group_long<false><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue, g->lg_ptr, g->up_first,
+                                                          g->rec, cntarr, nullptr, 0, nullptr, nullptr, nullptr,
+                                                          ctx->d_flags + 3, stats);
+    }
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
     MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st), fail);
     MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 1, ctx->d_flags + 3, 4, hipMemcpyDeviceToHost, st), fail);
@@ -959,10 +1029,13 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
         (rc = device_alloc(ctx, (void**)gcnt, size_t(std::max<int64_t>(ngroups, 1)) * 8)) != MOCHY_OK)
       return fail(rc);
     // the same grouping again, written this time (its parts were reported above)
-    if (c1 > c0)
-      k_group<true><<<unsigned(c1 - c0), kGroupThreads, 0, st>>>(c0, g->lg_ptr, g->up_first, g->rec,
-                                                                nullptr, *goff, 0, *grec, *gcnt,
-                                                                *gna, ctx->d_flags + 3, nullptr);
+    if (c1 > c0) {
+      k_group_short<true><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
+          c0, g->lg_ptr, g->up_first, g->rec, nullptr, *goff, 0, *grec, *gcnt, *gna, ctx->d_flags + 3, nullptr);
+      k_group_long<true><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue + 1, g->lg_ptr, g->up_first,
+                                                         g->rec, nullptr, *goff, 0, *grec, *gcnt, *gna,
+                                                         ctx->d_flags + 3, nullptr);
+    }
   }
   if (c1 > c0)
     k_group_stats<<<blocks(c1 - c0, 256), 256, 0, st>>>(c0, c1, *goff, *gna, stats);
@@ -971,8 +1044,10 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   if (*reinterpret_cast<int32_t*>(ctx->h_small + 1) != 0) return fail(MOCHY_ENOMEM);
   device_free(ctx, cntarr);
   device_free(ctx, tmp);
+  device_free(ctx, longrows);
   cntarr = nullptr;
   tmp = nullptr;
+  longrows = nullptr;
   MOCHY_HIP_OR(hipGetLastError(), fail);
   return MOCHY_OK;
 }
