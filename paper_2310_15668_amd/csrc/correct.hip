@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
     const uint32_t* __restrict__ esize, const uint16_t* __restrict__ code_to_id3,
-    unsigned long long* hist_out, unsigned long long* stats) {
+    unsigned long long* hist_out, uint2* tally) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
   // kFixCopies histogram copies, lane l adding to copy l % kFixCopies (fewer
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
   __shared__ uint32_t hmask;
+  __shared__ uint32_t s_tally[2];  // centres examined, centres reclassified
   const int64_t it = xcd_block(blockIdx.x, gridDim.x);
   const int64_t ob = item_owner[it];
   const int32_t j = owners[ob];
@@ -142,6 +143,8 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   for (int t = threadIdx.x; t < kFixCopies * kHistSlots; t += blockDim.x) hist[t] = 0;
   for (int w = threadIdx.x; w < nwE; w += blockDim.x) bm[w] = 0;
   if (threadIdx.x == 0) {
+    s_tally[0] = 0u;
+    s_tally[1] = 0u;
     uint32_t h = 0;
     int n = 0;
     for (int64_t q = edge_ptr[j]; q < edge_ptr[j + 1]; ++q, ++n)
@@ -250,11 +253,12 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
       }
     }
   }
-  if (lane == 0) {
-    atomicAdd(&stats[kStFixCentres], (unsigned long long)n_centres);
-    atomicAdd(&stats[kStFixChanged], (unsigned long long)n_changed);
+  if (lane == 0 && (n_centres | n_changed) != 0u) {
+    atomicAdd(&s_tally[0], n_centres);
+    atomicAdd(&s_tally[1], n_changed);
   }
   __syncthreads();
+  if (threadIdx.x == 0) tally[it] = make_uint2(s_tally[0], s_tally[1]);  // summed by k_fix_tally
   for (int t = threadIdx.x; t < kHistSlots; t += blockDim.x) {
     unsigned long long v = 0;
     for (int c = 0; c < kFixCopies; ++c) v += hist[c * kHistSlots + t];
@@ -262,18 +266,37 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   }
 }
 
-// Row entries the correction scans: the partner row of every light pair.
-__global__ __launch_bounds__(256) void k_fix_scanned(int64_t npairs, const int32_t* __restrict__ partners,
-                                                     const int64_t* __restrict__ lg_ptr,
-                                                     unsigned long long* stats) {
-  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  unsigned long long d = 0;
-  if (p < npairs) {
+// The correction's work counters for mochy_exact_stats: row entries scanned
+// (the partner row of every light pair) and the per-item tallies of the fix
+// kernel, summed over a fixed grid with one atomic per block and counter
+// (atomics on one address from every wave or item would serialize).
+constexpr int kTallyBlocks = 256;
+__global__ __launch_bounds__(256) void k_fix_tally(int64_t npairs, const int32_t* __restrict__ partners,
+                                                   const int64_t* __restrict__ lg_ptr, int64_t nitems,
+                                                   const uint2* __restrict__ tally, unsigned long long* stats) {
+  __shared__ unsigned long long red[3][256 / kWave];
+  unsigned long long v[3] = {0, 0, 0};
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < npairs; p += stride) {
     const int32_t k = partners[p];
-    d = (unsigned long long)(lg_ptr[k + 1] - lg_ptr[k]);
+    v[0] += (unsigned long long)(lg_ptr[k + 1] - lg_ptr[k]);
   }
-  for (int off = kWave / 2; off > 0; off >>= 1) d += __shfl_xor(d, off, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicAdd(&stats[kStFixScanned], d);
+  for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < nitems; q += stride) {
+    v[1] += tally[q].x;
+    v[2] += tally[q].y;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int x = 0; x < 3; ++x) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v[x] += __shfl_xor(v[x], off, kWave);
+    if (lane == 0) red[x][wave] = v[x];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long t = 0;
+    for (int w = 0; w < 256 / kWave; ++w) t += red[threadIdx.x][w];
+    const int slot = threadIdx.x == 0 ? kStFixScanned : threadIdx.x == 1 ? kStFixCentres : kStFixChanged;
+    if (t) atomicAdd(&stats[slot], t);
+  }
 }
 
 // esize[x] = |e_x|.
@@ -332,6 +355,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   uint32_t* esize = nullptr;
   int64_t* ioff = nullptr;
   int32_t* item_owner = nullptr;
+  uint2* tally = nullptr;
   auto done = [&](mochy_status s) {
     device_free(ctx, buf);
     device_free(ctx, eoff);
@@ -339,6 +363,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
     device_free(ctx, esize);
     device_free(ctx, ioff);
     device_free(ctx, item_owner);
+    device_free(ctx, tally);
     return s;
   };
   mochy_status rc = device_alloc(ctx, (void**)&buf, n64 * 8 + size_t(E) * 4);
@@ -384,16 +409,18 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t nitems = ctx->h_small[506];
-  if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK) return done(rc);
+  if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK ||
+      (rc = device_alloc(ctx, (void**)&tally, size_t(nitems) * 8)) != MOCHY_OK)
+    return done(rc);
   k_item_owners<<<blocks(nowners, 256), 256, 0, st>>>(nowners, ioff, item_owner);
   phase_begin(ctx, kPhFix);
   k_light_fix<<<unsigned(nitems), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, item_owner,
                                                           ioff, poff, partners,
                                                            g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
                                                            g->lg_col, g->recm, esize, ctx->d_code_to_id3,
-                                                           (unsigned long long*)d_hist, stats);
+                                                           (unsigned long long*)d_hist, tally);
   phase_end(ctx, kPhFix);
-  k_fix_scanned<<<blocks(npairs, 256), 256, 0, st>>>(npairs, partners, g->lg_ptr, stats);
+  k_fix_tally<<<kTallyBlocks, 256, 0, st>>>(npairs, partners, g->lg_ptr, nitems, tally, stats);
   MOCHY_HIP_OR(hipGetLastError(), done);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   return done(MOCHY_OK);

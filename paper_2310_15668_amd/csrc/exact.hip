@@ -401,11 +401,11 @@ struct GroupTable {
 // 2 * kSlots records per part, doubled whenever a part has more than
 // 3/4 * kSlots groups (rows have 0.38 groups per record on medium).
 template <bool kWrite, int kThreads, int kSlots>
-__device__ __forceinline__ void group_row(
+__device__ __forceinline__ int64_t group_row(
     GroupTable<kSlots>& T, int64_t i, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ up_first, const uint4* __restrict__ rec, int64_t* gcount,
     const int64_t* __restrict__ obase_of, int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna,
-    int32_t* flags, unsigned long long* stats) {
+    int32_t* flags) {
   constexpr int64_t kPartRecords = 2 * kSlots;
   constexpr uint32_t kPartGroups = kSlots * 3 / 4;
   const int tid = threadIdx.x;
@@ -425,7 +425,8 @@ __device__ __forceinline__ void group_row(
         atomicOr(flags, 1);
         if (gcount) gcount[i] = 0;
       }
-      return;
+      __syncthreads();
+      return 0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -544,12 +545,9 @@ __device__ __forceinline__ void group_row(
   if (tid == 0) {
     if (gcount) gcount[i] = int64_t(T.s_out) + T.s_outb;
     if (kWrite) gna[i] = int32_t(T.s_out);
-    if (stats) {  // one pass of the row's grouping reports its parts
-      if (parts > parts0) atomicAdd(&stats[kStRegrouped], 1ull);
-      atomicMax(&stats[kStMaxParts], (unsigned long long)parts);
-    }
   }
   __syncthreads();  // the table is free for the block's next row
+  return parts > parts0 ? -parts : parts;  // the parts used, negative if the row was regrouped
 }
 
 // Short rows: one block per row of [c0, c0 + gridDim.x); longer rows are
@@ -562,8 +560,14 @@ __global__ __launch_bounds__(kShortThreads) void k_group_short(
   __shared__ GroupTable<kShortSlots> T;
   const int64_t i = c0 + blockIdx.x;
   if (lg_ptr[i + 1] - lg_ptr[i] > kShortRow) return;  // uniform
-  group_row<kWrite, kShortThreads, kShortSlots>(T, i, lg_ptr, up_first, rec, gcount, obase_of, cap0, grec,
-                                                gcnt, gna, flags, stats);
+  const int64_t p = group_row<kWrite, kShortThreads, kShortSlots>(T, i, lg_ptr, up_first, rec, gcount, obase_of,
+                                                                  cap0, grec, gcnt, gna, flags);
+  // one pass of the grouping reports the parts; a row of one part is the
+  // common case and needs no report (the host's maximum starts at 1)
+  if (stats && threadIdx.x == 0 && (p < 0 || p > 1)) {
+    if (p < 0) atomicAdd(&stats[kStRegrouped], 1ull);
+    atomicMax(&stats[kStMaxParts], (unsigned long long)(p < 0 ? -p : p));
+  }
 }
 
 // Long rows: rows[0 .. *nrows), each block pulling the next from `queue`.
@@ -577,14 +581,21 @@ __global__ __launch_bounds__(kLongThreads) void k_group_long(
   __shared__ GroupTable<kLongSlots> T;
   __shared__ int64_t s_q;
   const int64_t n = int64_t(*nrows);
+  unsigned long long regrouped = 0, most = 0;  // this block's rows (thread 0's copy is used)
   for (;;) {  // rows pulled from a counter; every block leaves once the list is taken
     if (threadIdx.x == 0) s_q = int64_t(atomicAdd(queue, 1ull));
     __syncthreads();
     const int64_t q = s_q;
     __syncthreads();
     if (q >= n) break;
-    group_row<kWrite, kLongThreads, kLongSlots>(T, rows[q], lg_ptr, up_first, rec, gcount, obase_of, cap0,
-                                                grec, gcnt, gna, flags, stats);
+    const int64_t p = group_row<kWrite, kLongThreads, kLongSlots>(T, rows[q], lg_ptr, up_first, rec, gcount,
+                                                                  obase_of, cap0, grec, gcnt, gna, flags);
+    regrouped += p < 0 ? 1ull : 0ull;
+    most = max(most, (unsigned long long)(p < 0 ? -p : p));
+  }
+  if (stats && threadIdx.x == 0 && most > 0) {
+    if (regrouped) atomicAdd(&stats[kStRegrouped], regrouped);
+    atomicMax(&stats[kStMaxParts], most);
   }
 }
 
@@ -609,13 +620,18 @@ __global__ __launch_bounds__(256) void k_group_stats(int64_t c0, int64_t c1, con
   }
   unsigned long long v[4] = {ng, na, na * (na - (na ? 1 : 0)) / 2,
                              ng * (ng - (ng ? 1 : 0)) / 2 - na * (na - (na ? 1 : 0)) / 2};
-  for (int x = 0; x < 4; ++x)
+  __shared__ unsigned long long red[4][256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int x = 0; x < 4; ++x) {
     for (int off = kWave / 2; off > 0; off >>= 1) v[x] += __shfl_xor(v[x], off, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    if (v[0]) atomicAdd(&stats[kStGroups], v[0]);
-    if (v[1]) atomicAdd(&stats[kStGroupsAbove], v[1]);
-    if (v[2]) atomicAdd(&stats[kStPairsFull], v[2]);
-    if (v[3]) atomicAdd(&stats[kStPairsOpen], v[3]);
+    if (lane == 0) red[x][wave] = v[x];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {  // one atomic per block and counter
+    unsigned long long t = 0;
+    for (int w = 0; w < 256 / kWave; ++w) t += red[threadIdx.x][w];
+    const int slot = kStGroups + int(threadIdx.x);  // groups, above, full pairs, open pairs
+    if (t) atomicAdd(&stats[slot], t);
   }
 }
 
@@ -1159,6 +1175,10 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   const int64_t* hs = ctx->h_small + kExactStatsSlot;
   for (int x = 0; x < kStBatches; ++x)  // the device counters (the batch count is the host's)
     ctx->exact_stats[x] = x == kStMaxParts ? std::max(ctx->exact_stats[x], hs[x]) : ctx->exact_stats[x] + hs[x];
-  if (grouped) ctx->exact_stats[kStRows] += c1 - c0;
+  if (grouped) {
+    ctx->exact_stats[kStRows] += c1 - c0;
+    // rows of one hash part are not reported by the kernels
+    ctx->exact_stats[kStMaxParts] = std::max<int64_t>(ctx->exact_stats[kStMaxParts], 1);
+  }
   return MOCHY_OK;
 }
