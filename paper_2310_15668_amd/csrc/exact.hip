@@ -530,7 +530,10 @@ __device__ __forceinline__ int64_t group_row(
         const uint32_t oc = clamp_outside(f);
         const uint32_t pos = atomicAdd(&T.cfill[(above ? 0 : kOpenClasses) + open_class(f.x, oc)], 1u);
         const int64_t o = above ? obase + pos : oend - 1 - pos;
-        grec[o] = make_uint4(f.x, oc, f.z, f.w);
+        // y: clamped outside count (bits 0-7), |m| (8-15) and the open class
+        // (16-22), which the pair kernel then reads instead of recomputing
+        // them per pair with scalar instructions
+        grec[o] = make_uint4(f.x, oc | (uint32_t(__popc(f.x)) << 8) | (open_class(f.x, oc) << 16), f.z, f.w);
         gcnt[o] = make_uint2(T.nall[t], T.nabove[t]);
       }
       __syncthreads();
@@ -664,7 +667,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
     const uint32_t x = (disjoint ? cx : cy) & 0xffffffu;
     const uint32_t t = uint32_t(__popc(xm));
     const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
-    const uint32_t code = pair_code_aks(aks, __popc(mj), rj.y & 0xffu, k, t, r5);
+    const uint32_t code = pair_code_aks(aks, (rj.y >> 8) & 0xffu, rj.y & 0xffu, k, t, r5);
     atomicAdd(&hist[lut[code]], uint64_t(x) * y);
     return;
   }
@@ -681,7 +684,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
     const uint64_t w = uint64_t(x) * y;
     const uint32_t t = uint32_t(__popc(xm));
     const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
-    const uint32_t code = pair_code_aks(aks, __popc(mj), rj.y & 0xffu, k, t, r5);
+    const uint32_t code = pair_code_aks(aks, (rj.y >> 8) & 0xffu, rj.y & 0xffu, k, t, r5);
     atomicAdd(&hist[lut[code]], w);
   }
 }
@@ -728,7 +731,7 @@ __device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int 
                                           uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& acc,
                                           const uint16_t* __restrict__ lut,
                                           unsigned long long* hist) {
-  const uint32_t cls = open_class(rj.x, rj.y & 0xffu);  // uniform
+  const uint32_t cls = rj.y >> 16;  // uniform: the open class the grouping stored
   if (cls != cur) {
     open_flush(cur, acc, aks, k0, kn, lut, hist);
     cur = cls;
