@@ -10,13 +10,14 @@ spread ranks of every degree band above 8,192: these rows hold almost all of
 the medium workload's candidates and the largest are grouped in several hash
 parts by the pair kernel's grouping.  Both group layouts are checked (one pass into
 row capacity, and groups counted first).  Two hyperedge-profile rows of hub
-degree check the MoCHy-A / profile kernel on rows of thousands of neighbours.
+degree check the profile kernel on rows of thousands of neighbours, and MoCHy-A
+samples that draw those hyperedges check the sampler on them.
 """
 import numpy as np
 import pytest
 
 from conftest import golden
-from oracle import native
+from oracle import cp, native
 from oracle.make_medium_hub_golden import csr_digest
 from workloads import make_config
 
@@ -120,3 +121,24 @@ def test_hub_hyperedge_profiles_match_oracle(ctx, graph, stored):
         p26, p431 = M.mochy_hyperedge_profiles(ctx, graph, e, e + 1)
         assert (p431[0] == want).all(), (e, np.nonzero(p431[0] != want)[0][:8])
         assert (p26[0] == native.fold26(np.concatenate([[0], want]))).all()
+
+
+def test_hub_mochy_a_samples(ctx, graph, stored, medium):
+    # MoCHy-A (Algorithm 4) hits, for one sampled hyperedge, every instance
+    # that contains it once: a one-sample window whose Philox draw is a stored
+    # hub hyperedge returns that hyperedge's profile row
+    import paper_2310_15668_amd as M
+    _, _, prof = stored
+    E, seed = medium.num_edges, 7
+
+    def drawn(n):
+        x = native.philox4x32_10([n & 0xffffffff, n >> 32, 1, 0], [seed, 0])
+        return ((x[1] << 32 | x[0]) * E) >> 64
+
+    for e, d, want in prof:
+        n0 = next(n for n in range(4_000_000) if drawn(n) == e)
+        print(f"[gpu] medium MoCHy-A sample {n0} draws hyperedge {e} (degree {d})", flush=True)
+        raw26, est26, raw431, est431 = M.mochy_count_sampled_edges(ctx, graph, 1, seed, n0)
+        assert (raw431 == want).all(), (e, np.nonzero(raw431 != want)[0][:8])
+        assert (raw26 == native.fold26(np.concatenate([[0], want]))).all()
+        np.testing.assert_allclose(est431, cp.mochy_a_estimate(want, E, 1), rtol=1e-12, atol=0)
