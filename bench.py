@@ -91,18 +91,21 @@ VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 
 # Algorithmic integer operations per unit of the exact pair kernel (Lemma 2's
 # region sizes from the two neighbours' records; every operation a 32-bit
-# lane operation):
+# vector lane operation; the class-table read and the histogram add are LDS
+# operations and not counted):
 #  * a pair of neighbour groups that both have a member above the centre
 #    (its class is needed in full): the three mask intersections (centre
-#    nodes, two words of heavy outside nodes), two ORs and a compare for the
-#    disjointness test, three population counts and an add (t, R5), six
-#    subtractions for R1, R2, R3, R4, R6, seven min(., 2) for the ternary
-#    states, six multiply-adds for the base-3 code, two for the table lookup
-#    (address, read), four for the weight (two selects, a 48-bit product in
-#    two multiplies) and two for the histogram add (address, add): 36;
-#  * any other pair of groups (counted only when open): three
-#    intersections, two ORs, a compare and a select-add into the run sum: 8.
-OPS_FULL_PAIR, OPS_OPEN_PAIR = 36, 8
+#    nodes, two words of heavy outside nodes), an OR and a compare for the
+#    disjointness test, four population counts with their offsets added in
+#    the same instruction (t + 2, |e_i| - |e_i ∩ e_k| + t, and R5 + 2 in two),
+#    seven saturating subtracts max(2 - R, 0) for the ternary digits, six
+#    multiply-adds for the base-3 code, one shift for the table address, two
+#    selects and two multiplies for the 48-bit weight and one shift-add for
+#    the histogram address: 28;
+#  * any other pair of groups (counted only when open): the centre-node
+#    intersection, two AND-ORs for the heavy words, min(., 1) and a
+#    multiply-add into the run's overlap sum: 5.
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 28, 5
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
 # (4-byte hyperedge id) for every scanned entry, and for every centre it
 # finds the two 4-byte record masks (rows j and k) and the 4-byte size of e_i.

@@ -131,9 +131,11 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                      ones take one launch), or per graph when the graphs
                                      average a full grid of work items each (0, default);
                                      same counts */
-#define MOCHY_OPT_PAIR_BLOCKS 8  /* blocks of the exact pair kernel launched per compute
-                                    unit, 1..16 (default 8; a launch per graph takes at
-                                    most one wave per work item); same counts */
+#define MOCHY_OPT_PAIR_BLOCKS 8  /* waves of the exact pair kernel launched per compute
+                                    unit, in fours, 1..16 (default 8: 32 waves, as blocks
+                                    of 256 threads, or half as many blocks of 512 where
+                                    one histogram serves a whole graph; a launch per graph
+                                    takes at most one wave per work item); same counts */
 #define MOCHY_OPT_CACHE_BYTES 9  /* device buffers of 64 MiB or more that a call frees are
                                     kept by the context, up to this many bytes in all, and
                                     reused by later calls on it (default half of the

@@ -41,7 +41,7 @@ struct mochy_ctx {
   bool memo_all = false;              // memoize every key that fits (MOCHY_OPT_MEMO_ALL)
   bool memo_pool = false;             // always restrict other-side skips (MOCHY_OPT_MEMO_POOL)
   int batch_launch = 0;               // pair kernel over a batch: 0 size rule, 1 one launch, 2 per graph
-  int pair_blocks = 8;                // pair kernel blocks launched per CU (MOCHY_OPT_PAIR_BLOCKS)
+  int pair_blocks = 8;                // pair kernel waves per CU / 4 (MOCHY_OPT_PAIR_BLOCKS)
   int test_faults = 0;                // MOCHY_OPT_TEST_FAULTS bits (forced fallbacks)
   // allocation-free calls: device_alloc carves from this device's static
   // scratch array (bump allocation, reset per call; device_free does nothing)

@@ -642,13 +642,39 @@ __global__ __launch_bounds__(256) void k_group_stats(int64_t c0, int64_t c1, con
 constexpr int kGCopies = 2;
 constexpr int kGStride = kHistSlots + 1;
 
+// max(a - b, 0) in one saturating subtract.
+__device__ __forceinline__ uint32_t usat(uint32_t a, uint32_t b) { return a > b ? a - b : 0u; }
+
+// The reversed ternary code 2186 - code of a pair (code as pair_code_aks
+// gives it, same digit order): digit r enters as 2 - min(R_r, 2) =
+// max(2 - R_r, 0), one saturating subtract from t + 2 = |e_i ∩ e_j ∩ e_k| + 2,
+// r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy part) and aks + t, each a
+// population count with the constant added in the same instruction.  The
+// pair kernel's class table is stored reversed to match.  jy is j's record
+// word: oj in bits 0-7, pj in bits 8-15.
+__device__ __forceinline__ uint32_t pair_rcode(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t aks,
+                                               uint32_t jy, const Side& k) {
+  const uint32_t pj = (jy >> 8) & 0xffu, oj = jy & 0xffu;
+  const uint32_t t2 = uint32_t(__popc(xm)) + 2u;
+  const uint32_t v = uint32_t(__popc(xm)) + aks;
+  uint32_t r2;  // two chained population counts (not two and an add)
+  asm("v_bcnt_u32_b32 %0, %1, 2\n\tv_bcnt_u32_b32 %0, %2, %0" : "=&v"(r2) : "v"(xl), "v"(xh));
+  uint32_t c = usat(4u, t2);           // R7
+  c = mad3(c, usat(t2, k.s));          // R6
+  c = mad3(c, usat(4u, r2));           // R5
+  c = mad3(c, usat(t2, pj));           // R4
+  c = mad3(c, usat(r2, k.o));          // R3
+  c = mad3(c, usat(r2, oj));           // R2
+  return mad3(c, usat(pj + 2u, v));    // R1 = |e_i| - k.s - pj + t
+}
+
 // Every row is shorter than 2^24 (a graph has at most 200000 hyperedges), so
 // a weight is a product of two 24-bit counts (two full-rate multiplies
 // instead of a 64-bit one).  A disjoint pair (open at the centre) weighs nall_j * nall_k, an
-// overlapping one nabove_j * nabove_k; ka_m is the lane's nabove with every
-// bit set or clear as row j has members above the centre or not, so the
-// selected lane count is zero exactly when the pair weighs nothing (every
-// group holds at least one neighbour, and kn = 0 on lanes past the row).
+// overlapping one nabove_j * nabove_k.  gwalk walks only groups j with
+// members above the centre (they come first in a row), so the selected lane
+// count is zero exactly when the pair weighs nothing (every group holds at
+// least one neighbour, and kn = 0 on lanes past the row).
 // kAllA: every lane's group and j have members above the centre, so every
 // pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
 // past the row's end has N = A = 0 and adds 0 at a valid class).
@@ -660,41 +686,36 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   const uint32_t mj = rj.x;
   const uint32_t xm = mj & k.m, xl = rj.z & khl, xh = rj.w & khh;
   const bool disjoint = (xm | xl | xh) == 0u;
+  // j's counts arrive in vector registers (gwalk loads them per lane), so
+  // the selects below need no copies of scalar values
+  const uint32_t y = disjoint ? kn : ka;
   if (kAllA && !kDiag) {
-    uint32_t cx = cj.x, cy = cj.y;
-    asm("" : "+s"(cx), "+s"(cy));
-    const uint32_t y = disjoint ? kn : ka;
-    const uint32_t x = (disjoint ? cx : cy) & 0xffffffu;
-    const uint32_t t = uint32_t(__popc(xm));
-    const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
-    const uint32_t code = pair_code_aks(aks, (rj.y >> 8) & 0xffu, rj.y & 0xffu, k, t, r5);
-    atomicAdd(&hist[lut[code]], uint64_t(x) * y);
+    const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
+    const uint32_t rc = pair_rcode(xm, xl, xh, aks, rj.y, k);
+    atomicAdd(&hist[lut[rc]], uint64_t(x) * y);
     return;
   }
-  // the counts of j are uniform: kept in scalar registers as two 32-bit
-  // values (seen as one 64-bit word, the test below becomes a vector compare)
-  uint32_t cx = cj.x, cy = cj.y;
-  asm("" : "+s"(cx), "+s"(cy));
-  const uint32_t ka_m = ka & (cy != 0u ? ~0u : 0u);
-  const uint32_t y = disjoint ? kn : ka_m;
   bool act = y != 0u;
   if (kDiag) act = act && (j < kp);
   if (act) {
-    const uint32_t x = (disjoint ? cx : cy) & 0xffffffu;
+    const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
     const uint64_t w = uint64_t(x) * y;
-    const uint32_t t = uint32_t(__popc(xm));
-    const uint32_t r5 = uint32_t(__popc(xl) + __popc(xh));
-    const uint32_t code = pair_code_aks(aks, (rj.y >> 8) & 0xffu, rj.y & 0xffu, k, t, r5);
-    atomicAdd(&hist[lut[code]], w);
+    const uint32_t rc = pair_rcode(xm, xl, xh, aks, rj.y, k);
+    atomicAdd(&hist[lut[rc]], w);
   }
 }
 
 template <bool kDiag, bool kAllA>
-__device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc,
+__device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc0,
                                       int j0, int j1, uint32_t aks, const Side& k, uint32_t kn,
                                       uint32_t ka, int kp, const uint16_t* __restrict__ lut,
                                       unsigned long long* hist) {
   const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
+  // a lane-held zero makes the count loads vector loads (one 8-byte word
+  // broadcast to every lane) instead of scalar loads
+  int z = 0;
+  asm volatile("" : "+v"(z));
+  const uint2* gc = gc0 + z;
   int j = j0;
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
@@ -718,28 +739,53 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
 __device__ __forceinline__ void open_flush(uint32_t cls, uint32_t acc, uint32_t aks, uint32_t k0,
                                            uint32_t kn, const uint16_t* __restrict__ lut,
                                            unsigned long long* hist) {
-  if (acc != 0u) {
+  if (acc != 0u && kn != 0u) {
     const uint32_t pj = cls / 3u, oc = cls - 3u * pj;
     const uint32_t code = k0 + 27u * st3(pj) + 3u * oc + st3(aks - pj);
-    atomicAdd(&hist[lut[code]], uint64_t(acc) * kn);
+    atomicAdd(&hist[lut[kNumCodes - 1 - code]], uint64_t(acc) * kn);
   }
 }
 
+// (a & b) | c in one instruction, a taken from a scalar register.
+__device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// acc += min(x, 1) * n (n < 2^24, from a scalar register): a minimum and a
+// 24-bit multiply-add, written as instructions so that they are not turned
+// into a compare and a select (x is overwritten).
+__device__ __forceinline__ void acc_overlap(uint32_t& acc, uint32_t& x, uint32_t n) {
+  asm("v_min_u32 %1, 1, %1\n\tv_mad_u32_u24 %0, %1, %2, %0" : "+v"(acc), "+v"(x) : "s"(n));
+}
+
+// Lanes past the diagonal block take every j of a run: the run's sum of
+// nall_j (tot, uniform) less the sum over the j that overlap the lane's
+// group (acc), accumulated as min(overlap bits, 1) * nall_j in one
+// multiply-add.  The diagonal block (j < k only) adds per lane.
 template <bool kDiag>
 __device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int j, const Side& k,
                                           uint32_t khl, uint32_t khh, uint32_t kn, int kp,
-                                          uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& acc,
-                                          const uint16_t* __restrict__ lut,
+                                          uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& tot,
+                                          uint32_t& acc, const uint16_t* __restrict__ lut,
                                           unsigned long long* hist) {
   const uint32_t cls = rj.y >> 16;  // uniform: the open class the grouping stored
   if (cls != cur) {
-    open_flush(cur, acc, aks, k0, kn, lut, hist);
+    open_flush(cur, kDiag ? acc : tot - acc, aks, k0, kn, lut, hist);
     cur = cls;
+    tot = 0u;
     acc = 0u;
   }
-  bool act = ((rj.x & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u && kn != 0u;
-  if (kDiag) act = act && (j < kp);
-  if (act) acc += cj.x;
+  if (kDiag) {
+    bool act = ((rj.x & k.m) | (rj.z & khl) | (rj.w & khh)) == 0u && kn != 0u;
+    act = act && (j < kp);
+    if (act) acc += cj.x;
+  } else {
+    uint32_t x = and_or(rj.w, khh, and_or(rj.z, khl, rj.x & k.m));
+    tot += cj.x;
+    acc_overlap(acc, x, cj.x);
+  }
 }
 
 template <bool kDiag>
@@ -748,18 +794,19 @@ __device__ __forceinline__ void owalk(const uint4* __restrict__ grow, const uint
                                       uint32_t kn, int kp, const uint16_t* __restrict__ lut,
                                       unsigned long long* hist) {
   const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
-  uint32_t cur = 0u, acc = 0u;
+  uint32_t cur = 0u, tot = 0u, acc = 0u;
   int j = j0;
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    open_step<kDiag>(r0, c0, j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
-    open_step<kDiag>(r1, c1, j + 1, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
-    open_step<kDiag>(r2, c2, j + 2, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
-    open_step<kDiag>(r3, c3, j + 3, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r0, c0, j, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
+    open_step<kDiag>(r1, c1, j + 1, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
+    open_step<kDiag>(r2, c2, j + 2, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
+    open_step<kDiag>(r3, c3, j + 3, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
   }
-  for (; j < j1; ++j) open_step<kDiag>(grow[j], gc[j], j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
-  open_flush(cur, acc, aks, k0, kn, lut, hist);
+  for (; j < j1; ++j)
+    open_step<kDiag>(grow[j], gc[j], j, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
+  open_flush(cur, kDiag ? acc : tot - acc, aks, k0, kn, lut, hist);
 }
 
 __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane, int64_t g,
@@ -777,19 +824,24 @@ __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane,
 }
 
 // kShared (one graph per launch: a single graph, or one graph of a batch of
-// large graphs): the block's 4 histogram copies are shared by its waves, lane
-// l adding to copy l % 4, flushed once at the end: 18 KB of LDS
-// per block, so 8 blocks (32 waves) fit on a CU; 8 shared copies (fewer
-// same-word adds, but 5 blocks per CU) were 27 % slower, 16 copies in
-// 512-thread blocks slower still.  Otherwise each wave has 2 copies of its
-// own, flushed whenever its rows change graph.
-constexpr int kGSharedCopies = 4;
+// large graphs): 512-thread blocks whose 8 histogram copies are shared by
+// their waves, lane l adding to copy l % 8, flushed once at the end: 32 KB of
+// LDS per block, so 4 blocks (32 waves, as many as the registers allow) fit
+// on a CU.  Lanes of one add that hit the same word are serialized, so the
+// copies count: on the medium workload the pair kernel took 556 ms with 2
+// copies and 448 ms with 4 (256-thread blocks), 434 ms with 8 (512-thread
+// blocks), 538 ms with 16 (1024-thread blocks, 2 per CU), and 853 ms with a
+// single histogram over the 2187 codes (no class table read).  Otherwise
+// (kShared false) each wave has 2 copies of its own, flushed whenever its
+// rows change graph.
+constexpr int kGSharedCopies = 8;
+constexpr int kGSharedThreads = 512;
 // batches of up to this many graphs whose graphs average a full grid of
 // work items count each graph with its own launch of the shared-histogram
 // kernel; others use per-wave histograms in one launch
 constexpr int kPerGraphLaunches = 256;
 template <bool kShared>
-__global__ __launch_bounds__(256) void k_exact_grouped(
+__global__ __launch_bounds__(kShared ? kGSharedThreads : 256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
     const uint4* __restrict__ grec, const uint2* __restrict__ gcnt, const int32_t* __restrict__ gna,
@@ -799,7 +851,7 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
   __shared__ uint16_t lut[kNumCodes];
   constexpr int kAll = kShared ? kGSharedCopies : kWavesPerGroup * kGCopies;
   __shared__ unsigned long long hist[kAll * kGStride];
-  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
+  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[kNumCodes - 1 - t];  // indexed by the reversed code
   for (int t = threadIdx.x; t < kAll * kGStride; t += blockDim.x) hist[t] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -874,7 +926,7 @@ __global__ __launch_bounds__(256) void k_exact_grouped(
     if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
       const uint32_t r5 = uint32_t(__popcll(k.h));
       const uint32_t code = pair_code(a, k.s, k.o, k, k.s, r5);
-      atomicAdd(&myhist[lut[code]], uint64_t(ka) * (ka - 1u) / 2u);
+      atomicAdd(&myhist[lut[kNumCodes - 1 - code]], uint64_t(ka) * (ka - 1u) / 2u);
     }
   }
   if (kShared) {
@@ -1086,6 +1138,10 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     return MOCHY_EUNSUPPORTED;
   }
   const unsigned grid = unsigned(ctx->num_cus) * unsigned(ctx->pair_blocks);
+  // the shared-histogram kernel's blocks are kGSharedThreads wide: as many
+  // waves in flight as `grid` blocks of 256
+  constexpr int kSharedWaves = kGSharedThreads / kWave;
+  const unsigned sgrid = std::max(1u, grid * 256u / unsigned(kGSharedThreads));
   int64_t* goff = nullptr;
   const int64_t* gbase = nullptr;
   int64_t cap0 = 0;
@@ -1149,13 +1205,18 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
       const int64_t items = hgq[gi + 1] - hgq[gi];
       if (items <= 0) continue;
       // at most one wave per item
-      const unsigned ggrid = unsigned(std::min<int64_t>(grid, (items + kWavesPerGroup - 1) / kWavesPerGroup));
-      k_exact_grouped<true><<<ggrid, 256, 0, st>>>(
+      const unsigned ggrid = unsigned(std::min<int64_t>(sgrid, (items + kSharedWaves - 1) / kSharedWaves));
+      k_exact_grouped<true><<<ggrid, kGSharedThreads, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, hgq[gi], hgq[gi + 1],
           g->row_graph, gqueue + gi, ctx->d_code_to_id3, (unsigned long long*)d_hist + size_t(gi) * kHistSlots);
     }
   } else if (grouped) {
-    (ng == 1 ? k_exact_grouped<true> : k_exact_grouped<false>)<<<grid, 256, 0, st>>>(
+    if (ng == 1)
+      k_exact_grouped<true><<<sgrid, kGSharedThreads, 0, st>>>(
+          g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
+          S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
+    else
+    k_exact_grouped<false><<<grid, 256, 0, st>>>(
         g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
         S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
   } else {
