@@ -107,9 +107,9 @@ VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 #    multiply-add into the run's overlap sum: 5.
 OPS_FULL_PAIR, OPS_OPEN_PAIR = 28, 5
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
-# (4-byte hyperedge id) for every scanned entry, and for every centre it
-# finds the two 4-byte record masks (rows j and k) and the 4-byte size of e_i.
-FIX_BYTES_SCANNED, FIX_BYTES_CENTRE = 4, 12
+# (4-byte hyperedge id) for every scanned entry, and for every centre it finds
+# the partner row's 4-byte record mask and owner row's 2-byte size word.
+FIX_BYTES_SCANNED, FIX_BYTES_CENTRE = 4, 6
 
 
 def valu_issue(kernel_ms, ceiling):

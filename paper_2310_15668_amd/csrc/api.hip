@@ -449,7 +449,7 @@ extern "C" void mochy_graph_free(mochy_graph* g) {
                   g->lg_col,   g->up_first,   g->up_ptr,   g->rec,        g->geoff,     g->gvoff,
                   g->gnoff,    g->row_graph,  g->xoff,     g->xnodes,     g->deg,       g->hsize,
                   g->hpair,    g->htriple,    g->hmask,      g->hbig_key,   g->hbig_val,
-                  g->recm};
+                  g->recm,     g->rsz};
   for (void* b : bufs) {
     if (g->ctx) device_free(g->ctx, b);
     else (void)hipFree(b);

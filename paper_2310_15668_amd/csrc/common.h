@@ -123,6 +123,7 @@ struct mochy_graph {
   int64_t* up_ptr = nullptr;             // [E+1]: prefix sums of upper-row lengths (wedge order)
   uint4* rec = nullptr;                  // [2W]: per (centre, neighbour) region record
   uint32_t* recm = nullptr;              // [2W]: rec[].x alone (the light-pair correction's reads)
+  uint16_t* rsz = nullptr;               // [2W]: |e_i ∩ e_x| | |e_x| << 8 of each (centre i, neighbour x)
   // line-graph-free mode (no lg_ptr / lg_col / up_first / rec)
   bool lg_free = false;
   uint32_t* xoff = nullptr;              // [nnz+1]: slot p of E_v -> start of e_k's nodes in xnodes

@@ -12,14 +12,15 @@
 //     the endpoint with the longer line-graph row.
 //  2. for every light pair, the centres are N_j ∩ N_k: one workgroup per
 //     owner j holds row j as an LDS bitmap (with per-word ranks, so a hit gives
-//     the position of e_i in row j) and scans the partner's row.  For a
-//     centre e_i, with masks over the nodes of e_j taken from the records of
-//     row j (m_ji: e_j ∩ e_i, m_jk: e_j ∩ e_k) and the heavy-node mask H_j of
-//     e_j:
-//        t   = popcount(m_ji & m_jk)                 = |e_i ∩ e_j ∩ e_k|
-//        r5h = popcount(m_jk & H_j & ~m_ji)            heavy part of R5
-//        ls  = popcount(m_jk & ~H_j & ~m_ji)           light part of R5
-//     and omega(e_i, e_k) from the record of row k at the scanned position.
+//     the position of e_i in row j) and scans the partner's row.  With masks
+//     over the nodes of e_k (m_kj: e_k ∩ e_j, and its heavy and light parts
+//     H, L, formed once per pair from the two node lists) and, for a centre
+//     e_i, m_ki (e_k ∩ e_i) from the record of row k at the scanned position:
+//        t   = popcount(m_ki & m_kj)                 = |e_i ∩ e_j ∩ e_k|
+//        r5h = popcount(H & ~m_ki)                   heavy part of R5
+//        ls  = popcount(L & ~m_ki)                   light part of R5
+//     and |e_j ∩ e_i|, |e_i| from the size word of row j at e_i's position
+//     (the only read outside the scanned row).
 //     If ls = 0 the pair kernel was exact at this centre.  Otherwise the pair
 //     kernel recorded the class with R5 = r5h, counted iff both neighbours
 //     are above e_i or the two looked disjoint; the exact class has
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     const int64_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_nodes,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ lg_col, const uint32_t* __restrict__ recm,
-    const uint32_t* __restrict__ esize, const uint16_t* __restrict__ code_to_id3,
+    const uint16_t* __restrict__ rsz, const uint16_t* __restrict__ code_to_id3,
     unsigned long long* hist_out, uint2* tally) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   // graphs of up to 85k hyperedges, so that 4 blocks reside per CU
   __shared__ unsigned long long hist[kFixCopies * kHistSlots];
   __shared__ int32_t part[kFixThreads];
-  __shared__ uint32_t hmask;
+  __shared__ int32_t ej[MOCHY_MAX_EDGE];  // e_j's nodes (ascending)
   __shared__ uint32_t s_tally[2];  // centres examined, centres reclassified
   const int64_t it = xcd_block(blockIdx.x, gridDim.x);
   const int64_t ob = item_owner[it];
@@ -142,14 +143,11 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[t];
   for (int t = threadIdx.x; t < kFixCopies * kHistSlots; t += blockDim.x) hist[t] = 0;
   for (int w = threadIdx.x; w < nwE; w += blockDim.x) bm[w] = 0;
+  const uint32_t sizej = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
+  if (threadIdx.x < sizej) ej[threadIdx.x] = edge_nodes[edge_ptr[j] + threadIdx.x];
   if (threadIdx.x == 0) {
     s_tally[0] = 0u;
     s_tally[1] = 0u;
-    uint32_t h = 0;
-    int n = 0;
-    for (int64_t q = edge_ptr[j]; q < edge_ptr[j + 1]; ++q, ++n)
-      if (heavy_bit[edge_nodes[q]] >= 0) h |= 1u << n;
-    hmask = h;
   }
   __syncthreads();
   for (int p = threadIdx.x; p < dj; p += blockDim.x) {
@@ -177,9 +175,6 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     }
   }
   __syncthreads();
-  const uint32_t H = hmask;
-  const uint32_t sizej = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
-  const uint32_t L = (sizej >= 32u ? 0xffffffffu : ((1u << sizej) - 1u)) & ~H;
   // one partner per wave at a time (rows shorter than a block's sweep leave
   // no lanes idle)
   const int lane = int(threadIdx.x) & (kWave - 1), wave = int(threadIdx.x) / kWave;
@@ -187,14 +182,19 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
   uint32_t n_centres = 0, n_changed = 0;  // this wave's, for mochy_exact_stats
   for (int64_t pp = p0 + wave; pp < p1; pp += kFixThreads / kWave) {
     const int32_t k = partners[pp];
-    // record of e_k in row j
-    const int64_t kl = k - e0;
-    const uint32_t kw = bm[kl >> 5];
-    const int qk = int(rank[kl >> 5] + __popc(kw & ((1u << (kl & 31)) - 1u)));
-    const uint32_t mjk = recm[jb + qk];
+    // masks over e_k's nodes: e_j ∩ e_k (mkj), its heavy and light nodes
+    const int64_t kn0 = edge_ptr[k];
+    const uint32_t sizek = uint32_t(edge_ptr[k + 1] - kn0);
+    bool in_j = false, heavy = false;
+    if (uint32_t(lane) < sizek) {
+      const int32_t v = edge_nodes[kn0 + lane];
+      in_j = in_sorted(ej, int(sizej), v);
+      heavy = heavy_bit[v] >= 0;
+    }
+    const uint32_t mkj = uint32_t(__ballot(in_j));
+    const uint32_t Hk = mkj & uint32_t(__ballot(heavy)), Lk = mkj & ~Hk;
     const int64_t kb = lg_ptr[k];
     const int dk = int(lg_ptr[k + 1] - kb);
-    const uint32_t sizek = uint32_t(edge_ptr[k + 1] - edge_ptr[k]);
     // row k scanned kUnroll entries per thread at a time; the loads of one
     // stage are issued together, with no branch between them (an entry that
     // is not a centre reads a valid dummy slot), since the work is bound by
@@ -203,10 +203,12 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     constexpr int step = kWave;
     for (int r0 = lane; r0 < dk; r0 += kUnroll * step) {
       int32_t iv[kUnroll];
+      uint32_t mki[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int r = r0 + u * step;
         iv[u] = r < dk ? lg_col[kb + r] : -1;
+        mki[u] = recm[kb + min(r, dk - 1)];  // e_k ∩ e_i over e_k's nodes
       }
       int qj[kUnroll];
       bool hit[kUnroll];
@@ -220,30 +222,23 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
         hit[u] = in && (iw & ibit) != 0u;  // a neighbour of e_j (i == j never is)
         qj[u] = hit[u] ? int(rank[il >> 5] + __popc(iw & (ibit - 1u))) : 0;
       }
-      uint32_t mji[kUnroll], mik[kUnroll];
-      uint32_t av[kUnroll];
+      uint32_t szj[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int r = min(r0 + u * step, dk - 1);
-        const int32_t iu = hit[u] ? iv[u] : j;
-        mji[u] = recm[jb + qj[u]];
-        mik[u] = recm[kb + r];
-        av[u] = esize[iu];
-      }
+      for (int u = 0; u < kUnroll; ++u) szj[u] = rsz[jb + qj[u]];  // |e_j ∩ e_i| | |e_i| << 8
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         // wave-uniform tallies (a ballot counts the lanes still scanning)
         n_centres += uint32_t(__popcll(__ballot(hit[u])));
         if (!hit[u]) continue;
-        const int32_t i = iv[u];
-        const uint32_t ls = __popc(mjk & L & ~mji[u]);
+        const uint32_t ls = __popc(Lk & ~mki[u]);
         n_changed += uint32_t(__popcll(__ballot(ls != 0u)));
         if (ls == 0u) continue;  // the pair kernel was exact at this centre
-        const uint32_t wik = __popc(mik[u]);
-        const uint32_t t = __popc(mji[u] & mjk);
-        const uint32_t r5h = __popc(mjk & H & ~mji[u]);
-        const uint32_t pj = __popc(mji[u]);
-        const uint32_t a = av[u];
+        const int32_t i = iv[u];
+        const uint32_t wik = __popc(mki[u]);
+        const uint32_t t = __popc(mki[u] & mkj);
+        const uint32_t r5h = __popc(Hk & ~mki[u]);
+        const uint32_t pj = szj[u] & 0xffu;
+        const uint32_t a = szj[u] >> 8;
         Side K;
         K.m = 0u; K.s = wik; K.o = sizek - wik; K.h = 0ull;
         const uint32_t oj = sizej - pj;
@@ -299,12 +294,6 @@ __global__ __launch_bounds__(256) void k_fix_tally(int64_t npairs, const int32_t
   }
 }
 
-// esize[x] = |e_x|.
-__global__ void k_edge_sizes(int64_t E, const int64_t* __restrict__ edge_ptr, uint32_t* esize) {
-  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (x < E) esize[x] = uint32_t(edge_ptr[x + 1] - edge_ptr[x]);
-}
-
 // owners: hyperedges with at least one light partner, compacted.
 __global__ void k_owner_list(int64_t E, const unsigned long long* __restrict__ pcount,
                              unsigned long long* nown, int32_t* owners, int64_t* ocount) {
@@ -352,7 +341,6 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   char* buf = nullptr;
   int64_t* eoff = nullptr;
   int32_t* partners = nullptr;
-  uint32_t* esize = nullptr;
   int64_t* ioff = nullptr;
   int32_t* item_owner = nullptr;
   uint2* tally = nullptr;
@@ -360,7 +348,6 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
     device_free(ctx, buf);
     device_free(ctx, eoff);
     device_free(ctx, partners);
-    device_free(ctx, esize);
     device_free(ctx, ioff);
     device_free(ctx, item_owner);
     device_free(ctx, tally);
@@ -402,11 +389,6 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
                                                partners);
-  // hyperedge sizes as 32-bit words: one load and one register per centre in
-  // flight (two 64-bit offsets otherwise), which keeps the kernel within 64
-  // registers, so 4 blocks (32 waves) are resident per CU instead of 3
-  if ((rc = device_alloc(ctx, (void**)&esize, size_t(E) * 4)) != MOCHY_OK) return done(rc);
-  k_edge_sizes<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, esize);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t nitems = ctx->h_small[506];
   if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK ||
@@ -417,7 +399,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   k_light_fix<<<unsigned(nitems), kFixThreads, dyn, st>>>(c0, c1, g->row_graph, g->geoff, owners, item_owner,
                                                           ioff, poff, partners,
                                                            g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
-                                                           g->lg_col, g->recm, esize, ctx->d_code_to_id3,
+                                                           g->lg_col, g->recm, g->rsz, ctx->d_code_to_id3,
                                                            (unsigned long long*)d_hist, tally);
   phase_end(ctx, kPhFix);
   k_fix_tally<<<kTallyBlocks, 256, 0, st>>>(npairs, partners, g->lg_ptr, nitems, tally, stats);

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
                                                  const int8_t* __restrict__ heavy_bit,
                                                  const int64_t* __restrict__ lg_ptr,
                                                  const int32_t* __restrict__ lg_col, uint4* rec,
-                                                 uint32_t* recm, int32_t* flags) {
+                                                 uint32_t* recm, uint16_t* rsz, int32_t* flags) {
   __shared__ int32_t ei[MOCHY_MAX_EDGE];
   const int64_t i = blockIdx.x;
   const int64_t s = ptr[i];
@@ -243,6 +243,7 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
     if (o == 0 && __popc(m) == a) atomicOr(flags, kFlagDup);
     rec[base + p] = make_uint4(m, o | (light ? kRecLight : 0u), uint32_t(hv), uint32_t(hv >> 32));
     recm[base + p] = m;
+    rsz[base + p] = uint16_t(uint32_t(__popc(m)) | ((uint32_t(__popc(m)) + o) << 8));
   }
 }
 
@@ -368,7 +369,8 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   if ((rc = device_alloc(ctx, (void**)&g->lg_col, size_t(std::max<int64_t>(twoW, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->rec, size_t(std::max<int64_t>(twoW, 1)) * 16)) != MOCHY_OK) { cleanup(); return rc; }
   if ((rc = device_alloc(ctx, (void**)&g->recm, size_t(std::max<int64_t>(twoW, 1)) * 4)) != MOCHY_OK) { cleanup(); return rc; }
-  g->bytes += size_t(twoW) * 24;
+  if ((rc = device_alloc(ctx, (void**)&g->rsz, size_t(std::max<int64_t>(twoW, 1)) * 2)) != MOCHY_OK) { cleanup(); return rc; }
+  g->bytes += size_t(twoW) * 26;
   phase_begin(ctx, kPhRows);
   if (E > 0)
     k_proj_fill<<<unsigned(E), 256, bm_bytes, st>>>(E, g->edge_ptr, g->edge_nodes, g->node_ptr,
@@ -379,7 +381,7 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
   phase_begin(ctx, kPhRecords);
   if (E > 0)
     k_records<<<unsigned(E), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
-                                           g->lg_col, g->rec, g->recm, ctx->d_flags);
+                                           g->lg_col, g->rec, g->recm, g->rsz, ctx->d_flags);
   // upper-row prefix (hyperwedge order for sampling)
   k_upper_len<<<blocks(E + 1, 256), 256, 0, st>>>(E, g->lg_ptr, g->up_first, cnt);
   launch_exclusive_scan_i64(cnt, g->up_ptr, E + 1, tmp, st);
