@@ -162,6 +162,21 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
+def valu_calibration_runs():
+    """mochy_calibrate_valu at 2^12, 2^14 and 2^16 rounds, one JSON line each
+    (the integer VALU ceiling, for counter runs under rocprofv3)."""
+    import paper_2310_15668_amd as M
+    ctx = M.Context(0)
+    try:
+        for it in (1 << 12, 1 << 14, 1 << 16):
+            ms, ops = M.mochy_calibrate_valu(ctx, it)
+            rate = ops / (ms * 1e-3)
+            print(json.dumps({"iters": it, "ms": ms, "lane_ops": ops, "lane_ops_per_s": rate,
+                              "wave_instr_per_cu_per_cycle": rate / LANES / (NUM_CUS * CLOCK_HZ)}), flush=True)
+    finally:
+        ctx.close()
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -631,6 +646,8 @@ def main():
                     help="medium-exact: leave out the serving stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only run the integer VALU calibration kernel (its counters under rocprofv3)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -642,6 +659,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.valu_calibration:
+        valu_calibration_runs()
         return
     if args.workload == "large-aplus":
         large_aplus(args)

@@ -199,10 +199,19 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
                                                  const int32_t* __restrict__ lg_col, uint4* rec,
                                                  uint32_t* recm, uint16_t* rsz, int32_t* flags) {
   __shared__ int32_t ei[MOCHY_MAX_EDGE];
+  // membership filter of e_i's nodes by their low 10 bits: most nodes of a
+  // neighbour are outside e_i and leave after one read
+  __shared__ uint32_t filt[32];
   const int64_t i = blockIdx.x;
   const int64_t s = ptr[i];
   const int a = int(ptr[i + 1] - s);
-  if (threadIdx.x < unsigned(a)) ei[threadIdx.x] = nodes[s + threadIdx.x];
+  if (threadIdx.x < 32u) filt[threadIdx.x] = 0u;
+  __syncthreads();
+  if (threadIdx.x < unsigned(a)) {
+    const int32_t v = nodes[s + threadIdx.x];
+    ei[threadIdx.x] = v;
+    atomicOr(&filt[(v >> 5) & 31], 1u << (v & 31));
+  }
   __syncthreads();
   const int64_t base = lg_ptr[i];
   const int64_t d = lg_ptr[i + 1] - base;
@@ -221,7 +230,8 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
       int hb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        int lo = 0, hi = a;  // binary search of v in e_i
+        int lo = 0, hi = a;  // binary search of v in e_i, past the filter
+        if (v[u] < 0 || !((filt[(v[u] >> 5) & 31] >> (v[u] & 31)) & 1u)) hi = 0;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (ei[mid] < v[u]) lo = mid + 1; else hi = mid;
