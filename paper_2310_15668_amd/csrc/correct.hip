@@ -101,10 +101,11 @@ __device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
 // owner (an owner's items are consecutive, so they run at the same time on
 // one XCD and share the owner's row in its L2); 512 threads, so that the LDS
 // the row bitmap takes still leaves room for 24 resident waves per CU (the
-// scan waits on loads).
+// scan waits on loads).  128 partners per item build an owner's bitmap half
+// as often as 64 (on medium 121 ms against 125; 256 no better).
 constexpr int kFixThreads = 512;
 constexpr int kFixCopies = 2;
-constexpr int kFixChunk = 64;
+constexpr int kFixChunk = 128;
 
 // At most 64 registers (8 waves per SIMD, room for 4 blocks, 32 waves per CU,
 // when the LDS allows; the scan waits on loads, so resident waves count more
@@ -199,7 +200,8 @@ __global__ __launch_bounds__(kFixThreads) __attribute__((amdgpu_waves_per_eu(8))
     // stage are issued together, with no branch between them (an entry that
     // is not a centre reads a valid dummy slot), since the work is bound by
     // load latency: 3 of 4 scanned entries are centres on hub-heavy graphs
-    constexpr int kUnroll = 6;
+    // (7 entries per lane fit the 64 registers; 8 spill and were slower)
+    constexpr int kUnroll = 7;
     constexpr int step = kWave;
     for (int r0 = lane; r0 < dk; r0 += kUnroll * step) {
       int32_t iv[kUnroll];
