@@ -58,13 +58,20 @@ __device__ __forceinline__ bool smallest_shared_light(int32_t x, int32_t y, int3
 }
 
 // One wave per light node w: every pair of E_w whose smallest shared light
-// node is w.  kFill = false counts pairs per owner, true writes partners.
-template <bool kFill>
+// node is w.  kCount counts pairs per owner; kFill also writes the partners
+// (a second pass, after the owners' offsets are known); kFlat counts and
+// writes every candidate pair of E_w at its slot of a flat list (slot =
+// noff[w] + b (b - 1) / 2 + a for members a < b of E_w), (owner, partner)
+// or (-1, -1) where w is not the pair's smallest shared light node, so the
+// merges run once and a scatter pass replaces the second.
+enum LightMode { kCount = 0, kFill = 1, kFlat = 2 };
+template <int kMode>
 __global__ __launch_bounds__(256) void k_light_pairs(
     int64_t V, const int64_t* __restrict__ node_ptr, const int32_t* __restrict__ node_edges,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ edge_ptr,
     const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ lg_ptr,
-    unsigned long long* pcount, const int64_t* __restrict__ poff, int32_t* partners) {
+    unsigned long long* pcount, const int64_t* __restrict__ poff, int32_t* partners,
+    const int64_t* __restrict__ noff, int2* flat) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   if (w >= V || heavy_bit[w] >= 0) return;  // uniform per wave
@@ -78,13 +85,46 @@ __global__ __launch_bounds__(256) void k_light_pairs(
     for (int a = 0; a < aend; ++a) {
       const int32_t ya = node_edges[lo + a];
       if (!(b < D && a < b)) continue;
-      if (!smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit)) continue;
+      const bool first = smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit);
+      int2* slotp = nullptr;
+      if (kMode == kFlat) slotp = flat + noff[w] + int64_t(b) * (b - 1) / 2 + a;
+      if (!first) {
+        if (kMode == kFlat) *slotp = make_int2(-1, -1);
+        continue;
+      }
       const int64_t da = lg_ptr[ya + 1] - lg_ptr[ya];
       const bool a_owns = da > db || (da == db && ya < yb);
       const int32_t owner = a_owns ? ya : yb, partner = a_owns ? yb : ya;
       const unsigned long long slot = atomicAdd(&pcount[owner], 1ull);
-      if (kFill) partners[poff[owner] + int64_t(slot)] = partner;
+      if (kMode == kFill) partners[poff[owner] + int64_t(slot)] = partner;
+      if (kMode == kFlat) *slotp = make_int2(owner, partner);
     }
+  }
+}
+
+// Candidate pairs C(|E_w|, 2) of every light node (0 for heavy ones), the
+// input of the flat list's offsets; cnt[V] = 0.
+__global__ void k_pair_slots(int64_t V, const int64_t* __restrict__ node_ptr,
+                             const int8_t* __restrict__ heavy_bit, int64_t* cnt) {
+  const int64_t w = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w > V) return;
+  int64_t c = 0;
+  if (w < V && heavy_bit[w] < 0) {
+    const int64_t d = node_ptr[w + 1] - node_ptr[w];
+    c = d * (d - 1) / 2;
+  }
+  cnt[w] = c;
+}
+
+// The flat list's pairs into each owner's partner range (cursor[] from zero).
+__global__ void k_scatter_pairs(int64_t n, const int2* __restrict__ flat, const int64_t* __restrict__ eoff,
+                                unsigned long long* cursor, int32_t* partners) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += stride) {
+    const int2 v = flat[t];
+    if (v.x < 0) continue;
+    const unsigned long long s = atomicAdd(&cursor[v.x], 1ull);
+    partners[eoff[v.x] + int64_t(s)] = v.y;
   }
 }
 
@@ -104,6 +144,7 @@ __device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned nb) {
 // scan waits on loads).  128 partners per item build an owner's bitmap half
 // as often as 64 (on medium 121 ms against 125; 256 no better).
 constexpr int kFixThreads = 512;
+constexpr size_t kFlatBytes = size_t(4) << 30;  // largest flat list of candidate light pairs
 constexpr int kFixCopies = 2;
 constexpr int kFixChunk = 128;
 
@@ -338,7 +379,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
     MOCHY_HIP(hipFuncSetAttribute((const void*)k_light_fix, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   int(dyn)));
   // pcount[E] | nown | owners[E] | ocount[E+1] | poff[E+1] | tmp
-  const size_t tmpn = scan_tmp_elems(E + 1);
+  const size_t tmpn = scan_tmp_elems(std::max(E, V) + 1);  // scans of E + 1 and V + 1 entries
   const size_t n64 = size_t(E) + 1 + size_t(E + 1) * 2 + tmpn;
   char* buf = nullptr;
   int64_t* eoff = nullptr;
@@ -346,7 +387,11 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int64_t* ioff = nullptr;
   int32_t* item_owner = nullptr;
   uint2* tally = nullptr;
+  int64_t* noff = nullptr;
+  int2* flat = nullptr;
   auto done = [&](mochy_status s) {
+    device_free(ctx, noff);
+    device_free(ctx, flat);
     device_free(ctx, buf);
     device_free(ctx, eoff);
     device_free(ctx, partners);
@@ -365,9 +410,32 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   int32_t* owners = (int32_t*)(buf + n64 * 8);
   launch_fill_u32(buf, 0u, (size_t(E) + 1 + size_t(E + 1)) * 8, st);
   const unsigned wblocks = blocks(V * 64, 256);
-  k_light_pairs<false><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
-                                                g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
-                                                nullptr, nullptr);
+  // one pass over the candidate pairs into a flat list when it is small
+  // (8 bytes per pair of a light node's hyperedges, at most kFlatBytes, not
+  // carved from a caller's arena); otherwise a counting pass now and a
+  // filling pass once the owners' offsets are known
+  int64_t ncand = 0;
+  if (!ctx->arena) {
+    if ((rc = device_alloc(ctx, (void**)&noff, size_t(V + 1) * 8)) != MOCHY_OK) return done(rc);
+    k_pair_slots<<<blocks(V + 1, 256), 256, 0, st>>>(V, g->node_ptr, g->heavy_bit, noff);
+    launch_exclusive_scan_i64(noff, noff, V + 1, tmp, st);
+    MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 503, noff + V, 8, hipMemcpyDeviceToHost, st), done);
+    MOCHY_HIP_OR(hipStreamSynchronize(st), done);
+    ncand = ctx->h_small[503];
+    if (ncand > 0 && size_t(ncand) * 8 <= kFlatBytes &&
+        device_alloc(ctx, (void**)&flat, size_t(ncand) * 8) != MOCHY_OK) {
+      (void)hipGetLastError();  // no room for the list: the two passes instead
+      flat = nullptr;
+    }
+  }
+  if (flat)
+    k_light_pairs<kFlat><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
+                                                  g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
+                                                  nullptr, nullptr, noff, flat);
+  else
+    k_light_pairs<kCount><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
+                                                   g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
+                                                   nullptr, nullptr, nullptr, nullptr);
   k_owner_list<<<blocks(E, 256), 256, 0, st>>>(E, pcount, nown, owners, ocount);
   MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 504, nown, 8, hipMemcpyDeviceToHost, st), done);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
@@ -388,9 +456,13 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   launch_exclusive_scan_i64(ioff, ioff, nowners + 1, tmp, st);
   MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 506, ioff + nowners, 8, hipMemcpyDeviceToHost, st), done);
   launch_fill_u32(pcount, 0u, size_t(E) * 8, st);
-  k_light_pairs<true><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
-                                               g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
-                                               partners);
+  if (flat)
+    k_scatter_pairs<<<unsigned(std::min<int64_t>(blocks(ncand, 256), int64_t(ctx->num_cus) * 16)), 256, 0, st>>>(
+        ncand, flat, eoff, pcount, partners);
+  else
+    k_light_pairs<kFill><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
+                                                  g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
+                                                  partners, nullptr, nullptr);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t nitems = ctx->h_small[506];
   if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK ||
