@@ -151,7 +151,10 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                      mochy_count_exact_range_noalloc at 64 KiB; bit 2
                                      makes the grouping of a batch of more than two
                                      graphs report MOCHY_ENOMEM, so mochy_profile splits
-                                     it (default 0); same counts */
+                                     it; bit 3 leaves out the light-pair correction's
+                                     flat candidate list, so its pairs are listed in a
+                                     counting and a filling pass (default 0); same
+                                     counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

@@ -415,7 +415,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   // carved from a caller's arena); otherwise a counting pass now and a
   // filling pass once the owners' offsets are known
   int64_t ncand = 0;
-  if (!ctx->arena) {
+  if (!ctx->arena && !(ctx->test_faults & 8)) {
     if ((rc = device_alloc(ctx, (void**)&noff, size_t(V + 1) * 8)) != MOCHY_OK) return done(rc);
     k_pair_slots<<<blocks(V + 1, 256), 256, 0, st>>>(V, g->node_ptr, g->heavy_bit, noff);
     launch_exclusive_scan_i64(noff, noff, V + 1, tmp, st);

@@ -359,7 +359,28 @@ def test_row_capacity_fallback(ctx):
         g.close()
     assert (a431 == b431).all() and (a26 == b26).all()
     with pytest.raises(M.MochyError):
-        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 8)
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 16)
+
+
+def test_light_pairs_two_passes(ctx):
+    # the correction's light pairs listed by a counting and a filling pass
+    # instead of the flat candidate list: same pairs, same counts
+    import paper_2310_15668_amd as M
+    for h in (make_config("medium", scale=0.03), powerlaw_hypergraph(300, 2000, 2, 20, 2.5, 0.9, seed=22)):
+        print(f"[gpu] light pairs in two passes |E|={h.num_edges}", flush=True)
+        g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+        try:
+            a26, a431 = M.mochy_count_exact(ctx, g)
+            sa = M.mochy_exact_stats(ctx)
+            ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 8)
+            b26, b431 = M.mochy_count_exact(ctx, g)
+            sb = M.mochy_exact_stats(ctx)
+        finally:
+            ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 0)
+            g.close()
+        assert sa["light_pairs"] > 0 and sa["light_pairs"] == sb["light_pairs"]
+        assert sa["fix_centres"] == sb["fix_centres"] and sa["fix_changed"] == sb["fix_changed"]
+        assert (a431 == b431).all() and (a26 == b26).all()
 
 
 def test_exact_stats(ctx):
