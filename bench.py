@@ -463,7 +463,7 @@ def batched_cp(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serving(requests, rate, max_edges, slots_list, seed_log_every=50):
+def run_serving(requests, rate, max_edges, slots_list, log_every=None):
     """A Poisson stream of CP requests (a hypergraph + 8 stub-matched copies
     each) through the continuous-batching server, once per slot count;
     answers must not depend on the slot count."""
@@ -472,6 +472,7 @@ def run_serving(requests, rate, max_edges, slots_list, seed_log_every=50):
     from paper_2310_15668_amd.serving import CPServer
     from workloads import poisson_arrivals, serving_copies, serving_request
 
+    log_every = log_every or max(1, min(50, requests // 10))
     log(f"generating {requests} requests (|E| log-uniform in [1000, {max_edges}], 8 copies each)")
     reqs, sizes = [], []
     for n in range(requests):
@@ -494,7 +495,7 @@ def run_serving(requests, rate, max_edges, slots_list, seed_log_every=50):
                 tickets.append(srv.submit(r, arrival=t0 + arrivals[n]))
             for k, t in enumerate(tickets):
                 t.wait()
-                if (k + 1) % seed_log_every == 0:
+                if (k + 1) % log_every == 0:
                     log(f"  slots={slots}: {k + 1}/{len(tickets)} answered")
             end = max(t.done for t in tickets)
         lat = np.array([t.latency for t in tickets])

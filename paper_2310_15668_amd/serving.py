@@ -27,9 +27,9 @@ def request_bytes(graphs) -> int:
     """Upper bound of the device memory a request holds while it runs.
 
     Per graph: incidence and transpose, per-row arrays, and the line graph
-    (4-byte column + 16-byte record + 4-byte record mask per row entry, and
-    the exact counting's neighbour groups, 24 bytes per row entry, with
-    |wedges| bounded by sum_v C(deg(v), 2)).
+    (4-byte column + 16-byte record + 4-byte record mask + 2-byte size word per
+    row entry, and the exact counting's neighbour groups, 24 bytes per row
+    entry, with |wedges| bounded by sum_v C(deg(v), 2)).
     """
     total = 0
     for ptr, nodes, num_nodes in graphs:
@@ -37,7 +37,7 @@ def request_bytes(graphs) -> int:
         nnz = int(ptr[-1]) if E > 0 else 0
         deg = np.bincount(np.asarray(nodes), minlength=int(num_nodes)).astype(np.int64)
         wedges = int((deg * (deg - 1) // 2).sum())
-        total += 16 * (E + 1) + 8 * nnz + 9 * (int(num_nodes) + 1) + 40 * E + 2 * wedges * 48
+        total += 16 * (E + 1) + 8 * nnz + 9 * (int(num_nodes) + 1) + 40 * E + 2 * wedges * 50
     return total
 
 
@@ -48,16 +48,23 @@ class Admission:
     and starts each one whose memory bound fits in the budget left by the
     running requests, while slots remain.  Later requests may start ahead of
     an earlier one that does not fit (backfill) until that one has waited
-    ``aging_s`` seconds; from then on nothing passes it.  A request whose bound
-    exceeds the whole budget starts when nothing else runs.
+    ``aging_s`` seconds; from then on nothing passes it.  A large request
+    (bound above ``exclusive_frac`` of the budget) runs alone: it starts when
+    nothing else runs, and nothing starts beside it, so that its context may
+    keep the whole buffer-cache allowance (see CPServer).
     """
 
-    def __init__(self, budget: int, aging_s: float = 1.0):
+    def __init__(self, budget: int, aging_s: float = 1.0, exclusive_frac: float = 0.25):
         self.budget = int(budget)
         self.aging_s = float(aging_s)
+        self.exclusive_bytes = float(exclusive_frac) * self.budget
         self.waiting: deque = deque()  # (rid, nbytes, t_enqueued)
         self.in_use = 0
         self.running = 0
+        self.exclusive = False  # a large request is running alone
+
+    def is_large(self, nbytes: int) -> bool:
+        return nbytes > self.exclusive_bytes
 
     def add(self, rid, nbytes: int, now: float):
         self.waiting.append((rid, int(nbytes), now))
@@ -68,15 +75,18 @@ class Admission:
         blocked = False
         while self.waiting:
             rid, nb, t0 = self.waiting.popleft()
-            if free_slots == 0 or blocked:
+            if free_slots == 0 or blocked or self.exclusive:
                 kept.append((rid, nb, t0))
                 continue
-            fits = self.in_use + nb <= self.budget or (self.running == 0 and not started)
+            alone = self.running == 0 and not started
+            large = self.is_large(nb)
+            fits = alone if large else (self.in_use + nb <= self.budget or alone)
             if fits:
                 started.append((rid, nb))
                 self.in_use += nb
                 self.running += 1
                 free_slots -= 1
+                self.exclusive = large
             else:
                 kept.append((rid, nb, t0))
                 if now - t0 >= self.aging_s:
@@ -87,6 +97,8 @@ class Admission:
     def release(self, nbytes: int):
         self.in_use -= int(nbytes)
         self.running -= 1
+        if self.running == 0:
+            self.exclusive = False
 
 
 class Ticket:
@@ -121,7 +133,14 @@ class CPServer:
         # device memory: budget_bytes for the admitted requests, and each
         # slot's context keeps at most cache_bytes of the buffers its requests
         # freed (by default 80 % and 20 % / slots of what is free now), so
-        # that an idle slot's kept buffers never hold what admission hands out
+        # that an idle slot's kept buffers never hold what admission hands
+        # out.  A large request runs alone (Admission): its context may then
+        # keep the whole allowance, slots * cache_bytes, after the idle
+        # contexts give theirs back.  Its sub-batches free and allocate
+        # buffers of tens of GB, and mapping them again costs: on 40 requests
+        # of 1e3 to 2e5 hyperedges, one slot keeping 20 % of the memory served
+        # 0.39 requests/s, keeping 5 % 0.23, and four slots 0.24 before large
+        # requests took the whole allowance.
         if budget_bytes is None or cache_bytes is None:
             import torch
             free, _ = torch.cuda.mem_get_info(device)
@@ -130,6 +149,8 @@ class CPServer:
             if cache_bytes is None:
                 cache_bytes = max(0, int(min(0.2 * free, free - budget_bytes) / slots))
         self.eps = float(eps)
+        self._cache_small = int(cache_bytes)
+        self._cache_large = int(cache_bytes) * slots
         self._ctxs = [_lib.Context(device) for _ in range(slots)]
         for c in self._ctxs:
             c.set_option(_lib.MOCHY_OPT_CACHE_BYTES, cache_bytes)
@@ -177,11 +198,21 @@ class CPServer:
                 rid = self._work[s]
                 ticket, graphs, nbytes = self._pending.pop(rid)
             ticket.start = time.perf_counter()
+            large = self._adm.is_large(nbytes) and len(self._ctxs) > 1
             try:
+                if large:  # it runs alone: the idle contexts give their kept buffers back
+                    for c in self._ctxs:
+                        if c is not ctx:
+                            c.set_option(_lib.MOCHY_OPT_CACHE_BYTES, 0)
+                            c.set_option(_lib.MOCHY_OPT_CACHE_BYTES, self._cache_small)
+                    ctx.set_option(_lib.MOCHY_OPT_CACHE_BYTES, self._cache_large)
                 counts, sig26, cp26, sig431, cp431 = _lib.mochy_profile(ctx, graphs, self.eps)
                 ticket.result = dict(counts=counts, sig26=sig26, cp26=cp26, sig431=sig431, cp431=cp431)
             except Exception as e:  # reported to the waiter
                 ticket.error = e
+            finally:
+                if large:
+                    ctx.set_option(_lib.MOCHY_OPT_CACHE_BYTES, self._cache_small)
             ticket.done = time.perf_counter()
             with self._lock:
                 self._work[s] = None

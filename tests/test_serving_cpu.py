@@ -10,7 +10,7 @@ def ids(started):
 
 
 def test_fits_and_backfill():
-    a = Admission(budget=100, aging_s=1.0)
+    a = Admission(budget=100, aging_s=1.0, exclusive_frac=1.0)
     a.add("A", 60, 0.0)
     a.add("B", 50, 0.0)
     a.add("C", 30, 0.0)
@@ -23,7 +23,7 @@ def test_fits_and_backfill():
 
 
 def test_aged_request_blocks_backfill():
-    a = Admission(budget=100, aging_s=1.0)
+    a = Admission(budget=100, aging_s=1.0, exclusive_frac=1.0)
     a.add("X", 70, 0.0)
     assert ids(a.take(4, 0.0)) == ["X"]
     a.add("D", 50, 0.0)
@@ -46,11 +46,32 @@ def test_oversized_request_runs_alone():
     assert ids(a.take(1, 0.2)) == ["small"]
 
 
+def test_large_request_runs_exclusively():
+    # a request above a quarter of the budget starts only when nothing runs,
+    # and nothing starts beside it; small ones share the device as before
+    a = Admission(budget=100, aging_s=1.0)
+    a.add("s1", 10, 0.0)
+    a.add("L", 40, 0.0)
+    a.add("s2", 10, 0.0)
+    assert ids(a.take(4, 0.0)) == ["s1", "s2"]  # L waits for s1 to finish
+    a.release(10)
+    assert a.take(3, 0.1) == []                 # s2 still runs
+    a.add("s3", 10, 0.2)
+    assert ids(a.take(3, 0.2)) == ["s3"]        # young L: small ones pass it
+    a.release(10)
+    a.release(10)
+    a.add("s4", 10, 0.3)
+    assert ids(a.take(3, 0.3)) == ["L"]         # nothing runs: L starts, alone
+    assert a.exclusive and a.take(3, 0.4) == []
+    a.release(40)
+    assert not a.exclusive and ids(a.take(3, 0.5)) == ["s4"]
+
+
 def test_request_bytes_bounds_the_line_graph():
     h = from_edge_lists([[0, 1], [1, 2], [1, 3]], 4)
     g = (h.edge_ptr, h.edge_nodes, h.num_nodes)
     # node 1 is in 3 hyperedges: at most 3 hyperwedges, 2 row entries each
-    per = 16 * 4 + 8 * 6 + 9 * 5 + 40 * 3 + 2 * 3 * 48
+    per = 16 * 4 + 8 * 6 + 9 * 5 + 40 * 3 + 2 * 3 * 50
     assert request_bytes([g]) == per
     assert request_bytes([g, g]) == 2 * per
     assert isinstance(request_bytes([g]), int) and np.int64(request_bytes([g])) > 0
