@@ -96,16 +96,17 @@ VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 #  * a pair of neighbour groups that both have a member above the centre
 #    (its class is needed in full): the three mask intersections (centre
 #    nodes, two words of heavy outside nodes), an OR and a compare for the
-#    disjointness test, four population counts with their offsets added in
-#    the same instruction (t + 2, |e_i| - |e_i ∩ e_k| + t, and R5 + 2 in two),
-#    seven saturating subtracts max(2 - R, 0) for the ternary digits, six
-#    multiply-adds for the base-3 code, one shift for the table address, two
-#    selects and two multiplies for the 48-bit weight and one shift-add for
-#    the histogram address: 28;
+#    disjointness test, three population counts with their offsets added in
+#    the same instruction (t + 2, and R5 + 2 in two) and a shift-add for
+#    2 (|e_i| - |e_i ∩ e_k| + t), seven saturating subtracts max(2 - R, 0) for
+#    the ternary digits, six multiply-adds for the base-3 code (the last one
+#    doubling it into the table's byte offset), two selects and two
+#    multiplies for the 48-bit weight and one shift-add for the histogram
+#    address: 27;
 #  * any other pair of groups (counted only when open): the centre-node
 #    intersection, two AND-ORs for the heavy words, min(., 1) and a
 #    multiply-add into the run's overlap sum: 5.
-OPS_FULL_PAIR, OPS_OPEN_PAIR = 28, 5
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 27, 5
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
 # (4-byte hyperedge id) for every scanned entry, and for every centre it finds
 # the partner row's 4-byte record mask and owner row's 2-byte size word.

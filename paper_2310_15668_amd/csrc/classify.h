@@ -15,24 +15,12 @@ struct Side {          // a neighbour of the centre
 __device__ __forceinline__ uint32_t st3(uint32_t c) { return c < 2u ? c : 2u; }
 
 // code * 3 + d as one full-rate 24-bit multiply-add.  Written as an ALU
-// instruction so that the Horner chain below is not merged with the table
+// instruction so that a Horner chain of them is not merged with the table
 // offset formed from its result into 64-bit multiplies.
 __device__ __forceinline__ uint32_t mad3(uint32_t code, uint32_t d) {
   uint32_t r;
   asm("v_mad_u32_u24 %0, %1, 3, %2" : "=v"(r) : "v"(code), "v"(d));
   return r;
-}
-
-// pair_code (below) with aks = |e_i| - k.s (mod 2^32) taken once per k.
-__device__ __forceinline__ uint32_t pair_code_aks(uint32_t aks, uint32_t pj, uint32_t oj, const Side& k,
-                                                  uint32_t t, uint32_t r5) {
-  uint32_t code = st3(t);                 // R7
-  code = mad3(code, st3(k.s - t));        // R6
-  code = mad3(code, st3(r5));             // R5
-  code = mad3(code, st3(pj - t));         // R4
-  code = mad3(code, st3(k.o - r5));       // R3
-  code = mad3(code, st3(oj - r5));        // R2
-  return mad3(code, st3(aks - pj + t));   // R1
 }
 
 // Ternary code sum_r min(R_r, 2) * 3^r (R1 least significant) of the triple

@@ -645,27 +645,44 @@ constexpr int kGStride = kHistSlots + 1;
 // max(a - b, 0) in one saturating subtract.
 __device__ __forceinline__ uint32_t usat(uint32_t a, uint32_t b) { return a > b ? a - b : 0u; }
 
-// The reversed ternary code 2186 - code of a pair (code as pair_code_aks
-// gives it, same digit order): digit r enters as 2 - min(R_r, 2) =
-// max(2 - R_r, 0), one saturating subtract from t + 2 = |e_i ∩ e_j ∩ e_k| + 2,
-// r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy part) and aks + t, each a
-// population count with the constant added in the same instruction.  The
-// pair kernel's class table is stored reversed to match.  jy is j's record
-// word: oj in bits 0-7, pj in bits 8-15.
-__device__ __forceinline__ uint32_t pair_rcode(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t aks,
-                                               uint32_t jy, const Side& k) {
+// code * 6 + d as one 24-bit multiply-add (the Horner step that also doubles
+// the code into the class table's byte offset).
+__device__ __forceinline__ uint32_t mad6(uint32_t code, uint32_t d) {
+  uint32_t r;
+  asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(r) : "v"(code), "v"(d));
+  return r;
+}
+
+// Twice the reversed ternary code 2186 - code of a pair (code as
+// pair_code gives it, same digit order): the byte offset of its entry in
+// the pair kernel's class table (stored reversed, 2-byte entries).  Digit r
+// enters as 2 - min(R_r, 2) = max(2 - R_r, 0), one saturating subtract from
+// t + 2 = |e_i ∩ e_j ∩ e_k| + 2 and r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy
+// part), each a population count with the constant added in the same
+// instruction; R1 = aks - pj + t (aks = |e_i| - |e_i ∩ e_k|) enters doubled,
+// from 2 (t + 2) + aks2 with aks2 = 2 aks - 4, so that the last multiply-add
+// (by 6) yields the offset.
+// jy is j's record word: oj in bits 0-7, pj in bits 8-15.
+__device__ __forceinline__ uint32_t pair_rcode2(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t aks2,
+                                                uint32_t jy, const Side& k) {
   const uint32_t pj = (jy >> 8) & 0xffu, oj = jy & 0xffu;
   const uint32_t t2 = uint32_t(__popc(xm)) + 2u;
-  const uint32_t v = uint32_t(__popc(xm)) + aks;
+  uint32_t v2;  // 2 (aks + t) = 2 t2 + aks2, one shift-add
+  asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(v2) : "v"(t2), "v"(aks2));
   uint32_t r2;  // two chained population counts (not two and an add)
   asm("v_bcnt_u32_b32 %0, %1, 2\n\tv_bcnt_u32_b32 %0, %2, %0" : "=&v"(r2) : "v"(xl), "v"(xh));
-  uint32_t c = usat(4u, t2);           // R7
-  c = mad3(c, usat(t2, k.s));          // R6
-  c = mad3(c, usat(4u, r2));           // R5
-  c = mad3(c, usat(t2, pj));           // R4
-  c = mad3(c, usat(r2, k.o));          // R3
-  c = mad3(c, usat(r2, oj));           // R2
-  return mad3(c, usat(pj + 2u, v));    // R1 = |e_i| - k.s - pj + t
+  uint32_t c = usat(4u, t2);              // R7
+  c = mad3(c, usat(t2, k.s));             // R6
+  c = mad3(c, usat(4u, r2));              // R5
+  c = mad3(c, usat(t2, pj));              // R4
+  c = mad3(c, usat(r2, k.o));             // R3
+  c = mad3(c, usat(r2, oj));              // R2
+  return mad6(c, usat(2u * pj + 4u, v2));  // R1, doubled
+}
+
+// The class table entry at a byte offset.
+__device__ __forceinline__ uint32_t lut_at(const uint16_t* __restrict__ lut, uint32_t off2) {
+  return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(lut) + off2);
 }
 
 // Every row is shorter than 2^24 (a graph has at most 200000 hyperedges), so
@@ -679,7 +696,7 @@ __device__ __forceinline__ uint32_t pair_rcode(uint32_t xm, uint32_t xl, uint32_
 // pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
 // past the row's end has N = A = 0 and adds 0 at a valid class).
 template <bool kDiag, bool kAllA>
-__device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks,
+__device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks2,
                                            const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
                                            uint32_t ka, int kp, const uint16_t* __restrict__ lut,
                                            unsigned long long* hist) {
@@ -691,8 +708,8 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   const uint32_t y = disjoint ? kn : ka;
   if (kAllA && !kDiag) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
-    const uint32_t rc = pair_rcode(xm, xl, xh, aks, rj.y, k);
-    atomicAdd(&hist[lut[rc]], uint64_t(x) * y);
+    const uint32_t rc2 = pair_rcode2(xm, xl, xh, aks2, rj.y, k);
+    atomicAdd(&hist[lut_at(lut, rc2)], uint64_t(x) * y);
     return;
   }
   bool act = y != 0u;
@@ -700,8 +717,8 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   if (act) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
     const uint64_t w = uint64_t(x) * y;
-    const uint32_t rc = pair_rcode(xm, xl, xh, aks, rj.y, k);
-    atomicAdd(&hist[lut[rc]], w);
+    const uint32_t rc2 = pair_rcode2(xm, xl, xh, aks2, rj.y, k);
+    atomicAdd(&hist[lut_at(lut, rc2)], w);
   }
 }
 
@@ -716,17 +733,18 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   int z = 0;
   asm volatile("" : "+v"(z));
   const uint2* gc = gc0 + z;
+  const uint32_t aks2 = 2u * aks - 4u;
   int j = j0;
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag, kAllA>(r0, c0, j, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r1, c1, j + 1, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r2, c2, j + 2, aks, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r3, c3, j + 3, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r0, c0, j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r1, c1, j + 1, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r2, c2, j + 2, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(r3, c3, j + 3, aks2, k, khl, khh, kn, ka, kp, lut, hist);
   }
   for (; j < j1; ++j)
-    gpair_step<kDiag, kAllA>(grow[j], gc[j], j, aks, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA>(grow[j], gc[j], j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
 }
 
 // A pair in which one group has no member above the centre counts only when
@@ -1216,9 +1234,9 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
           S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
     else
-    k_exact_grouped<false><<<grid, 256, 0, st>>>(
-        g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
-        S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
+      k_exact_grouped<false><<<grid, 256, 0, st>>>(
+          g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
+          S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
   } else {
     k_exact_main<<<grid, 256, 0, st>>>(g->edge_ptr, g->lg_ptr, g->up_first, g->rec, S.order, S.rstart,
                                        S.rows, g->row_graph, S.queue, ctx->d_code_to_id3,
