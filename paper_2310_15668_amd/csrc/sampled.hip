@@ -109,16 +109,17 @@ __global__ __launch_bounds__(256) void k_aplus(
 //
 // One 256-thread block per sample.  N_i is an LDS bitmap over its graph's
 // hyperedges with per-word ranks (the rank is e_k's position in row i, whose
-// record gives omega(i, k)).  All pairs of N_i are first counted as if
+// size word gives omega(i, k)).  All pairs of N_i are first counted as if
 // disjoint from each other (class fixed by |e_j|, omega(i, j), |e_k|,
 // omega(i, k)) with a histogram of N_i by (size, omega) and products of its
-// bins.  Then the rows of e_i's neighbours are scanned (64-bit records of
-// row j: e_j's nodes held by e_k, so omega(j, k) and t = |e_i ∩ e_j ∩ e_k|
-// with the record of e_i in row j): a hit e_k in N_i with j < k is an
-// adjacent pair, its disjoint class is taken back and its exact class
+// bins.  Then the rows of e_i's neighbours are scanned: row j's record masks
+// (e_j's nodes held by e_k; t = |e_i ∩ e_j ∩ e_k| with the mask of e_i in
+// row j) and size words (omega(j, k), |e_k|), 10 bytes per entry, and
+// row i's size word at e_k's rank for a hit: a hit e_k in N_i with j < k is
+// an adjacent pair, its disjoint class is taken back and its exact class
 // added; a hit outside N_i is a path.
 constexpr int kHsThreads = 256;
-constexpr int kHsUnroll = 8;  // row entries per thread in flight at once
+constexpr int kHsUnroll = 12;  // row entries per thread in flight at once (12: 2 % faster than 8)
 // blocks launched per CU (a persistent queue of work items): as many as the
 // LDS and registers let reside, so that every CU keeps its waves busy
 constexpr unsigned kHsBlocksPerCu = 8;
@@ -163,7 +164,8 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
     const int32_t* __restrict__ row_graph,
     const int64_t* __restrict__ geoff, const int64_t* __restrict__ edge_ptr,
     const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ lg_col,
-    const uint4* __restrict__ rec, const uint16_t* __restrict__ code_to_id3,
+    const uint32_t* __restrict__ recm, const uint16_t* __restrict__ rsz,
+    const uint16_t* __restrict__ code_to_id3,
     unsigned long long* queue, unsigned long long* hist_out) {
   extern __shared__ uint32_t sm[];
   __shared__ uint16_t lut[kNumCodes];
@@ -214,10 +216,9 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
       const int64_t x = lg_col[ib + p] - e0;
       atomicOr(&bm[x >> 5], 1u << (x & 31));
       if (chunk == 0) {
-        const uint4 r = rec[ib + p];
-        const uint32_t om = __popc(r.x);
-        if (atomicAdd(&bins[bin_of(om + (r.y & 0xffu), om)], 1u) == 0u)
-          blist[atomicAdd(&s_nb, 1u)] = bin_of(om + (r.y & 0xffu), om);
+        const uint32_t sz = rsz[ib + p];  // |e_i ∩ e_x| | |e_x| << 8
+        const uint32_t om = sz & 0xffu, ox = sz >> 8;
+        if (atomicAdd(&bins[bin_of(ox, om)], 1u) == 0u) blist[atomicAdd(&s_nb, 1u)] = bin_of(ox, om);
       }
     }
     __syncthreads();
@@ -272,17 +273,18 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
           const int mid = (lo + hi) >> 1;
           if (lg_col[jb + mid] < int32_t(i)) lo = mid + 1; else hi = mid;
         }
-        const uint32_t mji = rec[jb + lo].x;
+        const uint32_t mji = recm[jb + lo];
         const uint32_t b = uint32_t(edge_ptr[j + 1] - edge_ptr[j]);
         const uint32_t p = __popc(mji);
         for (int r0 = lane; r0 < dj; r0 += kHsUnroll * kWave) {
           int32_t kv[kHsUnroll];
-          uint4 rv[kHsUnroll];
+          uint32_t mv[kHsUnroll], sv[kHsUnroll];  // e_j ∩ e_k over e_j's nodes; |e_j ∩ e_k| | |e_k| << 8
 #pragma unroll
           for (int u = 0; u < kHsUnroll; ++u) {
             const int r = min(r0 + u * kWave, dj - 1);
             kv[u] = lg_col[jb + r];
-            rv[u] = rec[jb + r];
+            mv[u] = recm[jb + r];
+            sv[u] = rsz[jb + r];
           }
           int64_t ipos[kHsUnroll];
           uint32_t kin[kHsUnroll];
@@ -293,21 +295,20 @@ __global__ __launch_bounds__(kHsThreads) void k_hsample(
             kin[u] = kw & kbit;  // e_k is a neighbour of e_i (never e_i itself)
             ipos[u] = kin[u] ? ib + int64_t(rank[kl >> 5] + __popc(kw & (kbit - 1u))) : ib;
           }
-          uint32_t wiv[kHsUnroll];
+          uint32_t wiv[kHsUnroll];  // |e_i ∩ e_k| from row i's size word
 #pragma unroll
-          for (int u = 0; u < kHsUnroll; ++u) wiv[u] = rec[ipos[u]].x;
+          for (int u = 0; u < kHsUnroll; ++u) wiv[u] = rsz[ipos[u]] & 0xffu;
 #pragma unroll
           for (int u = 0; u < kHsUnroll; ++u) {
             if (r0 + u * kWave >= dj) continue;
             const int32_t k = kv[u];
             if (k == int32_t(i)) continue;
-            const uint4 rjk = rv[u];
-            const uint32_t wjk = __popc(rjk.x);
-            const uint32_t c = wjk + (rjk.y & 0xffu);
+            const uint32_t wjk = sv[u] & 0xffu;
+            const uint32_t c = sv[u] >> 8;
             if (kin[u]) {
               if (!(j < k)) continue;  // an adjacent pair of N_i, once
-              const uint32_t wik = __popc(wiv[u]);
-              const uint32_t t = __popc(mji & rjk.x);
+              const uint32_t wik = wiv[u];
+              const uint32_t t = __popc(mji & mv[u]);
               atomicAdd(&hist[lut[triple_code(a, b, c, p, 0u, wik, 0u)]], ~0ull);  // taken back
               atomicAdd(&hist[lut[triple_code(a, b, c, p, wjk, wik, t)]], 1ull);
             } else {
@@ -398,8 +399,8 @@ mochy_status sampled_edges_device(mochy_ctx* ctx, const mochy_graph* g, int64_t 
   if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
   k_hsample<false><<<unsigned(ctx->num_cus) * kHsBlocksPerCu, kHsThreads, dyn, st>>>(
-      n0, s, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
-      ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
+      n0, s, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->recm,
+      g->rsz, ctx->d_code_to_id3, queue, (unsigned long long*)d_hist);
   phase_end(ctx, kPhSample);
   const hipError_t e = hipGetLastError();
   it.release(ctx);
@@ -425,8 +426,8 @@ mochy_status profiles_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, i
   if (rc != MOCHY_OK) return rc;
   phase_begin(ctx, kPhSample);
   k_hsample<true><<<unsigned(ctx->num_cus) * kHsBlocksPerCu, kHsThreads, dyn, st>>>(
-      c0, n, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->rec,
-      ctx->d_code_to_id3, queue, (unsigned long long*)d_prof);
+      c0, n, it.sample_i, it.ioff, g->row_graph, g->geoff, g->edge_ptr, g->lg_ptr, g->lg_col, g->recm,
+      g->rsz, ctx->d_code_to_id3, queue, (unsigned long long*)d_prof);
   k_fold_rows<<<unsigned((n * MOCHY_NUM_H + 255) / 256), 256, 0, st>>>(n, d_prof, ctx->d_id3_to_id26,
                                                                         d_prof26);
   phase_end(ctx, kPhSample);
