@@ -95,18 +95,20 @@ VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 # operations and not counted):
 #  * a pair of neighbour groups that both have a member above the centre
 #    (its class is needed in full): the three mask intersections (centre
-#    nodes, two words of heavy outside nodes), an OR and a compare for the
-#    disjointness test, three population counts with their offsets added in
-#    the same instruction (t + 2, and R5 + 2 in two) and a shift-add for
-#    2 (|e_i| - |e_i ∩ e_k| + t), seven saturating subtracts max(2 - R, 0) for
-#    the ternary digits, six multiply-adds for the base-3 code (the last one
-#    doubling it into the table's byte offset), two selects and two
-#    multiplies for the 48-bit weight and one shift-add for the histogram
-#    address: 27;
+#    nodes, two words of heavy outside nodes), three population counts with
+#    their offsets added in the same instruction (t + 2, and R5 + 2 in two),
+#    an add and a compare for the disjointness test (t + R5 = 0), a
+#    shift-add for 2 (|e_i| - |e_i ∩ e_k| + t), seven saturating subtracts
+#    max(2 - R, 0) for the ternary digits, six multiply-adds for the base-3
+#    code (the last one doubling it into the table's byte offset), two
+#    selects, one multiply for the 32-bit weight and one add for the
+#    histogram address: 26 (27 where a row reaches 2^17 neighbours and the
+#    weight takes a second multiply for its high half);
 #  * any other pair of groups (counted only when open): the centre-node
-#    intersection, two AND-ORs for the heavy words, min(., 1) and a
-#    multiply-add into the run's overlap sum: 5.
-OPS_FULL_PAIR, OPS_OPEN_PAIR = 27, 5
+#    intersection, two AND-ORs for the heavy words, max(1 - x, 0) and a
+#    multiply-add into the run's sum over disjoint groups: 5.
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 26, 5
+WIDE_ROW = 1 << 17  # line-graph degree from which a pair weight takes 48 bits
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
 # (4-byte hyperedge id) for every scanned entry, and for every centre it finds
 # the partner row's 4-byte record mask and owner row's 2-byte size word.
@@ -752,7 +754,8 @@ def medium_exact(args):
     identity_ok = (s_open + 3 * s_closed) == st["candidates"]
 
     pair_ms = phase_sum["exact_pairs"] / K
-    ops = OPS_FULL_PAIR * xs["group_pairs_full"] + OPS_OPEN_PAIR * xs["group_pairs_open"]
+    ops_full = OPS_FULL_PAIR + (1 if st["max_line_degree"] >= WIDE_ROW else 0)
+    ops = ops_full * xs["group_pairs_full"] + OPS_OPEN_PAIR * xs["group_pairs_open"]
     achieved = ops / (pair_ms * 1e-3)
     fix_ms = phase_sum["exact_fix_kernel"] / K
     fix_bytes = FIX_BYTES_SCANNED * xs["fix_scanned"] + FIX_BYTES_CENTRE * xs["fix_centres"]
@@ -771,7 +774,7 @@ def medium_exact(args):
         "roofline": {"bound": "alu", "kernel": "k_exact_grouped (MoCHy-E pairs of neighbour groups)",
                      "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
                      "frac": achieved / valu_peak, "traffic": measured_traffic(),
-                     "model": f"{OPS_FULL_PAIR} integer lane operations per pair of neighbour groups "
+                     "model": f"{ops_full} integer lane operations per pair of neighbour groups "
                               f"classified in full, {OPS_OPEN_PAIR} per other pair (counted only when open)",
                      "peak_source": "integer VALU rate of mochy_calibrate_valu measured in this run "
                                     f"(chip-derived: 256 CUs x 64 lanes x 2.4 GHz = "

@@ -153,8 +153,10 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                      graphs report MOCHY_ENOMEM, so mochy_profile splits
                                      it; bit 3 leaves out the light-pair correction's
                                      flat candidate list, so its pairs are listed in a
-                                     counting and a filling pass (default 0); same
-                                     counts */
+                                     counting and a filling pass; bit 4 makes the pair
+                                     kernel form 64-bit pair weights, as for graphs
+                                     whose line-graph degree reaches 2^17 (default 0);
+                                     same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 
 /* Line-graph construction (Algorithm 1, section 4.1).  Validates the CSR,

@@ -434,7 +434,7 @@ extern "C" mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int
     if (ctx->cache_bytes > value) cache_release(ctx);
     return MOCHY_OK;
   }
-  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 15) {
+  if (option == MOCHY_OPT_TEST_FAULTS && value >= 0 && value <= 31) {
     ctx->test_faults = int(value);
     return MOCHY_OK;
   }

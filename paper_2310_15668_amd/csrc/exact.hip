@@ -663,14 +663,11 @@ __device__ __forceinline__ uint32_t mad6(uint32_t code, uint32_t d) {
 // from 2 (t + 2) + aks2 with aks2 = 2 aks - 4, so that the last multiply-add
 // (by 6) yields the offset.
 // jy is j's record word: oj in bits 0-7, pj in bits 8-15.
-__device__ __forceinline__ uint32_t pair_rcode2(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t aks2,
-                                                uint32_t jy, const Side& k) {
+__device__ __forceinline__ uint32_t pair_rcode2(uint32_t t2, uint32_t r2, uint32_t aks2, uint32_t jy,
+                                                const Side& k) {
   const uint32_t pj = (jy >> 8) & 0xffu, oj = jy & 0xffu;
-  const uint32_t t2 = uint32_t(__popc(xm)) + 2u;
   uint32_t v2;  // 2 (aks + t) = 2 t2 + aks2, one shift-add
   asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(v2) : "v"(t2), "v"(aks2));
-  uint32_t r2;  // two chained population counts (not two and an add)
-  asm("v_bcnt_u32_b32 %0, %1, 2\n\tv_bcnt_u32_b32 %0, %2, %0" : "=&v"(r2) : "v"(xl), "v"(xh));
   uint32_t c = usat(4u, t2);              // R7
   c = mad3(c, usat(t2, k.s));             // R6
   c = mad3(c, usat(4u, r2));              // R5
@@ -678,6 +675,18 @@ __device__ __forceinline__ uint32_t pair_rcode2(uint32_t xm, uint32_t xl, uint32
   c = mad3(c, usat(r2, k.o));             // R3
   c = mad3(c, usat(r2, oj));              // R2
   return mad6(c, usat(2u * pj + 4u, v2));  // R1, doubled
+}
+
+// t + 2 and r5 + 2 of a pair from its mask intersections (population counts
+// with the constant added in the same instruction; r5 over two words).
+__device__ __forceinline__ void pair_counts(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t& t2, uint32_t& r2) {
+  t2 = uint32_t(__popc(xm)) + 2u;
+  asm("v_bcnt_u32_b32 %0, %1, 2\n\tv_bcnt_u32_b32 %0, %2, %0" : "=&v"(r2) : "v"(xl), "v"(xh));
+}
+
+// The histogram word at a byte offset the class table gives.
+__device__ __forceinline__ unsigned long long* hist_at(unsigned long long* hist, uint32_t off) {
+  return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(hist) + off);
 }
 
 // The class table entry at a byte offset.
@@ -695,34 +704,44 @@ __device__ __forceinline__ uint32_t lut_at(const uint16_t* __restrict__ lut, uin
 // kAllA: every lane's group and j have members above the centre, so every
 // pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
 // past the row's end has N = A = 0 and adds 0 at a valid class).
-template <bool kDiag, bool kAllA>
+// kNarrow: every row is shorter than 2^17 neighbours, so the weight of a
+// pair of distinct groups, at most (row length / 2)^2, fits 32 bits and is
+// one 24-bit multiply (its high half is zero).
+template <bool kNarrow>
+__device__ __forceinline__ uint64_t pair_weight(uint32_t x, uint32_t y) {
+  return kNarrow ? uint64_t(x * y) : uint64_t(x) * y;
+}
+
+template <bool kDiag, bool kAllA, bool kNarrow>
 __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks2,
                                            const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
                                            uint32_t ka, int kp, const uint16_t* __restrict__ lut,
                                            unsigned long long* hist) {
   const uint32_t mj = rj.x;
   const uint32_t xm = mj & k.m, xl = rj.z & khl, xh = rj.w & khh;
-  const bool disjoint = (xm | xl | xh) == 0u;
+  uint32_t t2, r2;
+  pair_counts(xm, xl, xh, t2, r2);
+  const bool disjoint = t2 + r2 == 4u;  // t = r5 = 0 (one add, not a three-way OR)
   // j's counts arrive in vector registers (gwalk loads them per lane), so
   // the selects below need no copies of scalar values
   const uint32_t y = disjoint ? kn : ka;
   if (kAllA && !kDiag) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
-    const uint32_t rc2 = pair_rcode2(xm, xl, xh, aks2, rj.y, k);
-    atomicAdd(&hist[lut_at(lut, rc2)], uint64_t(x) * y);
+    const uint32_t rc2 = pair_rcode2(t2, r2, aks2, rj.y, k);
+    atomicAdd(hist_at(hist, lut_at(lut, rc2)), pair_weight<kNarrow>(x, y));
     return;
   }
   bool act = y != 0u;
   if (kDiag) act = act && (j < kp);
   if (act) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
-    const uint64_t w = uint64_t(x) * y;
-    const uint32_t rc2 = pair_rcode2(xm, xl, xh, aks2, rj.y, k);
-    atomicAdd(&hist[lut_at(lut, rc2)], w);
+    const uint64_t w = pair_weight<kNarrow>(x, y);
+    const uint32_t rc2 = pair_rcode2(t2, r2, aks2, rj.y, k);
+    atomicAdd(hist_at(hist, lut_at(lut, rc2)), w);
   }
 }
 
-template <bool kDiag, bool kAllA>
+template <bool kDiag, bool kAllA, bool kNarrow>
 __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint2* __restrict__ gc0,
                                       int j0, int j1, uint32_t aks, const Side& k, uint32_t kn,
                                       uint32_t ka, int kp, const uint16_t* __restrict__ lut,
@@ -738,13 +757,13 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag, kAllA>(r0, c0, j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r1, c1, j + 1, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r2, c2, j + 2, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA>(r3, c3, j + 3, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(r0, c0, j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(r1, c1, j + 1, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(r2, c2, j + 2, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(r3, c3, j + 3, aks2, k, khl, khh, kn, ka, kp, lut, hist);
   }
   for (; j < j1; ++j)
-    gpair_step<kDiag, kAllA>(grow[j], gc[j], j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(grow[j], gc[j], j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
 }
 
 // A pair in which one group has no member above the centre counts only when
@@ -760,7 +779,7 @@ __device__ __forceinline__ void open_flush(uint32_t cls, uint32_t acc, uint32_t 
   if (acc != 0u && kn != 0u) {
     const uint32_t pj = cls / 3u, oc = cls - 3u * pj;
     const uint32_t code = k0 + 27u * st3(pj) + 3u * oc + st3(aks - pj);
-    atomicAdd(&hist[lut[kNumCodes - 1 - code]], uint64_t(acc) * kn);
+    atomicAdd(hist_at(hist, lut[kNumCodes - 1 - code]), uint64_t(acc) * kn);
   }
 }
 
@@ -771,28 +790,29 @@ __device__ __forceinline__ uint32_t and_or(uint32_t a, uint32_t b, uint32_t c) {
   return r;
 }
 
-// acc += min(x, 1) * n (n < 2^24, from a scalar register): a minimum and a
+// acc += n if x = 0 (n < 2^24, from a scalar register): max(1 - x, 0), a
+// saturating subtract (a full-rate instruction, unlike a minimum), and a
 // 24-bit multiply-add, written as instructions so that they are not turned
-// into a compare and a select (x is overwritten).
-__device__ __forceinline__ void acc_overlap(uint32_t& acc, uint32_t& x, uint32_t n) {
-  asm("v_min_u32 %1, 1, %1\n\tv_mad_u32_u24 %0, %1, %2, %0" : "+v"(acc), "+v"(x) : "s"(n));
+// into a compare and a select.
+__device__ __forceinline__ void acc_disjoint(uint32_t& acc, uint32_t x, uint32_t n) {
+  uint32_t z;
+  asm("v_sub_u32_e64 %1, 1, %2 clamp\n\tv_mad_u32_u24 %0, %1, %3, %0" : "+v"(acc), "=&v"(z) : "v"(x), "s"(n));
 }
 
-// Lanes past the diagonal block take every j of a run: the run's sum of
-// nall_j (tot, uniform) less the sum over the j that overlap the lane's
-// group (acc), accumulated as min(overlap bits, 1) * nall_j in one
-// multiply-add.  The diagonal block (j < k only) adds per lane.
+// Lanes past the diagonal block sum nall_j over the j of a run that are
+// disjoint from the lane's group, as max(1 - overlap bits, 0) * nall_j (a
+// saturating subtract and a multiply-add).  The diagonal block (j < k
+// only) adds per lane.
 template <bool kDiag>
 __device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int j, const Side& k,
                                           uint32_t khl, uint32_t khh, uint32_t kn, int kp,
-                                          uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& tot,
-                                          uint32_t& acc, const uint16_t* __restrict__ lut,
+                                          uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& acc,
+                                          const uint16_t* __restrict__ lut,
                                           unsigned long long* hist) {
   const uint32_t cls = rj.y >> 16;  // uniform: the open class the grouping stored
   if (cls != cur) {
-    open_flush(cur, kDiag ? acc : tot - acc, aks, k0, kn, lut, hist);
+    open_flush(cur, acc, aks, k0, kn, lut, hist);
     cur = cls;
-    tot = 0u;
     acc = 0u;
   }
   if (kDiag) {
@@ -800,9 +820,8 @@ __device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int 
     act = act && (j < kp);
     if (act) acc += cj.x;
   } else {
-    uint32_t x = and_or(rj.w, khh, and_or(rj.z, khl, rj.x & k.m));
-    tot += cj.x;
-    acc_overlap(acc, x, cj.x);
+    const uint32_t x = and_or(rj.w, khh, and_or(rj.z, khl, rj.x & k.m));
+    acc_disjoint(acc, x, cj.x);
   }
 }
 
@@ -812,19 +831,19 @@ __device__ __forceinline__ void owalk(const uint4* __restrict__ grow, const uint
                                       uint32_t kn, int kp, const uint16_t* __restrict__ lut,
                                       unsigned long long* hist) {
   const uint32_t khl = uint32_t(k.h), khh = uint32_t(k.h >> 32);
-  uint32_t cur = 0u, tot = 0u, acc = 0u;
+  uint32_t cur = 0u, acc = 0u;
   int j = j0;
   for (; j + 4 <= j1; j += 4) {
     const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
     const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    open_step<kDiag>(r0, c0, j, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
-    open_step<kDiag>(r1, c1, j + 1, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
-    open_step<kDiag>(r2, c2, j + 2, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
-    open_step<kDiag>(r3, c3, j + 3, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
+    open_step<kDiag>(r0, c0, j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r1, c1, j + 1, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r2, c2, j + 2, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+    open_step<kDiag>(r3, c3, j + 3, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
   }
   for (; j < j1; ++j)
-    open_step<kDiag>(grow[j], gc[j], j, k, khl, khh, kn, kp, aks, k0, cur, tot, acc, lut, hist);
-  open_flush(cur, kDiag ? acc : tot - acc, aks, k0, kn, lut, hist);
+    open_step<kDiag>(grow[j], gc[j], j, k, khl, khh, kn, kp, aks, k0, cur, acc, lut, hist);
+  open_flush(cur, acc, aks, k0, kn, lut, hist);
 }
 
 __device__ __forceinline__ void gflush_wave(unsigned long long* whist, int lane, int64_t g,
@@ -858,7 +877,7 @@ constexpr int kGSharedThreads = 512;
 // work items count each graph with its own launch of the shared-histogram
 // kernel; others use per-wave histograms in one launch
 constexpr int kPerGraphLaunches = 256;
-template <bool kShared>
+template <bool kShared, bool kNarrow>
 __global__ __launch_bounds__(kShared ? kGSharedThreads : 256) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
@@ -869,7 +888,8 @@ __global__ __launch_bounds__(kShared ? kGSharedThreads : 256) void k_exact_group
   __shared__ uint16_t lut[kNumCodes];
   constexpr int kAll = kShared ? kGSharedCopies : kWavesPerGroup * kGCopies;
   __shared__ unsigned long long hist[kAll * kGStride];
-  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = code_to_id3[kNumCodes - 1 - t];  // indexed by the reversed code
+  // indexed by the reversed code; entries are byte offsets of the ids
+  for (int t = threadIdx.x; t < kNumCodes; t += blockDim.x) lut[t] = uint16_t(code_to_id3[kNumCodes - 1 - t] * 8u);
   for (int t = threadIdx.x; t < kAll * kGStride; t += blockDim.x) hist[t] = 0ull;
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
@@ -933,18 +953,18 @@ __global__ __launch_bounds__(kShared ? kGSharedThreads : 256) void k_exact_group
       owalk<false>(growb, gcb, na, blo, aks, k0, k, kn, kp, lut, myhist);
       owalk<true>(growb, gcb, blo, kmax, aks, k0, k, kn, kp, lut, myhist);
     } else if (blo + kWave <= na) {  // every lane has members above the centre
-      gwalk<false, true>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
-      gwalk<true, false>(grow, gc, blo, kmax, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<false, true, kNarrow>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, false, kNarrow>(grow, gc, blo, kmax, aks, k, kn, ka, kp, lut, myhist);
     } else {  // j with members above the centre: every pair; the others: open only
       const int ka1 = min(kmax, na);
-      gwalk<false, false>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
-      gwalk<true, false>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<false, false, kNarrow>(grow, gc, 0, blo, aks, k, kn, ka, kp, lut, myhist);
+      gwalk<true, false, kNarrow>(grow, gc, blo, ka1, aks, k, kn, ka, kp, lut, myhist);
       owalk<true>(growb, gcb, ka1, kmax, aks, k0, k, kn, kp, lut, myhist);
     }
     if (valid && ka >= 2u) {  // pairs inside the group: above the centre only
       const uint32_t r5 = uint32_t(__popcll(k.h));
       const uint32_t code = pair_code(a, k.s, k.o, k, k.s, r5);
-      atomicAdd(&myhist[lut[kNumCodes - 1 - code]], uint64_t(ka) * (ka - 1u) / 2u);
+      atomicAdd(hist_at(myhist, lut[kNumCodes - 1 - code]), uint64_t(ka) * (ka - 1u) / 2u);
     }
   }
   if (kShared) {
@@ -1216,6 +1236,10 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     MOCHY_HIP_OR(hipStreamSynchronize(st), release);
     if (ctx->batch_launch == 0 && hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
   }
+  // rows shorter than 2^17 neighbours: 32-bit pair weights (test bit 4
+  // takes the 64-bit form regardless)
+  const bool narrow = g->max_deg < (1 << 17) && !(ctx->test_faults & 16);
+  const auto kshared = narrow ? k_exact_grouped<true, true> : k_exact_grouped<true, false>;
   if (!hgq.empty()) {
     if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) return release(rc);
     launch_fill_u32(gqueue, 0u, size_t(ng) * 8, st);
@@ -1224,17 +1248,17 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
       if (items <= 0) continue;
       // at most one wave per item
       const unsigned ggrid = unsigned(std::min<int64_t>(sgrid, (items + kSharedWaves - 1) / kSharedWaves));
-      k_exact_grouped<true><<<ggrid, kGSharedThreads, 0, st>>>(
+      kshared<<<ggrid, kGSharedThreads, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, hgq[gi], hgq[gi + 1],
           g->row_graph, gqueue + gi, ctx->d_code_to_id3, (unsigned long long*)d_hist + size_t(gi) * kHistSlots);
     }
   } else if (grouped) {
     if (ng == 1)
-      k_exact_grouped<true><<<sgrid, kGSharedThreads, 0, st>>>(
+      kshared<<<sgrid, kGSharedThreads, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
           S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
     else
-      k_exact_grouped<false><<<grid, 256, 0, st>>>(
+      (narrow ? k_exact_grouped<false, true> : k_exact_grouped<false, false>)<<<grid, 256, 0, st>>>(
           g->edge_ptr, goff, gbase, cap0, grec, gcnt, gna, S.order, S.rstart, S.rows, 0, -1, g->row_graph,
           S.queue, ctx->d_code_to_id3, (unsigned long long*)d_hist);
   } else {

@@ -359,7 +359,25 @@ def test_row_capacity_fallback(ctx):
         g.close()
     assert (a431 == b431).all() and (a26 == b26).all()
     with pytest.raises(M.MochyError):
-        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 16)
+        ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 32)
+
+
+def test_wide_pair_weights(ctx):
+    # the pair kernel's 64-bit weights (taken when a row reaches 2^17
+    # neighbours) forced on graphs whose weights fit 32 bits: same counts
+    import paper_2310_15668_amd as M
+    for h in (make_config("medium", scale=0.03), powerlaw_hypergraph(300, 2000, 2, 20, 2.5, 0.9, seed=23)):
+        print(f"[gpu] 64-bit pair weights |E|={h.num_edges}", flush=True)
+        g = M.mochy_project(ctx, h.edge_ptr, h.edge_nodes, h.num_nodes)
+        try:
+            a26, a431 = M.mochy_count_exact(ctx, g)
+            ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 16)
+            b26, b431 = M.mochy_count_exact(ctx, g)
+        finally:
+            ctx.set_option(M.MOCHY_OPT_TEST_FAULTS, 0)
+            g.close()
+        assert int(b431.sum()) > 0
+        assert (a431 == b431).all() and (a26 == b26).all()
 
 
 def test_light_pairs_two_passes(ctx):
