@@ -82,32 +82,35 @@ def summary_values(summary, source):
 
 # Integer vector-ALU ceiling from the chip's unit counts: 256 CUs, each with
 # 4 SIMD units of 16 lanes (one wave64 instruction per CU per cycle), at the
-# 2.4 GHz peak engine clock: 39.3e12 32-bit lane operations per second.  A
+# 2.4 GHz peak engine clock: 39.3e12 32-bit lane instructions per second.  A
 # pure integer-VALU kernel of the pair kernel's instruction mix
-# (mochy_calibrate_valu) sustains about 1.06 of it on the box, so the
-# roofline takes the measured rate, from the same run, as its peak.
+# (mochy_calibrate_valu) sustains about that on the box, so the roofline
+# takes the measured rate, from the same run, as its peak.
 NUM_CUS, CLOCK_HZ, LANES = 256, 2.4e9, 64
 VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 
-# Algorithmic integer operations per unit of the exact pair kernel (Lemma 2's
-# region sizes from the two neighbours' records; every operation a 32-bit
-# vector lane operation; the class-table read and the histogram add are LDS
-# operations and not counted):
+# Algorithmic integer vector instructions per unit of the exact pair kernel
+# (Lemma 2's region sizes from the two neighbours' records; counted as
+# instructions, as the calibrated ceiling is, so a packed instruction that
+# does two 16-bit operations counts once; the class-table read and the
+# histogram add are LDS operations and not counted):
 #  * a pair of neighbour groups that both have a member above the centre
 #    (its class is needed in full): the three mask intersections (centre
 #    nodes, two words of heavy outside nodes), three population counts with
 #    their offsets added in the same instruction (t + 2, and R5 + 2 in two),
-#    an add and a compare for the disjointness test (t + R5 = 0), a
-#    shift-add for 2 (|e_i| - |e_i ∩ e_k| + t), seven saturating subtracts
-#    max(2 - R, 0) for the ternary digits, six multiply-adds for the base-3
-#    code (the last one doubling it into the table's byte offset), two
-#    selects, one multiply for the 32-bit weight and one add for the
-#    histogram address: 26 (27 where a row reaches 2^17 neighbours and the
-#    weight takes a second multiply for its high half);
+#    a shift-or packing t + 2 and R5 + 2 into the halves of one word, a
+#    compare of that word for the disjointness test (t = R5 = 0), a
+#    shift-add for 2 (|e_i| - |e_i ∩ e_k| + t), the seven ternary digits
+#    max(2 - R, 0) as one saturating subtract and three packed ones (two
+#    digits each), the base-3 code doubled into the table's byte offset as
+#    three two-term dot products, two selects, one multiply for the 32-bit
+#    weight and one add for the histogram address: 20 (26 operations; 21
+#    where a row reaches 2^17 neighbours and the weight takes a second
+#    multiply for its high half);
 #  * any other pair of groups (counted only when open): the centre-node
 #    intersection, two AND-ORs for the heavy words, max(1 - x, 0) and a
 #    multiply-add into the run's sum over disjoint groups: 5.
-OPS_FULL_PAIR, OPS_OPEN_PAIR = 26, 5
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 20, 5
 WIDE_ROW = 1 << 17  # line-graph degree from which a pair weight takes 48 bits
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
 # (4-byte hyperedge id) for every scanned entry, and for every centre it finds
@@ -132,7 +135,7 @@ def valu_issue(kernel_ms, ceiling):
 
 
 def valu_calibration(M, ctx, iters=1 << 16, runs=3):
-    """Best integer-VALU rate (lane operations/s) of mochy_calibrate_valu."""
+    """Best integer-VALU rate (lane instructions/s) of mochy_calibrate_valu."""
     best = 0.0
     for _ in range(runs):
         ms, ops = M.mochy_calibrate_valu(ctx, iters)
@@ -774,7 +777,7 @@ def medium_exact(args):
         "roofline": {"bound": "alu", "kernel": "k_exact_grouped (MoCHy-E pairs of neighbour groups)",
                      "achieved": achieved / 1e12, "peak": valu_peak / 1e12, "unit": "TOP/s",
                      "frac": achieved / valu_peak, "traffic": measured_traffic(),
-                     "model": f"{ops_full} integer lane operations per pair of neighbour groups "
+                     "model": f"{ops_full} integer vector lane instructions per pair of neighbour groups "
                               f"classified in full, {OPS_OPEN_PAIR} per other pair (counted only when open)",
                      "peak_source": "integer VALU rate of mochy_calibrate_valu measured in this run "
                                     f"(chip-derived: 256 CUs x 64 lanes x 2.4 GHz = "

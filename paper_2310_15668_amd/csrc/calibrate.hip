@@ -1,14 +1,17 @@
 // Measurement helper: the integer VALU issue rate the device sustains.
 //
 // Every lane runs `iters` rounds of 32 dependent-by-chain 32-bit integer
-// vector instructions, the mix the exact pair kernel is made of (and, or,
-// xor, population count, add, subtract, min, 24-bit multiply-add), over 8
-// independent accumulator chains so that issue, not latency, sets the rate.
-// The instructions are written out so that their number is exact: one round
-// is 32 wave instructions per wave.  The grid holds 8 blocks of 256 threads
-// per compute unit (32 waves per CU).  The result is a ceiling for integer
-// ALU work measured on the chip itself, which the pair kernel's rate is
-// compared against.
+// vector instructions in the proportions the exact pair kernel issues them
+// (its full-class and open pairs weighted by their counts on the medium
+// workload): AND, add and saturating subtract (the full-rate kinds, 11 of
+// 32), population count, shift-or, shift-add, packed 16-bit saturating
+// subtract, two-term 16-bit dot product, select, 24-bit multiply, AND-OR and
+// 24-bit multiply-add (21 of 32), over 8 independent accumulator chains so
+// that issue, not latency, sets the rate.  The instructions are written out
+// so that their number is exact: one round is 32 wave instructions per wave.
+// The grid holds 8 blocks of 256 threads per compute unit (32 waves per CU).
+// The result is a ceiling for integer ALU work of that mix measured on the
+// chip itself, which the pair kernel's rate is compared against.
 #include "common.h"
 
 namespace {
@@ -21,42 +24,43 @@ __global__ __launch_bounds__(kCalThreads) void k_valu_calibrate(int64_t iters, u
   uint32_t a0 = seed ^ threadIdx.x, a1 = a0 * 3u, a2 = a0 * 5u, a3 = a0 * 7u;
   uint32_t a4 = a0 * 11u, a5 = a0 * 13u, a6 = a0 * 17u, a7 = a0 * 19u;
   const uint32_t k = seed | 1u;
+  const uint64_t m = uint64_t(seed >> 31);  // an all-clear select mask (the seeds are below 2^31)
   for (int64_t n = 0; n < iters; ++n) {
     asm volatile(
         "v_and_b32 %0, %0, %8\n\t"
-        "v_or_b32 %1, %1, %8\n\t"
-        "v_xor_b32 %2, %2, %8\n\t"
-        "v_bcnt_u32_b32 %3, %3, %8\n\t"
-        "v_add_u32 %4, %4, %8\n\t"
-        "v_sub_u32 %5, %5, %8\n\t"
-        "v_min_u32 %6, %6, %8\n\t"
-        "v_mad_u32_u24 %7, %7, 3, %8\n\t"
-        "v_or_b32 %0, %0, %8\n\t"
-        "v_xor_b32 %1, %1, %8\n\t"
-        "v_bcnt_u32_b32 %2, %2, %8\n\t"
-        "v_add_u32 %3, %3, %8\n\t"
-        "v_sub_u32 %4, %4, %8\n\t"
-        "v_min_u32 %5, %5, %8\n\t"
-        "v_mad_u32_u24 %6, %6, 3, %8\n\t"
-        "v_and_b32 %7, %7, %8\n\t"
-        "v_xor_b32 %0, %0, %8\n\t"
         "v_bcnt_u32_b32 %1, %1, %8\n\t"
-        "v_add_u32 %2, %2, %8\n\t"
-        "v_sub_u32 %3, %3, %8\n\t"
-        "v_min_u32 %4, %4, %8\n\t"
+        "v_pk_sub_u16 %2, %2, %8 clamp\n\t"
+        "v_dot2_u32_u16 %3, %3, %8, %3\n\t"
+        "v_sub_u32_e64 %4, %4, %8 clamp\n\t"
+        "v_and_or_b32 %5, %5, %8, %8\n\t"
+        "v_cndmask_b32_e64 %6, %6, %8, %9\n\t"
+        "v_add_u32 %7, %7, %8\n\t"
+        "v_bcnt_u32_b32 %0, %0, %8\n\t"
+        "v_pk_sub_u16 %1, %1, %8 clamp\n\t"
+        "v_dot2_u32_u16 %2, %2, %8, %2\n\t"
+        "v_and_b32 %3, %3, %8\n\t"
+        "v_and_or_b32 %4, %4, %8, %8\n\t"
         "v_mad_u32_u24 %5, %5, 3, %8\n\t"
         "v_and_b32 %6, %6, %8\n\t"
-        "v_or_b32 %7, %7, %8\n\t"
-        "v_bcnt_u32_b32 %0, %0, %8\n\t"
-        "v_add_u32 %1, %1, %8\n\t"
-        "v_sub_u32 %2, %2, %8\n\t"
-        "v_min_u32 %3, %3, %8\n\t"
-        "v_mad_u32_u24 %4, %4, 3, %8\n\t"
+        "v_lshl_or_b32 %7, %7, 16, %8\n\t"
+        "v_sub_u32_e64 %0, %0, %8 clamp\n\t"
+        "v_and_b32 %1, %1, %8\n\t"
+        "v_cndmask_b32_e64 %2, %2, %8, %9\n\t"
+        "v_bcnt_u32_b32 %3, %3, %8\n\t"
+        "v_pk_sub_u16 %4, %4, %8 clamp\n\t"
         "v_and_b32 %5, %5, %8\n\t"
-        "v_or_b32 %6, %6, %8\n\t"
-        "v_xor_b32 %7, %7, %8\n\t"
+        "v_dot2_u32_u16 %6, %6, %8, %6\n\t"
+        "v_and_or_b32 %7, %7, %8, %8\n\t"
+        "v_lshl_add_u32 %0, %0, 1, %8\n\t"
+        "v_mul_u32_u24 %1, %1, %8\n\t"
+        "v_and_b32 %2, %2, %8\n\t"
+        "v_sub_u32_e64 %3, %3, %8 clamp\n\t"
+        "v_cndmask_b32_e64 %4, %4, %8, %9\n\t"
+        "v_and_or_b32 %5, %5, %8, %8\n\t"
+        "v_add_u32 %6, %6, %8\n\t"
+        "v_mad_u32_u24 %7, %7, 3, %8\n\t"
         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
-        : "v"(k));
+        : "v"(k), "s"(m));
   }
   const uint32_t r = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
   if (r == 0x9E3779B9u) out[0] = r;  // keeps the chains live; almost never taken

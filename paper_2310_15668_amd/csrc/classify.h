@@ -14,15 +14,6 @@ struct Side {          // a neighbour of the centre
 
 __device__ __forceinline__ uint32_t st3(uint32_t c) { return c < 2u ? c : 2u; }
 
-// code * 3 + d as one full-rate 24-bit multiply-add.  Written as an ALU
-// instruction so that a Horner chain of them is not merged with the table
-// offset formed from its result into 64-bit multiplies.
-__device__ __forceinline__ uint32_t mad3(uint32_t code, uint32_t d) {
-  uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, 3, %2" : "=v"(r) : "v"(code), "v"(d));
-  return r;
-}
-
 // Ternary code sum_r min(R_r, 2) * 3^r (R1 least significant) of the triple
 // (e_i, e_j, e_k): a = |e_i|, j given by (pj = popcount(mj), oj), k by `k`,
 // t = |e_i ∩ e_j ∩ e_k|, r5 = |e_j ∩ e_k - e_i|.

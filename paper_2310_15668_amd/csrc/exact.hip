@@ -645,43 +645,65 @@ constexpr int kGStride = kHistSlots + 1;
 // max(a - b, 0) in one saturating subtract.
 __device__ __forceinline__ uint32_t usat(uint32_t a, uint32_t b) { return a > b ? a - b : 0u; }
 
-// code * 6 + d as one 24-bit multiply-add (the Horner step that also doubles
-// the code into the class table's byte offset).
-__device__ __forceinline__ uint32_t mad6(uint32_t code, uint32_t d) {
+// max(a - b, 0) on both 16-bit halves at once (a packed saturating subtract).
+__device__ __forceinline__ uint32_t pk_usat_sv(uint32_t a, uint32_t b) {  // a uniform
   uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, 6, %2" : "=v"(r) : "v"(code), "v"(d));
+  asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(r) : "s"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ uint32_t pk_usat_vv(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ uint32_t pk_usat_vs(uint32_t a, uint32_t b) {  // b uniform
+  uint32_t r;
+  asm("v_pk_sub_u16 %0, %1, %2 clamp" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+
+// lo(d) * lo(w) + hi(d) * hi(w) + c, 16-bit halves (w uniform): two
+// multiply-adds of a Horner chain in one instruction.
+__device__ __forceinline__ uint32_t dot2(uint32_t d, uint32_t w, uint32_t c) {
+  uint32_t r;
+  asm("v_dot2_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(d), "s"(w), "v"(c));
   return r;
 }
 
 // Twice the reversed ternary code 2186 - code of a pair (code as
 // pair_code gives it, same digit order): the byte offset of its entry in
 // the pair kernel's class table (stored reversed, 2-byte entries).  Digit r
-// enters as 2 - min(R_r, 2) = max(2 - R_r, 0), one saturating subtract from
+// enters as 2 - min(R_r, 2) = max(2 - R_r, 0), a saturating subtract from
 // t + 2 = |e_i ∩ e_j ∩ e_k| + 2 and r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy
-// part), each a population count with the constant added in the same
-// instruction; R1 = aks - pj + t (aks = |e_i| - |e_i ∩ e_k|) enters doubled,
-// from 2 (t + 2) + aks2 with aks2 = 2 aks - 4, so that the last multiply-add
-// (by 6) yields the offset.
-// jy is j's record word: oj in bits 0-7, pj in bits 8-15.
-__device__ __forceinline__ uint32_t pair_rcode2(uint32_t t2, uint32_t r2, uint32_t aks2, uint32_t jy,
-                                                const Side& k) {
+// part), held as the two halves of tr: R7 and R5 against 2, R6 and R3
+// against k's (|e_i ∩ e_k|, outside count), R4 and R2 against j's, each
+// pair of digits one packed subtract; the weighted sum 2 (3^6 R7 + ... + R1)
+// is three two-term dot products over those pairs.  R1 = aks - pj + t (aks =
+// |e_i| - |e_i ∩ e_k|) enters doubled, from 2 (t + 2) + aks2 with aks2 =
+// 2 aks - 4.
+// jy is j's record word: oj in bits 0-7, pj in bits 8-15; kso = k.s | k.o << 16.
+__device__ __forceinline__ uint32_t pair_rcode2(uint32_t t2, uint32_t tr, uint32_t aks2, uint32_t jy,
+                                                uint32_t kso) {
   const uint32_t pj = (jy >> 8) & 0xffu, oj = jy & 0xffu;
   uint32_t v2;  // 2 (aks + t) = 2 t2 + aks2, one shift-add
   asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(v2) : "v"(t2), "v"(aks2));
-  uint32_t c = usat(4u, t2);              // R7
-  c = mad3(c, usat(t2, k.s));             // R6
-  c = mad3(c, usat(4u, r2));              // R5
-  c = mad3(c, usat(t2, pj));              // R4
-  c = mad3(c, usat(r2, k.o));             // R3
-  c = mad3(c, usat(r2, oj));              // R2
-  return mad6(c, usat(2u * pj + 4u, v2));  // R1, doubled
+  const uint32_t d75 = pk_usat_sv(0x00040004u, tr);     // (R7, R5)
+  const uint32_t d63 = pk_usat_vv(tr, kso);             // (R6, R3)
+  const uint32_t d42 = pk_usat_vs(tr, pj | (oj << 16));  // (R4, R2)
+  uint32_t c = usat(2u * pj + 4u, v2);                  // 2 R1
+  c = dot2(d42, 54u | (6u << 16), c);
+  c = dot2(d63, 486u | (18u << 16), c);
+  return dot2(d75, 1458u | (162u << 16), c);
 }
 
 // t + 2 and r5 + 2 of a pair from its mask intersections (population counts
 // with the constant added in the same instruction; r5 over two words).
-__device__ __forceinline__ void pair_counts(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t& t2, uint32_t& r2) {
+// tr = (t + 2) | (r5 + 2) << 16.
+__device__ __forceinline__ void pair_counts(uint32_t xm, uint32_t xl, uint32_t xh, uint32_t& t2, uint32_t& tr) {
   t2 = uint32_t(__popc(xm)) + 2u;
+  uint32_t r2;
   asm("v_bcnt_u32_b32 %0, %1, 2\n\tv_bcnt_u32_b32 %0, %2, %0" : "=&v"(r2) : "v"(xl), "v"(xh));
+  asm("v_lshl_or_b32 %0, %1, 16, %2" : "=v"(tr) : "v"(r2), "v"(t2));
 }
 
 // The histogram word at a byte offset the class table gives.
@@ -714,20 +736,20 @@ __device__ __forceinline__ uint64_t pair_weight(uint32_t x, uint32_t y) {
 
 template <bool kDiag, bool kAllA, bool kNarrow>
 __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int j, uint32_t aks2,
-                                           const Side& k, uint32_t khl, uint32_t khh, uint32_t kn,
-                                           uint32_t ka, int kp, const uint16_t* __restrict__ lut,
+                                           const Side& k, uint32_t khl, uint32_t khh, uint32_t kso,
+                                           uint32_t kn, uint32_t ka, int kp, const uint16_t* __restrict__ lut,
                                            unsigned long long* hist) {
   const uint32_t mj = rj.x;
   const uint32_t xm = mj & k.m, xl = rj.z & khl, xh = rj.w & khh;
-  uint32_t t2, r2;
-  pair_counts(xm, xl, xh, t2, r2);
-  const bool disjoint = t2 + r2 == 4u;  // t = r5 = 0 (one add, not a three-way OR)
+  uint32_t t2, tr;
+  pair_counts(xm, xl, xh, t2, tr);
+  const bool disjoint = tr == 0x00020002u;  // t = r5 = 0
   // j's counts arrive in vector registers (gwalk loads them per lane), so
   // the selects below need no copies of scalar values
   const uint32_t y = disjoint ? kn : ka;
   if (kAllA && !kDiag) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
-    const uint32_t rc2 = pair_rcode2(t2, r2, aks2, rj.y, k);
+    const uint32_t rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
     atomicAdd(hist_at(hist, lut_at(lut, rc2)), pair_weight<kNarrow>(x, y));
     return;
   }
@@ -736,9 +758,25 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   if (act) {
     const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
     const uint64_t w = pair_weight<kNarrow>(x, y);
-    const uint32_t rc2 = pair_rcode2(t2, r2, aks2, rj.y, k);
+    const uint32_t rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
     atomicAdd(hist_at(hist, lut_at(lut, rc2)), w);
   }
+}
+
+// A full-class pair's class table offset and weight (every lane's group and
+// j with members above the centre).
+template <bool kNarrow>
+__device__ __forceinline__ void pair_full(const uint4& rj, const uint2& cj, uint32_t aks2, const Side& k,
+                                          uint32_t khl, uint32_t khh, uint32_t kso, uint32_t kn,
+                                          uint32_t ka, uint32_t& rc2, uint64_t& w) {
+  const uint32_t xm = rj.x & k.m, xl = rj.z & khl, xh = rj.w & khh;
+  uint32_t t2, tr;
+  pair_counts(xm, xl, xh, t2, tr);
+  const bool disjoint = tr == 0x00020002u;  // t = r5 = 0
+  const uint32_t y = disjoint ? kn : ka;
+  const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
+  rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
+  w = pair_weight<kNarrow>(x, y);
 }
 
 template <bool kDiag, bool kAllA, bool kNarrow>
@@ -753,17 +791,41 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   asm volatile("" : "+v"(z));
   const uint2* gc = gc0 + z;
   const uint32_t aks2 = 2u * aks - 4u;
+  const uint32_t kso = k.s | (k.o << 16);
   int j = j0;
-  for (; j + 4 <= j1; j += 4) {
-    const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
-    const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
-    gpair_step<kDiag, kAllA, kNarrow>(r0, c0, j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA, kNarrow>(r1, c1, j + 1, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA, kNarrow>(r2, c2, j + 2, aks2, k, khl, khh, kn, ka, kp, lut, hist);
-    gpair_step<kDiag, kAllA, kNarrow>(r3, c3, j + 3, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+  if (kAllA && !kDiag) {
+    // four pairs at a time: the four class table reads are issued together
+    // and waited for once, then the four histogram adds
+    for (; j + 4 <= j1; j += 4) {
+      const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
+      const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
+      uint32_t o0, o1, o2, o3;
+      uint64_t w0, w1, w2, w3;
+      pair_full<kNarrow>(r0, c0, aks2, k, khl, khh, kso, kn, ka, o0, w0);
+      pair_full<kNarrow>(r1, c1, aks2, k, khl, khh, kso, kn, ka, o1, w1);
+      pair_full<kNarrow>(r2, c2, aks2, k, khl, khh, kso, kn, ka, o2, w2);
+      pair_full<kNarrow>(r3, c3, aks2, k, khl, khh, kso, kn, ka, o3, w3);
+      o0 = lut_at(lut, o0);
+      o1 = lut_at(lut, o1);
+      o2 = lut_at(lut, o2);
+      o3 = lut_at(lut, o3);
+      atomicAdd(hist_at(hist, o0), w0);
+      atomicAdd(hist_at(hist, o1), w1);
+      atomicAdd(hist_at(hist, o2), w2);
+      atomicAdd(hist_at(hist, o3), w3);
+    }
+  } else {
+    for (; j + 4 <= j1; j += 4) {
+      const uint4 r0 = grow[j], r1 = grow[j + 1], r2 = grow[j + 2], r3 = grow[j + 3];
+      const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
+      gpair_step<kDiag, kAllA, kNarrow>(r0, c0, j, aks2, k, khl, khh, kso, kn, ka, kp, lut, hist);
+      gpair_step<kDiag, kAllA, kNarrow>(r1, c1, j + 1, aks2, k, khl, khh, kso, kn, ka, kp, lut, hist);
+      gpair_step<kDiag, kAllA, kNarrow>(r2, c2, j + 2, aks2, k, khl, khh, kso, kn, ka, kp, lut, hist);
+      gpair_step<kDiag, kAllA, kNarrow>(r3, c3, j + 3, aks2, k, khl, khh, kso, kn, ka, kp, lut, hist);
+    }
   }
   for (; j < j1; ++j)
-    gpair_step<kDiag, kAllA, kNarrow>(grow[j], gc[j], j, aks2, k, khl, khh, kn, ka, kp, lut, hist);
+    gpair_step<kDiag, kAllA, kNarrow>(grow[j], gc[j], j, aks2, k, khl, khh, kso, kn, ka, kp, lut, hist);
 }
 
 // A pair in which one group has no member above the centre counts only when
@@ -877,8 +939,15 @@ constexpr int kGSharedThreads = 512;
 // work items count each graph with its own launch of the shared-histogram
 // kernel; others use per-wave histograms in one launch
 constexpr int kPerGraphLaunches = 256;
+// At most 100 scalar registers for the shared-histogram kernel, so that a
+// SIMD holds 8 of its waves (4 blocks of 512 threads per compute unit, the
+// default launch); its loops left to themselves take 106 registers, which
+// allow 7 waves per SIMD and so only 3 blocks per compute unit (measured on
+// medium: 403 ms at 3 blocks, 360 ms at 4).  The per-wave-histogram kernel
+// is held to 5 waves per SIMD by its shared memory anyway.
 template <bool kShared, bool kNarrow>
-__global__ __launch_bounds__(kShared ? kGSharedThreads : 256) void k_exact_grouped(
+__global__ __launch_bounds__(kShared ? kGSharedThreads : 256)
+__attribute__((amdgpu_waves_per_eu(kShared ? 8 : 5, 8))) void k_exact_grouped(
     const int64_t* __restrict__ edge_ptr, const int64_t* __restrict__ goff,
     const int64_t* __restrict__ gbase, int64_t cap0,
     const uint4* __restrict__ grec, const uint2* __restrict__ gcnt, const int32_t* __restrict__ gna,
