@@ -103,15 +103,16 @@ VALU_PEAK_DERIVED = NUM_CUS * LANES * CLOCK_HZ
 #    shift-add for 2 (|e_i| - |e_i ∩ e_k| + t), the seven ternary digits
 #    max(2 - R, 0) as one saturating subtract and three packed ones (two
 #    digits each), the base-3 code doubled into the table's byte offset as
-#    three two-term dot products, two selects, one multiply for the 32-bit
-#    weight and one add for the histogram address: 20 (26 operations; 21
-#    where a row reaches 2^17 neighbours and the weight takes a second
-#    multiply for its high half);
+#    three two-term dot products, the weight N_j N_k or A_j A_k as a select
+#    of the lane's (0, N_k) or (A_k, 0) and a two-term dot product with j's
+#    counts packed as 16-bit halves, and one add for the histogram address:
+#    19 (21 where a row reaches 2^16 neighbours, the counts no longer fit 16
+#    bits and the weight takes two selects and two multiplies for 48 bits);
 #  * any other pair of groups (counted only when open): the centre-node
 #    intersection, two AND-ORs for the heavy words, max(1 - x, 0) and a
 #    multiply-add into the run's sum over disjoint groups: 5.
-OPS_FULL_PAIR, OPS_OPEN_PAIR = 20, 5
-WIDE_ROW = 1 << 17  # line-graph degree from which a pair weight takes 48 bits
+OPS_FULL_PAIR, OPS_OPEN_PAIR = 19, 5
+WIDE_ROW = 1 << 16  # line-graph degree from which a pair weight takes 48 bits
 # Algorithmic bytes of the light-pair fix kernel: the partner row's entry
 # (4-byte hyperedge id) for every scanned entry, and for every centre it finds
 # the partner row's 4-byte record mask and owner row's 2-byte size word.
@@ -757,7 +758,7 @@ def medium_exact(args):
     identity_ok = (s_open + 3 * s_closed) == st["candidates"]
 
     pair_ms = phase_sum["exact_pairs"] / K
-    ops_full = OPS_FULL_PAIR + (1 if st["max_line_degree"] >= WIDE_ROW else 0)
+    ops_full = OPS_FULL_PAIR + (2 if st["max_line_degree"] >= WIDE_ROW else 0)
     ops = ops_full * xs["group_pairs_full"] + OPS_OPEN_PAIR * xs["group_pairs_open"]
     achieved = ops / (pair_ms * 1e-3)
     fix_ms = phase_sum["exact_fix_kernel"] / K

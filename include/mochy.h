@@ -154,8 +154,9 @@ const char* mochy_last_error(const mochy_ctx* ctx);
                                      it; bit 3 leaves out the light-pair correction's
                                      flat candidate list, so its pairs are listed in a
                                      counting and a filling pass; bit 4 makes the pair
-                                     kernel form 64-bit pair weights, as for graphs
-                                     whose line-graph degree reaches 2^17 (default 0);
+                                     kernel form 48-bit pair weights from unpacked group
+                                     counts, as for graphs whose line-graph degree
+                                     reaches 2^16 (default 0);
                                      same counts */
 mochy_status mochy_ctx_set_option(mochy_ctx* ctx, int32_t option, int64_t value);
 

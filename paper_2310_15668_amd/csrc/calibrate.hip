@@ -3,11 +3,11 @@
 // Every lane runs `iters` rounds of 32 dependent-by-chain 32-bit integer
 // vector instructions in the proportions the exact pair kernel issues them
 // (its full-class and open pairs weighted by their counts on the medium
-// workload): AND, add and saturating subtract (the full-rate kinds, 11 of
+// workload): AND, add and saturating subtract (the full-rate kinds, 9 of
 // 32), population count, shift-or, shift-add, packed 16-bit saturating
-// subtract, two-term 16-bit dot product, select, 24-bit multiply, AND-OR and
-// 24-bit multiply-add (21 of 32), over 8 independent accumulator chains so
-// that issue, not latency, sets the rate.  The instructions are written out
+// subtract, two-term 16-bit dot product, select, AND-OR and 24-bit
+// multiply-add (23 of 32), over 8 independent accumulator chains so that
+// issue, not latency, sets the rate.  The instructions are written out
 // so that their number is exact: one round is 32 wave instructions per wave.
 // The grid holds 8 blocks of 256 threads per compute unit (32 waves per CU).
 // The result is a ceiling for integer ALU work of that mix measured on the
@@ -34,30 +34,30 @@ __global__ __launch_bounds__(kCalThreads) void k_valu_calibrate(int64_t iters, u
         "v_sub_u32_e64 %4, %4, %8 clamp\n\t"
         "v_and_or_b32 %5, %5, %8, %8\n\t"
         "v_cndmask_b32_e64 %6, %6, %8, %9\n\t"
-        "v_add_u32 %7, %7, %8\n\t"
+        "v_dot2_u32_u16 %7, %7, %8, %7\n\t"
         "v_bcnt_u32_b32 %0, %0, %8\n\t"
         "v_pk_sub_u16 %1, %1, %8 clamp\n\t"
-        "v_dot2_u32_u16 %2, %2, %8, %2\n\t"
-        "v_and_b32 %3, %3, %8\n\t"
+        "v_and_b32 %2, %2, %8\n\t"
+        "v_dot2_u32_u16 %3, %3, %8, %3\n\t"
         "v_and_or_b32 %4, %4, %8, %8\n\t"
         "v_mad_u32_u24 %5, %5, 3, %8\n\t"
         "v_and_b32 %6, %6, %8\n\t"
         "v_lshl_or_b32 %7, %7, 16, %8\n\t"
         "v_sub_u32_e64 %0, %0, %8 clamp\n\t"
         "v_and_b32 %1, %1, %8\n\t"
-        "v_cndmask_b32_e64 %2, %2, %8, %9\n\t"
-        "v_bcnt_u32_b32 %3, %3, %8\n\t"
-        "v_pk_sub_u16 %4, %4, %8 clamp\n\t"
-        "v_and_b32 %5, %5, %8\n\t"
-        "v_dot2_u32_u16 %6, %6, %8, %6\n\t"
-        "v_and_or_b32 %7, %7, %8, %8\n\t"
+        "v_bcnt_u32_b32 %2, %2, %8\n\t"
+        "v_pk_sub_u16 %3, %3, %8 clamp\n\t"
+        "v_dot2_u32_u16 %4, %4, %8, %4\n\t"
+        "v_and_or_b32 %5, %5, %8, %8\n\t"
+        "v_cndmask_b32_e64 %6, %6, %8, %9\n\t"
+        "v_add_u32 %7, %7, %8\n\t"
         "v_lshl_add_u32 %0, %0, 1, %8\n\t"
-        "v_mul_u32_u24 %1, %1, %8\n\t"
+        "v_bcnt_u32_b32 %1, %1, %8\n\t"
         "v_and_b32 %2, %2, %8\n\t"
         "v_sub_u32_e64 %3, %3, %8 clamp\n\t"
-        "v_cndmask_b32_e64 %4, %4, %8, %9\n\t"
-        "v_and_or_b32 %5, %5, %8, %8\n\t"
-        "v_add_u32 %6, %6, %8\n\t"
+        "v_pk_sub_u16 %4, %4, %8 clamp\n\t"
+        "v_dot2_u32_u16 %5, %5, %8, %5\n\t"
+        "v_and_or_b32 %6, %6, %8, %8\n\t"
         "v_mad_u32_u24 %7, %7, 3, %8\n\t"
         : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3), "+v"(a4), "+v"(a5), "+v"(a6), "+v"(a7)
         : "v"(k), "s"(m));

@@ -405,7 +405,7 @@ __device__ __forceinline__ int64_t group_row(
     GroupTable<kSlots>& T, int64_t i, const int64_t* __restrict__ lg_ptr,
     const int32_t* __restrict__ up_first, const uint4* __restrict__ rec, int64_t* gcount,
     const int64_t* __restrict__ obase_of, int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna,
-    int32_t* flags) {
+    int32_t* flags, bool pack16) {
   constexpr int64_t kPartRecords = 2 * kSlots;
   constexpr uint32_t kPartGroups = kSlots * 3 / 4;
   const int tid = threadIdx.x;
@@ -534,7 +534,10 @@ __device__ __forceinline__ int64_t group_row(
         // (16-22), which the pair kernel then reads instead of recomputing
         // them per pair with scalar instructions
         grec[o] = make_uint4(f.x, oc | (uint32_t(__popc(f.x)) << 8) | (open_class(f.x, oc) << 16), f.z, f.w);
-        gcnt[o] = make_uint2(T.nall[t], T.nabove[t]);
+        // pack16 (every row shorter than 2^16 neighbours): the second word
+        // holds nabove and nall as 16-bit halves, for the pair kernel's
+        // two-term dot product of the weight
+        gcnt[o] = make_uint2(T.nall[t], pack16 ? T.nabove[t] | (T.nall[t] << 16) : T.nabove[t]);
       }
       __syncthreads();
       if (tid == 0) {  // both kinds' ends: the last class's next slot
@@ -559,12 +562,13 @@ template <bool kWrite>
 __global__ __launch_bounds__(kShortThreads) void k_group_short(
     int64_t c0, const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
     const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
-    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats) {
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats,
+    bool pack16) {
   __shared__ GroupTable<kShortSlots> T;
   const int64_t i = c0 + blockIdx.x;
   if (lg_ptr[i + 1] - lg_ptr[i] > kShortRow) return;  // uniform
   const int64_t p = group_row<kWrite, kShortThreads, kShortSlots>(T, i, lg_ptr, up_first, rec, gcount, obase_of,
-                                                                  cap0, grec, gcnt, gna, flags);
+                                                                  cap0, grec, gcnt, gna, flags, pack16);
   // one pass of the grouping reports the parts; a row of one part is the
   // common case and needs no report (the host's maximum starts at 1)
   if (stats && threadIdx.x == 0 && (p < 0 || p > 1)) {
@@ -580,7 +584,8 @@ __global__ __launch_bounds__(kLongThreads) void k_group_long(
     unsigned long long* queue,
     const int64_t* __restrict__ lg_ptr, const int32_t* __restrict__ up_first,
     const uint4* __restrict__ rec, int64_t* gcount, const int64_t* __restrict__ obase_of,
-    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats) {
+    int64_t cap0, uint4* grec, uint2* gcnt, int32_t* gna, int32_t* flags, unsigned long long* stats,
+    bool pack16) {
   __shared__ GroupTable<kLongSlots> T;
   __shared__ int64_t s_q;
   const int64_t n = int64_t(*nrows);
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(kLongThreads) void k_group_long(
     __syncthreads();
     if (q >= n) break;
     const int64_t p = group_row<kWrite, kLongThreads, kLongSlots>(T, rows[q], lg_ptr, up_first, rec, gcount,
-                                                                  obase_of, cap0, grec, gcnt, gna, flags);
+                                                                  obase_of, cap0, grec, gcnt, gna, flags, pack16);
     regrouped += p < 0 ? 1ull : 0ull;
     most = max(most, (unsigned long long)(p < 0 ? -p : p));
   }
@@ -670,6 +675,13 @@ __device__ __forceinline__ uint32_t dot2(uint32_t d, uint32_t w, uint32_t c) {
   return r;
 }
 
+// lo(a) * lo(b) + hi(a) * hi(b), 16-bit halves, both per lane.
+__device__ __forceinline__ uint32_t dot2_vv(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_dot2_u32_u16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Twice the reversed ternary code 2186 - code of a pair (code as
 // pair_code gives it, same digit order): the byte offset of its entry in
 // the pair kernel's class table (stored reversed, 2-byte entries).  Digit r
@@ -726,9 +738,10 @@ __device__ __forceinline__ uint32_t lut_at(const uint16_t* __restrict__ lut, uin
 // kAllA: every lane's group and j have members above the centre, so every
 // pair weighs at least 1 (N_j N_k or A_j A_k): no test and no branch (a lane
 // past the row's end has N = A = 0 and adds 0 at a valid class).
-// kNarrow: every row is shorter than 2^17 neighbours, so the weight of a
-// pair of distinct groups, at most (row length / 2)^2, fits 32 bits and is
-// one 24-bit multiply (its high half is zero).
+// kNarrow: every row is shorter than 2^16 neighbours, so the group counts
+// fit 16 bits and the weight of a pair of distinct groups, at most (row
+// length / 2)^2, fits 32 bits: one 24-bit multiply (its high half is zero),
+// or, in the full-class loop, a two-term dot product of the packed counts.
 template <bool kNarrow>
 __device__ __forceinline__ uint64_t pair_weight(uint32_t x, uint32_t y) {
   return kNarrow ? uint64_t(x * y) : uint64_t(x) * y;
@@ -747,8 +760,9 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   // j's counts arrive in vector registers (gwalk loads them per lane), so
   // the selects below need no copies of scalar values
   const uint32_t y = disjoint ? kn : ka;
+  const uint32_t nab = kNarrow ? (cj.y & 0xffffu) : cj.y;  // nabove_j
   if (kAllA && !kDiag) {
-    const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
+    const uint32_t x = (disjoint ? cj.x : nab) & 0xffffffu;
     const uint32_t rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
     atomicAdd(hist_at(hist, lut_at(lut, rc2)), pair_weight<kNarrow>(x, y));
     return;
@@ -756,7 +770,7 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
   bool act = y != 0u;
   if (kDiag) act = act && (j < kp);
   if (act) {
-    const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
+    const uint32_t x = (disjoint ? cj.x : nab) & 0xffffffu;
     const uint64_t w = pair_weight<kNarrow>(x, y);
     const uint32_t rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
     atomicAdd(hist_at(hist, lut_at(lut, rc2)), w);
@@ -765,18 +779,24 @@ __device__ __forceinline__ void gpair_step(const uint4& rj, const uint2& cj, int
 
 // A full-class pair's class table offset and weight (every lane's group and
 // j with members above the centre).
+// kNarrow: j's second count word holds (nabove_j, nall_j) as 16-bit halves,
+// so the weight is one dot product with the lane's (0, N_k) or (A_k, 0).
 template <bool kNarrow>
 __device__ __forceinline__ void pair_full(const uint4& rj, const uint2& cj, uint32_t aks2, const Side& k,
                                           uint32_t khl, uint32_t khh, uint32_t kso, uint32_t kn,
-                                          uint32_t ka, uint32_t& rc2, uint64_t& w) {
+                                          uint32_t ka, uint32_t kn16, uint32_t& rc2, uint64_t& w) {
   const uint32_t xm = rj.x & k.m, xl = rj.z & khl, xh = rj.w & khh;
   uint32_t t2, tr;
   pair_counts(xm, xl, xh, t2, tr);
   const bool disjoint = tr == 0x00020002u;  // t = r5 = 0
-  const uint32_t y = disjoint ? kn : ka;
-  const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
   rc2 = pair_rcode2(t2, tr, aks2, rj.y, kso);
-  w = pair_weight<kNarrow>(x, y);
+  if (kNarrow) {
+    w = dot2_vv(cj.y, disjoint ? kn16 : ka);
+  } else {
+    const uint32_t y = disjoint ? kn : ka;
+    const uint32_t x = (disjoint ? cj.x : cj.y) & 0xffffffu;
+    w = pair_weight<kNarrow>(x, y);
+  }
 }
 
 template <bool kDiag, bool kAllA, bool kNarrow>
@@ -792,6 +812,7 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
   const uint2* gc = gc0 + z;
   const uint32_t aks2 = 2u * aks - 4u;
   const uint32_t kso = k.s | (k.o << 16);
+  const uint32_t kn16 = kn << 16;
   int j = j0;
   if (kAllA && !kDiag) {
     // four pairs at a time: the four class table reads are issued together
@@ -801,10 +822,10 @@ __device__ __forceinline__ void gwalk(const uint4* __restrict__ grow, const uint
       const uint2 c0 = gc[j], c1 = gc[j + 1], c2 = gc[j + 2], c3 = gc[j + 3];
       uint32_t o0, o1, o2, o3;
       uint64_t w0, w1, w2, w3;
-      pair_full<kNarrow>(r0, c0, aks2, k, khl, khh, kso, kn, ka, o0, w0);
-      pair_full<kNarrow>(r1, c1, aks2, k, khl, khh, kso, kn, ka, o1, w1);
-      pair_full<kNarrow>(r2, c2, aks2, k, khl, khh, kso, kn, ka, o2, w2);
-      pair_full<kNarrow>(r3, c3, aks2, k, khl, khh, kso, kn, ka, o3, w3);
+      pair_full<kNarrow>(r0, c0, aks2, k, khl, khh, kso, kn, ka, kn16, o0, w0);
+      pair_full<kNarrow>(r1, c1, aks2, k, khl, khh, kso, kn, ka, kn16, o1, w1);
+      pair_full<kNarrow>(r2, c2, aks2, k, khl, khh, kso, kn, ka, kn16, o2, w2);
+      pair_full<kNarrow>(r3, c3, aks2, k, khl, khh, kso, kn, ka, kn16, o3, w3);
       o0 = lut_at(lut, o0);
       o1 = lut_at(lut, o1);
       o2 = lut_at(lut, o2);
@@ -1012,7 +1033,7 @@ __attribute__((amdgpu_waves_per_eu(kShared ? 8 : 5, 8))) void k_exact_grouped(
       ka = ck.y;
     }
     kn &= 0xffffffu;
-    ka &= 0xffffffu;
+    ka &= kNarrow ? 0xffffu : 0xffffffu;  // packed: (nabove, nall) halves
     const int blo = b * kWave;
     const int kmax = min(blo + kWave, ng);
     const uint32_t aks = a - k.s;
@@ -1117,7 +1138,7 @@ mochy_status build_schedule(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
 // pairs every record.
 mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int64_t c1,
                           int64_t** goff, uint4** grec, uint2** gcnt, int32_t** gna,
-                          const int64_t** gbase, int64_t* cap0, unsigned long long* stats) {
+                          const int64_t** gbase, int64_t* cap0, unsigned long long* stats, bool pack16) {
   hipStream_t st = ctx->stream;
   const int64_t E = g->E;
   int64_t* cntarr = nullptr;
@@ -1180,10 +1201,11 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     *cap0 = row0;
     if (c1 > c0) {
       k_group_short<true><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
-          c0, g->lg_ptr, g->up_first, g->rec, cntarr, g->lg_ptr, row0, *grec, *gcnt, *gna, ctx->d_flags + 3, stats);
+          c0, g->lg_ptr, g->up_first, g->rec, cntarr, g->lg_ptr, row0, *grec, *gcnt, *gna, ctx->d_flags + 3, stats,
+          pack16);
       k_group_long<true><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue, g->lg_ptr, g->up_first, g->rec,
                                                          cntarr, g->lg_ptr, row0, *grec, *gcnt, *gna,
-                                                         ctx->d_flags + 3, stats);
+                                                         ctx->d_flags + 3, stats, pack16);
     }
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
   } else {
@@ -1192,10 +1214,10 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     if (c1 > c0) {
       k_group_short<false><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
           c0, g->lg_ptr, g->up_first, g->rec, cntarr, nullptr, 0, nullptr, nullptr, nullptr, ctx->d_flags + 3,
-          stats);
+          stats, pack16);
       k_group_long<false><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue, g->lg_ptr, g->up_first,
                                                           g->rec, cntarr, nullptr, 0, nullptr, nullptr, nullptr,
-                                                          ctx->d_flags + 3, stats);
+                                                          ctx->d_flags + 3, stats, pack16);
     }
     launch_exclusive_scan_i64(cntarr, *goff, E + 1, tmp, st);
     MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small, *goff + E, 8, hipMemcpyDeviceToHost, st), fail);
@@ -1209,10 +1231,11 @@ mochy_status build_groups(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     // the same grouping again, written this time (its parts were reported above)
     if (c1 > c0) {
       k_group_short<true><<<unsigned(c1 - c0), kShortThreads, 0, st>>>(
-          c0, g->lg_ptr, g->up_first, g->rec, nullptr, *goff, 0, *grec, *gcnt, *gna, ctx->d_flags + 3, nullptr);
+          c0, g->lg_ptr, g->up_first, g->rec, nullptr, *goff, 0, *grec, *gcnt, *gna, ctx->d_flags + 3, nullptr,
+          pack16);
       k_group_long<true><<<lgrid, kLongThreads, 0, st>>>(longrows, nlong, lqueue + 1, g->lg_ptr, g->up_first,
                                                          g->rec, nullptr, *goff, 0, *grec, *gcnt, *gna,
-                                                         ctx->d_flags + 3, nullptr);
+                                                         ctx->d_flags + 3, nullptr, pack16);
     }
   }
   if (c1 > c0)
@@ -1258,11 +1281,15 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
   unsigned long long* gqueue = nullptr;
   mochy_status rc;
   phase_begin(ctx, kPhSched);
+  // rows shorter than 2^16 neighbours: the group counts fit 16 bits and a
+  // pair's weight (below 2^32) is a two-term dot product of packed counts
+  // (test bit 4 takes the 48-bit form regardless)
+  const bool narrow = g->max_deg < (1 << 16) && !(ctx->test_faults & 16);
   bool grouped = ctx->group_neighbours;
   if (grouped) {
     rc = (ctx->test_faults & 4) && ng > 2
              ? MOCHY_ENOMEM  // forced for tests of the batch split
-             : build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0, stats);
+             : build_groups(ctx, g, c0, c1, &goff, &grec, &gcnt, &gna, &gbase, &cap0, stats, narrow);
     if (rc == MOCHY_ENOMEM && ng > 1) {
       return rc;  // a batch: the caller splits it and counts the parts with groups
     } else if (rc == MOCHY_ENOMEM) {  // not enough memory for one graph's groups: pair every record
@@ -1305,9 +1332,6 @@ mochy_status exact_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, int6
     MOCHY_HIP_OR(hipStreamSynchronize(st), release);
     if (ctx->batch_launch == 0 && hgq[ng] < int64_t(ng) * grid * kWavesPerGroup) hgq.clear();
   }
-  // rows shorter than 2^17 neighbours: 32-bit pair weights (test bit 4
-  // takes the 64-bit form regardless)
-  const bool narrow = g->max_deg < (1 << 17) && !(ctx->test_faults & 16);
   const auto kshared = narrow ? k_exact_grouped<true, true> : k_exact_grouped<true, false>;
   if (!hgq.empty()) {
     if ((rc = device_alloc(ctx, (void**)&gqueue, size_t(ng) * 8)) != MOCHY_OK) return release(rc);

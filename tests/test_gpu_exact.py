@@ -363,8 +363,9 @@ def test_row_capacity_fallback(ctx):
 
 
 def test_wide_pair_weights(ctx):
-    # the pair kernel's 64-bit weights (taken when a row reaches 2^17
-    # neighbours) forced on graphs whose weights fit 32 bits: same counts
+    # the pair kernel's 48-bit weights from unpacked group counts (taken
+    # when a row reaches 2^16 neighbours) forced on graphs whose counts fit
+    # 16 bits: same counts
     import paper_2310_15668_amd as M
     for h in (make_config("medium", scale=0.03), powerlaw_hypergraph(300, 2000, 2, 20, 2.5, 0.9, seed=23)):
         print(f"[gpu] 64-bit pair weights |E|={h.num_edges}", flush=True)
