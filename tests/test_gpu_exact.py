@@ -427,3 +427,19 @@ def test_exact_stats(ctx):
     assert st0["groups"] == 0 and st0["group_pairs_full"] == 0
     for k in ("light_pairs", "fix_scanned", "fix_centres", "fix_changed"):
         assert st0[k] == st[k], k
+
+
+def test_valu_calibration(ctx):
+    # the integer VALU calibration launch: its instruction count is the
+    # written-out one and its rate a plausible one; bad arguments are refused
+    import torch
+    import paper_2310_15668_amd as M
+    print("[gpu] VALU calibration, 256 rounds", flush=True)
+    ms, ops = M.mochy_calibrate_valu(ctx, 256)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert ops == cus * 8 * 256 * 256 * 32  # 8 blocks of 256 threads per CU, 32 per round
+    assert ms > 0.0
+    assert ops / (ms * 1e-3) < 2.0 * cus * 64 * 2.4e9  # below twice the one-per-cycle rate
+    for bad in (0, -1, (1 << 32) + 1):
+        with pytest.raises(M.MochyError):
+            M.mochy_calibrate_valu(ctx, bad)
