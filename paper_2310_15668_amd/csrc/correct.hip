@@ -59,19 +59,15 @@ __device__ __forceinline__ bool smallest_shared_light(int32_t x, int32_t y, int3
 
 // One wave per light node w: every pair of E_w whose smallest shared light
 // node is w.  kCount counts pairs per owner; kFill also writes the partners
-// (a second pass, after the owners' offsets are known); kFlat counts and
-// writes every candidate pair of E_w at its slot of a flat list (slot =
-// noff[w] + b (b - 1) / 2 + a for members a < b of E_w), (owner, partner)
-// or (-1, -1) where w is not the pair's smallest shared light node, so the
-// merges run once and a scatter pass replaces the second.
-enum LightMode { kCount = 0, kFill = 1, kFlat = 2 };
+// (a second pass, after the owners' offsets are known).  Where the flat list
+// of candidate slots fits, k_light_slots runs the merges once instead.
+enum LightMode { kCount = 0, kFill = 1 };
 template <int kMode>
 __global__ __launch_bounds__(256) void k_light_pairs(
     int64_t V, const int64_t* __restrict__ node_ptr, const int32_t* __restrict__ node_edges,
     const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ edge_ptr,
     const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ lg_ptr,
-    unsigned long long* pcount, const int64_t* __restrict__ poff, int32_t* partners,
-    const int64_t* __restrict__ noff, int2* flat) {
+    unsigned long long* pcount, const int64_t* __restrict__ poff, int32_t* partners) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   if (w >= V || heavy_bit[w] >= 0) return;  // uniform per wave
@@ -85,21 +81,55 @@ __global__ __launch_bounds__(256) void k_light_pairs(
     for (int a = 0; a < aend; ++a) {
       const int32_t ya = node_edges[lo + a];
       if (!(b < D && a < b)) continue;
-      const bool first = smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit);
-      int2* slotp = nullptr;
-      if (kMode == kFlat) slotp = flat + noff[w] + int64_t(b) * (b - 1) / 2 + a;
-      if (!first) {
-        if (kMode == kFlat) *slotp = make_int2(-1, -1);
-        continue;
-      }
+      if (!smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit)) continue;
       const int64_t da = lg_ptr[ya + 1] - lg_ptr[ya];
       const bool a_owns = da > db || (da == db && ya < yb);
       const int32_t owner = a_owns ? ya : yb, partner = a_owns ? yb : ya;
       const unsigned long long slot = atomicAdd(&pcount[owner], 1ull);
       if (kMode == kFill) partners[poff[owner] + int64_t(slot)] = partner;
-      if (kMode == kFlat) *slotp = make_int2(owner, partner);
     }
   }
+}
+
+// The flat list of candidate slots (slot noff[w] + b (b - 1) / 2 + a for
+// members a < b of E_w): (owner, partner), or (-1, -1) where w is not the
+// pair's smallest shared light node, so that the merges run once and a
+// scatter pass replaces the filling pass.  One thread per slot t: the light node w with
+// noff[w] <= t < noff[w + 1] (a binary search), then the members a < b of
+// E_w with t - noff[w] = b (b - 1) / 2 + a, merged as in k_light_pairs.  A
+// node's C(|E_w|, 2) merges are spread over as many threads, where the
+// one-wave-per-node kernel leaves the largest light node's wave running
+// long after the others.
+__global__ __launch_bounds__(256) void k_light_slots(
+    int64_t V, int64_t ncand, const int64_t* __restrict__ node_ptr, const int32_t* __restrict__ node_edges,
+    const int8_t* __restrict__ heavy_bit, const int64_t* __restrict__ edge_ptr,
+    const int32_t* __restrict__ edge_nodes, const int64_t* __restrict__ lg_ptr,
+    unsigned long long* pcount, const int64_t* __restrict__ noff, int2* flat) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ncand) return;
+  int64_t lo = 0, hi = V;  // largest w with noff[w] <= t (noff is nondecreasing, noff[V] = ncand > t)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (noff[mid] <= t) lo = mid; else hi = mid;
+  }
+  const int64_t w = lo;
+  const int64_t r = t - noff[w];
+  // b (b - 1) / 2 <= r < b (b + 1) / 2
+  int64_t b = int64_t((1.0 + sqrt(1.0 + 8.0 * double(r))) * 0.5);
+  while (b * (b - 1) / 2 > r) --b;
+  while ((b + 1) * b / 2 <= r) ++b;
+  const int64_t a = r - b * (b - 1) / 2;
+  const int64_t base = node_ptr[w];
+  const int32_t ya = node_edges[base + a], yb = node_edges[base + b];
+  if (!smallest_shared_light(ya, yb, int32_t(w), edge_ptr, edge_nodes, heavy_bit)) {
+    flat[t] = make_int2(-1, -1);
+    return;
+  }
+  const int64_t da = lg_ptr[ya + 1] - lg_ptr[ya], db = lg_ptr[yb + 1] - lg_ptr[yb];
+  const bool a_owns = da > db || (da == db && ya < yb);
+  const int32_t owner = a_owns ? ya : yb, partner = a_owns ? yb : ya;
+  atomicAdd(&pcount[owner], 1ull);
+  flat[t] = make_int2(owner, partner);
 }
 
 // Candidate pairs C(|E_w|, 2) of every light node (0 for heavy ones), the
@@ -429,13 +459,13 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
     }
   }
   if (flat)
-    k_light_pairs<kFlat><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
-                                                  g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
-                                                  nullptr, nullptr, noff, flat);
+    k_light_slots<<<unsigned(blocks(ncand, 256)), 256, 0, st>>>(V, ncand, g->node_ptr, g->node_edges,
+                                                              g->heavy_bit, g->edge_ptr, g->edge_nodes,
+                                                              g->lg_ptr, pcount, noff, flat);
   else
     k_light_pairs<kCount><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                    g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount,
-                                                   nullptr, nullptr, nullptr, nullptr);
+                                                   nullptr, nullptr);
   k_owner_list<<<blocks(E, 256), 256, 0, st>>>(E, pcount, nown, owners, ocount);
   MOCHY_HIP_OR(hipMemcpyAsync(ctx->h_small + 504, nown, 8, hipMemcpyDeviceToHost, st), done);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
@@ -462,7 +492,7 @@ mochy_status correct_device(mochy_ctx* ctx, const mochy_graph* g, int64_t c0, in
   else
     k_light_pairs<kFill><<<wblocks, 256, 0, st>>>(V, g->node_ptr, g->node_edges, g->heavy_bit,
                                                   g->edge_ptr, g->edge_nodes, g->lg_ptr, pcount, eoff,
-                                                  partners, nullptr, nullptr);
+                                                  partners);
   MOCHY_HIP_OR(hipStreamSynchronize(st), done);
   const int64_t nitems = ctx->h_small[506];
   if ((rc = device_alloc(ctx, (void**)&item_owner, size_t(nitems) * 4)) != MOCHY_OK ||
