@@ -192,9 +192,25 @@ __global__ __launch_bounds__(256) void k_proj_fill(int64_t E, const int64_t* __r
   }
 }
 
+// Each hyperedge's heavy nodes as a 64-bit mask (bit heavy_bit[v]).
+__global__ void k_edge_heavy(int64_t E, const int64_t* __restrict__ ptr, const int32_t* __restrict__ nodes,
+                             const int8_t* __restrict__ heavy_bit, unsigned long long* hmask) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x >= E) return;
+  unsigned long long h = 0;
+  for (int64_t q = ptr[x]; q < ptr[x + 1]; ++q) {
+    const int b = heavy_bit[nodes[q]];
+    if (b >= 0) h |= 1ull << b;
+  }
+  hmask[x] = h;
+}
+
+// Row i's records: for each neighbour e_x, the mask of e_i's nodes it holds
+// (found by scanning e_x's nodes against e_i), its outside count, and its
+// heavy outside nodes, hmask[x] less e_i's own heavy nodes.
 __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __restrict__ ptr,
                                                  const int32_t* __restrict__ nodes,
-                                                 const int8_t* __restrict__ heavy_bit,
+                                                 const unsigned long long* __restrict__ hmask,
                                                  const int64_t* __restrict__ lg_ptr,
                                                  const int32_t* __restrict__ lg_col, uint4* rec,
                                                  uint32_t* recm, uint16_t* rsz, int32_t* flags) {
@@ -215,41 +231,31 @@ __global__ __launch_bounds__(256) void k_records(int64_t E, const int64_t* __res
   __syncthreads();
   const int64_t base = lg_ptr[i];
   const int64_t d = lg_ptr[i + 1] - base;
+  const unsigned long long hi = hmask[i];
   for (int64_t p = threadIdx.x; p < d; p += blockDim.x) {
     const int32_t x = lg_col[base + p];
-    uint32_t m = 0, o = 0, light = 0;
-    unsigned long long hv = 0;
-    const int64_t q1 = ptr[x + 1];
-    // four of e_x's nodes at a time, their loads (nodes, then heavy bits)
-    // issued together before any is used; -1 pads past the list's end
-    for (int64_t q = ptr[x]; q < q1; q += 4) {
+    uint32_t m = 0;
+    const int64_t q0 = ptr[x], q1 = ptr[x + 1];
+    const unsigned long long hv = hmask[x] & ~hi;  // heavy nodes of e_x outside e_i
+    // four of e_x's nodes at a time, their loads issued together before any
+    // is used; -1 pads past the list's end
+    for (int64_t q = q0; q < q1; q += 4) {
       int32_t v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[u] = q + u < q1 ? nodes[q + u] : -1;
-      int at[4];
-      int hb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        int lo = 0, hi = a;  // binary search of v in e_i, past the filter
-        if (v[u] < 0 || !((filt[(v[u] >> 5) & 31] >> (v[u] & 31)) & 1u)) hi = 0;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (ei[mid] < v[u]) lo = mid + 1; else hi = mid;
+        int lo = 0, hb = a;  // binary search of v in e_i, past the filter
+        if (v[u] < 0 || !((filt[(v[u] >> 5) & 31] >> (v[u] & 31)) & 1u)) hb = 0;
+        while (lo < hb) {
+          const int mid = (lo + hb) >> 1;
+          if (ei[mid] < v[u]) lo = mid + 1; else hb = mid;
         }
-        at[u] = lo < a && ei[lo] == v[u] ? lo : -1;
-        hb[u] = v[u] >= 0 && at[u] < 0 ? int(heavy_bit[v[u]]) : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (v[u] < 0) continue;
-        if (at[u] >= 0) {
-          m |= 1u << at[u];
-        } else {
-          ++o;
-          if (hb[u] >= 0) hv |= 1ull << hb[u]; else light = 1;
-        }
+        if (lo < a && ei[lo] == v[u]) m |= 1u << lo;
       }
     }
+    const uint32_t o = uint32_t(q1 - q0) - uint32_t(__popc(m));
+    const uint32_t light = o > uint32_t(__popcll(hv)) ? 1u : 0u;  // an outside node that is not heavy
     if (o == 0 && __popc(m) == a) atomicOr(flags, kFlagDup);
     rec[base + p] = make_uint4(m, o | (light ? kRecLight : 0u), uint32_t(hv), uint32_t(hv >> 32));
     recm[base + p] = m;
@@ -387,11 +393,14 @@ mochy_status project_device(mochy_ctx* ctx, mochy_graph* g) {
                                                     g->node_edges, g->row_graph, g->geoff, g->lg_ptr,
                                                     g->lg_col, g->up_first);
   phase_end(ctx, kPhRows);
-  // 7. records
+  // 7. records (cnt, free until the upper-row prefix, holds the heavy masks)
   phase_begin(ctx, kPhRecords);
-  if (E > 0)
-    k_records<<<unsigned(E), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, g->lg_ptr,
-                                           g->lg_col, g->rec, g->recm, g->rsz, ctx->d_flags);
+  if (E > 0) {
+    unsigned long long* hmask = reinterpret_cast<unsigned long long*>(cnt);
+    k_edge_heavy<<<blocks(E, 256), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, g->heavy_bit, hmask);
+    k_records<<<unsigned(E), 256, 0, st>>>(E, g->edge_ptr, g->edge_nodes, hmask, g->lg_ptr, g->lg_col,
+                                           g->rec, g->recm, g->rsz, ctx->d_flags);
+  }
   // upper-row prefix (hyperwedge order for sampling)
   k_upper_len<<<blocks(E + 1, 256), 256, 0, st>>>(E, g->lg_ptr, g->up_first, cnt);
   launch_exclusive_scan_i64(cnt, g->up_ptr, E + 1, tmp, st);
