@@ -685,14 +685,14 @@ __device__ __forceinline__ uint32_t dot2_vv(uint32_t a, uint32_t b) {
 // Twice the reversed ternary code 2186 - code of a pair (code as
 // pair_code gives it, same digit order): the byte offset of its entry in
 // the pair kernel's class table (stored reversed, 2-byte entries).  Digit r
-// enters as 2 - min(R_r, 2) = max(2 - R_r, 0), a saturating subtract from
-// t + 2 = |e_i ∩ e_j ∩ e_k| + 2 and r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy
-// part), held as the two halves of tr: R7 and R5 against 2, R6 and R3
-// against k's (|e_i ∩ e_k|, outside count), R4 and R2 against j's, each
-// pair of digits one packed subtract; the weighted sum 2 (3^6 R7 + ... + R1)
-// is three two-term dot products over those pairs.  R1 = aks - pj + t (aks =
-// |e_i| - |e_i ∩ e_k|) enters doubled, from 2 (t + 2) + aks2 with aks2 =
-// 2 aks - 4.
+// enters as 2 - min(R_r, 2) = max(2 - R_r, 0).  With tr holding t + 2 =
+// |e_i ∩ e_j ∩ e_k| + 2 and r5 + 2 = |e_j ∩ e_k - e_i| + 2 (its heavy part)
+// as 16-bit halves, three packed saturating subtracts give two digits each:
+// (4, 4) - tr is (R7, R5), tr - (|e_i ∩ e_k|, k's outside count) is
+// (R6, R3), tr - (pj, oj) is (R4, R2).  R1 = aks - pj + t (aks = |e_i| -
+// |e_i ∩ e_k|) enters doubled, from 2 (t + 2) + aks2 with aks2 = 2 aks - 4,
+// as the start of three two-term dot products that add 2 (3^6 R7 + ...)
+// pair by pair.
 // jy is j's record word: oj in bits 0-7, pj in bits 8-15; kso = k.s | k.o << 16.
 __device__ __forceinline__ uint32_t pair_rcode2(uint32_t t2, uint32_t tr, uint32_t aks2, uint32_t jy,
                                                 uint32_t kso) {
