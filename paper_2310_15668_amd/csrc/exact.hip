@@ -530,10 +530,12 @@ __device__ __forceinline__ int64_t group_row(
         const uint32_t oc = clamp_outside(f);
         const uint32_t pos = atomicAdd(&T.cfill[(above ? 0 : kOpenClasses) + open_class(f.x, oc)], 1u);
         const int64_t o = above ? obase + pos : oend - 1 - pos;
-        // y: clamped outside count (bits 0-7), |m| (8-15) and the open class
-        // (16-22), which the pair kernel then reads instead of recomputing
-        // them per pair with scalar instructions
-        grec[o] = make_uint4(f.x, oc | (uint32_t(__popc(f.x)) << 8) | (open_class(f.x, oc) << 16), f.z, f.w);
+        // y: |m| (bits 0-7), 2 |m| + 4 (8-15), the clamped outside count
+        // (16-23) and the open class (24-30), which the pair kernel then
+        // reads instead of recomputing them per pair: (|m|, outside) is y
+        // with bits 8-15 and 24-31 cleared, one scalar AND
+        const uint32_t pm = uint32_t(__popc(f.x));
+        grec[o] = make_uint4(f.x, pm | ((2u * pm + 4u) << 8) | (oc << 16) | (open_class(f.x, oc) << 24), f.z, f.w);
         // pack16 (every row shorter than 2^16 neighbours): the second word
         // holds nabove and nall as 16-bit halves, for the pair kernel's
         // two-term dot product of the weight
@@ -693,16 +695,17 @@ __device__ __forceinline__ uint32_t dot2_vv(uint32_t a, uint32_t b) {
 // |e_i ∩ e_k|) enters doubled, from 2 (t + 2) + aks2 with aks2 = 2 aks - 4,
 // as the start of three two-term dot products that add 2 (3^6 R7 + ...)
 // pair by pair.
-// jy is j's record word: oj in bits 0-7, pj in bits 8-15; kso = k.s | k.o << 16.
+// jy is j's record word: pj in bits 0-7, 2 pj + 4 in bits 8-15, oj in bits
+// 16-23; kso = k.s | k.o << 16.
 __device__ __forceinline__ uint32_t pair_rcode2(uint32_t t2, uint32_t tr, uint32_t aks2, uint32_t jy,
                                                 uint32_t kso) {
-  const uint32_t pj = (jy >> 8) & 0xffu, oj = jy & 0xffu;
+  const uint32_t pjo = jy & 0x00ff00ffu, pj24 = (jy >> 8) & 0xffu;
   uint32_t v2;  // 2 (aks + t) = 2 t2 + aks2, one shift-add
   asm("v_lshl_add_u32 %0, %1, 1, %2" : "=v"(v2) : "v"(t2), "v"(aks2));
   const uint32_t d75 = pk_usat_sv(0x00040004u, tr);     // (R7, R5)
   const uint32_t d63 = pk_usat_vv(tr, kso);             // (R6, R3)
-  const uint32_t d42 = pk_usat_vs(tr, pj | (oj << 16));  // (R4, R2)
-  uint32_t c = usat(2u * pj + 4u, v2);                  // 2 R1
+  const uint32_t d42 = pk_usat_vs(tr, pjo);             // (R4, R2)
+  uint32_t c = usat(pj24, v2);                          // 2 R1
   c = dot2(d42, 54u | (6u << 16), c);
   c = dot2(d63, 486u | (18u << 16), c);
   return dot2(d75, 1458u | (162u << 16), c);
@@ -892,7 +895,7 @@ __device__ __forceinline__ void open_step(const uint4& rj, const uint2& cj, int 
                                           uint32_t aks, uint32_t k0, uint32_t& cur, uint32_t& acc,
                                           const uint16_t* __restrict__ lut,
                                           unsigned long long* hist) {
-  const uint32_t cls = rj.y >> 16;  // uniform: the open class the grouping stored
+  const uint32_t cls = rj.y >> 24;  // uniform: the open class the grouping stored
   if (cls != cur) {
     open_flush(cur, acc, aks, k0, kn, lut, hist);
     cur = cls;
@@ -1026,7 +1029,7 @@ __attribute__((amdgpu_waves_per_eu(kShared ? 8 : 5, 8))) void k_exact_grouped(
       const uint4 rk = valid ? grow[kpos] : make_uint4(0, 0, 0, 0);
       const uint2 ck = valid ? gc[kpos] : make_uint2(0, 0);
       k.m = rk.x;
-      k.o = rk.y & 0xffu;
+      k.o = (rk.y >> 16) & 0xffu;
       k.s = __popc(rk.x);
       k.h = (unsigned long long)rk.z | ((unsigned long long)rk.w << 32);
       kn = ck.x;
