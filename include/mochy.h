@@ -334,11 +334,13 @@ mochy_status mochy_exact_stats(const mochy_ctx* ctx, int64_t* out);
 
 /* Measurement helper (not part of the method): the integer vector-ALU rate
  * the device sustains.  One timed launch of 32 waves per compute unit, every
- * lane running `iters` rounds of 32 32-bit integer vector instructions of
- * the exact pair kernel's mix (and, or, xor, population count, add, subtract,
- * min, 24-bit multiply-add) over independent chains.  *ms (host) receives
- * the launch's duration from HIP events on the context stream, *lane_ops
- * (host) the lane-operations it executed (threads x iters x 32).
+ * lane running `iters` rounds of 32 integer vector instructions in the
+ * proportions the exact pair kernel issues them (AND, add, saturating and
+ * packed 16-bit saturating subtract, population count, two-term 16-bit dot
+ * product, select, AND-OR, shift-or, shift-add, 24-bit multiply-add) over
+ * independent chains.  *ms (host) receives the launch's duration from HIP
+ * events on the context stream, *lane_ops (host) the lane instructions it
+ * executed (threads x iters x 32).
  * iters in [1, 2^32], else MOCHY_EINVAL. */
 mochy_status mochy_calibrate_valu(mochy_ctx* ctx, int64_t iters, double* ms, int64_t* lane_ops);
 
